@@ -1,0 +1,177 @@
+/*
+ * exprb -- exponential Rosenbrock integration of the rotating shallow-water
+ * equations on icosahedral geodesic grids, native to AMD MI355X (gfx950).
+ *
+ * C ABI of libexprb.so.  Plain pointers and sizes only.
+ *
+ * Conventions
+ *  - A state or direction vector is FP64, length 4N, laid out as
+ *    [u_x | u_y | u_z | h] with each block N cells long, in the cell order of
+ *    the mesh passed to xrb_create (the state layout of Sec. 2, eq. dynu:
+ *    Cartesian velocity components and fluid depth).
+ *  - Vector arguments of the compute calls are DEVICE pointers owned by the
+ *    caller; they must stay valid until the enqueued work has finished.
+ *    Scalars, rho arrays and pointer arrays are HOST memory.
+ *  - Work is enqueued on the context's HIP stream.  Calls return XRB_OK once
+ *    the launches were accepted.  xrb_phi_combo and xrb_step synchronise the
+ *    stream internally once per substep attempt (the host decides how many
+ *    Krylov iterations to launch), so they return after their work is done.
+ *  - A context is not thread-safe; use one context per stream.
+ *  - On error the call returns a negative xrb_status and xrb_last_error()
+ *    describes it; device-side failures (NaN, non-convergence) are reported
+ *    by the call that detects them.
+ */
+#ifndef EXPRB_H
+#define EXPRB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xrb_ctx xrb_ctx;
+
+typedef enum {
+    XRB_OK = 0,
+    XRB_EINVAL = -1,   /* bad argument (size, pointer, rho order, p, mode) */
+    XRB_ENOMEM = -2,   /* device or host allocation failed */
+    XRB_EDEVICE = -3,  /* a HIP runtime call failed */
+    XRB_ENOTCONV = -4, /* substep loop exceeded max_attempts or tau underflowed */
+    XRB_ENAN = -5,     /* NaN/Inf met in a norm or in the error estimate */
+    XRB_ESTATE = -6,   /* context state does not allow the call */
+    XRB_ESCHED = -7    /* replay schedule exhausted or inconsistent */
+} xrb_status;
+
+/* The schemes of Sec. 3.3 plus the comparison and starting methods:
+ * exprb42 (eq. 3.11), pexprb43 (eq. 3.12), exprb53 (eq. 3.13),
+ * epi3 (eq. epi3, started by one EPI2 step), EPI2 = exponential
+ * Rosenbrock-Euler (eq. 3.5). */
+typedef enum {
+    XRB_EXPRB42 = 0,
+    XRB_PEXPRB43 = 1,
+    XRB_EXPRB53 = 2,
+    XRB_EPI3 = 3,
+    XRB_EPI2 = 4
+} xrb_method;
+
+/* Substep schedule handling of phi_combo: FREE = the device controller
+ * decides; RECORD = as FREE, and every attempt (tau used, Krylov size,
+ * accept/land flags) is appended to the context's schedule; REPLAY = the
+ * attempts are taken from a schedule given with xrb_schedule_set instead of
+ * the controller (bitwise-reproducible reruns). */
+typedef enum { XRB_FREE = 0, XRB_RECORD = 1, XRB_REPLAY = 2 } xrb_sched_mode;
+
+/* Icosahedral geodesic grid, unit sphere, HOST arrays (copied by xrb_create):
+ *   xyz[3*i+k]        cell centre i (unit vector), k = x, y, z
+ *   deg[i]            5 (pentagon) or 6
+ *   nbr[6*i+s]        neighbours in counter-clockwise order seen from outside;
+ *                     a pentagon's slot 5 holds i itself
+ *   corners[18*i+3*s+k] Voronoi vertex shared by i, nbr[s], nbr[s+1 mod deg]
+ * Cell geometry (areas, edge lengths, normals) is derived from these. */
+typedef struct {
+    int64_t n_cells;
+    const double *xyz;
+    const int32_t *deg;
+    const int32_t *nbr;
+    const double *corners;
+} xrb_mesh;
+
+/* Model and evaluator parameters.
+ *   radius, omega, gravity       sphere radius (m), rotation rate (1/s), g (m/s^2)
+ *   gamma_h, dt_e                hyperdissipation D_f = -nu L^2 with
+ *                                nu = gamma_h dxbar^4 / dt_e, dxbar = sqrt(4 pi a^2 / N)
+ *                                (eqs. swdis, niu; n_gamma = 4)
+ *   tol                          phi_combo tolerance, relative to max_l ||v_l||_2
+ *   m_init, m_max                first / largest Krylov size (m_max <= XRB_MMAX_LIMIT)
+ *   delta, gamma                 acceptance safety factor (Alg. 1: 1.4) and
+ *                                controller safety factor (0.8)
+ *   max_attempts                 cap on substep attempts per phi_combo call */
+typedef struct {
+    double radius, omega, gravity, gamma_h, dt_e;
+    double tol;
+    int32_t m_init, m_max;
+    double delta, gamma;
+    int32_t max_attempts;
+} xrb_params;
+
+#define XRB_MMAX_LIMIT 44
+#define XRB_PMAX 4
+
+typedef struct {
+    int32_t attempts, rejected, accepted, matvecs, expms, sum_m, max_m, last_m, rec_matvecs;
+} xrb_phi_stats;
+
+/* Fill p with the defaults (a = 6.371e6 m, Omega = 7.292e-5 1/s,
+ * g = 9.80616 m/s^2, gamma_h = 4e-4, dt_e = 240 s, tol = 1e-10, m_init = 1,
+ * m_max = 40, delta = 1.4, gamma = 0.8, max_attempts = 10000). */
+xrb_status xrb_default_params(xrb_params *p);
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t (NULL
+ * = the default stream).  Allocates all device workspace (Krylov basis of
+ * m_max+1 vectors plus stage vectors, about (m_max + 24) * 32 N bytes).
+ * Errors: EINVAL (mesh inconsistent, m_max out of range), ENOMEM, EDEVICE. */
+xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stream,
+                      xrb_ctx **out);
+xrb_status xrb_destroy(xrb_ctx *ctx);
+xrb_status xrb_set_stream(xrb_ctx *ctx, void *stream);
+/* Wait for all work enqueued on the context's stream. */
+xrb_status xrb_sync(xrb_ctx *ctx);
+const char *xrb_last_error(const xrb_ctx *ctx);
+int64_t xrb_n_cells(const xrb_ctx *ctx);
+
+/* f = F(u): the semi-discrete shallow-water right-hand side of eq. sweqsinv
+ * (vector-invariant momentum with absolute vorticity eq. vort, flux-form
+ * continuity, h_s = 0) plus D_f = -nu L^2 on every variable (eq. swdis).
+ * u, f: device, length 4N, must not alias. */
+xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f);
+
+/* jv = J(u) v with J = J_v + J_r + J_m of eqs. dynjs-dynjc (the Jacobian of
+ * F, so the row-2 rotation signs follow from P_y = n_z u_x - n_x u_z).
+ * Device vectors of length 4N; jv must not alias u or v. */
+xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv);
+
+/* W_i = sum_{l=0}^p rho_i^l phi_l(rho_i dt J(u)) v_l, i = 1..ns
+ * (phipm_simul_iom2, Alg. 1 of Sec. 4.3; the multi-output form of
+ * eq. exp_multistage with the rho^l weights that make W_i the solution of
+ * eq. 3.15 at t = rho_i).
+ *   dt     scaling of the Jacobian (A = dt J(u))
+ *   u      device, linearisation state
+ *   p      0 <= p <= XRB_PMAX
+ *   v      host array of p+1 device pointers; NULL = zero vector (enables the
+ *          zero-skip of Sec. 4.3)
+ *   ns     1 <= ns <= 8; rho host array, 0 < rho_1 < ... < rho_ns <= 1
+ *   w_out  host array of ns device pointers, must not alias u or any v
+ *   stats  optional host output
+ * Substeps follow the context's schedule mode.  Each call starts at Krylov
+ * size m_init (the scheme driver xrb_step keeps per-call-site warm starts).
+ * Errors: EINVAL (sizes, rho order, aliasing that can be seen), ENOTCONV,
+ * ENAN, ESCHED (replay schedule exhausted), EDEVICE. */
+xrb_status xrb_phi_combo(xrb_ctx *ctx, double dt, const double *u, int p,
+                         const double *const *v, int ns, const double *rho,
+                         double *const *w_out, xrb_phi_stats *stats);
+
+/* One step u <- u_{n+1} of `method` with step size dt (device u, in place),
+ * through the phi_combo call mapping of Sec. 4.4 with A = dt J(u_n),
+ * v = dt F(u_n).  Each scheme call site keeps its own Krylov warm start;
+ * epi3 keeps u_{n-1} and F(u_{n-1}) in the context (the first epi3 step, or
+ * the first after xrb_reset_history, is an EPI2 step). */
+xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt);
+
+/* Per-call-site statistics of the last xrb_step (3 entries). */
+xrb_status xrb_step_stats(const xrb_ctx *ctx, xrb_phi_stats *out3);
+
+/* Forget warm starts, epi3 history and the recorded schedule. */
+xrb_status xrb_reset_history(xrb_ctx *ctx);
+
+/* Schedule control.  Entries are host triples (tau, m, flags) with flags
+ * bit 0 = accepted, bit 1 = landed on an output time.  xrb_schedule_set
+ * copies `len` entries and rewinds the replay cursor; xrb_schedule_get copies
+ * up to `cap` recorded entries and reports the total in *len. */
+xrb_status xrb_schedule_mode(xrb_ctx *ctx, int mode);
+xrb_status xrb_schedule_set(xrb_ctx *ctx, const double *entries, int len);
+xrb_status xrb_schedule_get(const xrb_ctx *ctx, double *entries, int cap, int *len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -310,9 +310,10 @@ class Stepper:
     """Runs one of the schemes with the oracle (keeps warm starts and epi3
     history across steps)."""
 
-    def __init__(self, problem_n, problem, method):
+    def __init__(self, problem_n, problem, method, owner=None):
         self.n = problem_n
         self.problem = problem
+        self._owner = owner          # keeps the model (and its C state) alive
         self.method = METHODS[method] if isinstance(method, str) else method
         self.state = StepState()
         lib().orc_step_state_init(C.byref(self.state), self.n)
@@ -337,7 +338,7 @@ class Stepper:
 
 
 def swe_stepper(swe, method):
-    return Stepper(swe.N, swe.problem, method)
+    return Stepper(swe.N, swe.problem, method, owner=swe)
 
 
 class CallbackProblem:
@@ -360,4 +361,4 @@ class CallbackProblem:
         self.problem = Problem(n, self._rhs, self._jv, None)
 
     def stepper(self, method):
-        return Stepper(self.n, self.problem, method)
+        return Stepper(self.n, self.problem, method, owner=self)

@@ -1,0 +1,226 @@
+"""Python binding of libexprb (HIP, gfx950): argument marshalling only.
+
+Every arithmetic step runs in the library's HIP kernels.  PyTorch is used
+for device memory (tensors are passed by data_ptr) and for the current HIP
+stream.  There is no CPU fallback: importing works without a GPU, but any
+call needs the built library and a visible GPU, and fails loudly otherwise.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libexprb.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ENAN, ESTATE, ESCHED = 0, -1, -2, -3, -4, -5, -6, -7
+FREE, RECORD, REPLAY = 0, 1, 2
+METHODS = {"exprb42": 0, "pexprb43": 1, "exprb53": 2, "epi3": 3, "epi2": 4}
+MMAX_LIMIT = 44
+PMAX = 4
+
+EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
+           "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
+           "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
+           "xrb_schedule_get"]
+
+_dp = C.POINTER(C.c_double)
+
+
+class Mesh(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("xyz", _dp), ("deg", C.POINTER(C.c_int32)),
+                ("nbr", C.POINTER(C.c_int32)), ("corners", _dp)]
+
+
+class Params(C.Structure):
+    _fields_ = [("radius", C.c_double), ("omega", C.c_double), ("gravity", C.c_double),
+                ("gamma_h", C.c_double), ("dt_e", C.c_double), ("tol", C.c_double),
+                ("m_init", C.c_int32), ("m_max", C.c_int32), ("delta", C.c_double),
+                ("gamma", C.c_double), ("max_attempts", C.c_int32)]
+
+
+class PhiStats(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("attempts", "rejected", "accepted", "matvecs", "expms",
+                                         "sum_m", "max_m", "last_m", "rec_matvecs")]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libexprb.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libexprb.so is not built: run paper_1805_02144_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIBPATH)
+        vp = C.c_void_p
+        L.xrb_default_params.argtypes = [C.POINTER(Params)]
+        L.xrb_create.argtypes = [C.POINTER(Mesh), C.POINTER(Params), vp, C.POINTER(vp)]
+        L.xrb_destroy.argtypes = [vp]
+        L.xrb_set_stream.argtypes = [vp, vp]
+        L.xrb_sync.argtypes = [vp]
+        L.xrb_last_error.argtypes = [vp]
+        L.xrb_last_error.restype = C.c_char_p
+        L.xrb_n_cells.argtypes = [vp]
+        L.xrb_n_cells.restype = C.c_int64
+        L.xrb_rhs.argtypes = [vp, vp, vp]
+        L.xrb_jv.argtypes = [vp, vp, vp, vp]
+        L.xrb_phi_combo.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(vp), C.c_int, _dp,
+                                    C.POINTER(vp), C.POINTER(PhiStats)]
+        L.xrb_step.argtypes = [vp, C.c_int, vp, C.c_double]
+        L.xrb_step_stats.argtypes = [vp, C.POINTER(PhiStats)]
+        L.xrb_reset_history.argtypes = [vp]
+        L.xrb_schedule_mode.argtypes = [vp, C.c_int]
+        L.xrb_schedule_set.argtypes = [vp, _dp, C.c_int]
+        L.xrb_schedule_get.argtypes = [vp, _dp, C.c_int, C.POINTER(C.c_int)]
+        for f in EXPORTS:
+            if f not in ("xrb_last_error", "xrb_n_cells"):
+                getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def default_params(**kw):
+    p = Params()
+    lib().xrb_default_params(C.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+class ExprbError(RuntimeError):
+    pass
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libexprb needs a visible GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context: mesh geometry on the GPU plus workspaces."""
+
+    def __init__(self, mesh, device="cuda:0", **params):
+        torch = _torch()
+        self.torch = torch
+        self.device = torch.device(device)
+        self._xyz = np.ascontiguousarray(mesh["xyz"], dtype=np.float64)
+        self._deg = np.ascontiguousarray(mesh["deg"], dtype=np.int32)
+        self._nbr = np.ascontiguousarray(mesh["nbr"], dtype=np.int32)
+        self._cor = np.ascontiguousarray(mesh["corners"], dtype=np.float64)
+        self.n = len(self._xyz)
+        self.N = 4 * self.n
+        m = Mesh(self.n, self._xyz.ctypes.data_as(_dp),
+                 self._deg.ctypes.data_as(C.POINTER(C.c_int32)),
+                 self._nbr.ctypes.data_as(C.POINTER(C.c_int32)), self._cor.ctypes.data_as(_dp))
+        self.params = default_params(**params)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            self._check(lib().xrb_create(C.byref(m), C.byref(self.params), C.c_void_p(stream),
+                                         C.byref(h)), None)
+        self.h = h
+
+    def _check(self, rc, h="self"):
+        if rc != OK:
+            msg = lib().xrb_last_error(self.h if h == "self" else None)
+            raise ExprbError("libexprb error %d: %s" % (rc, msg.decode() if msg else ""))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().xrb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        lib().xrb_set_stream(self.h, C.c_void_p(s))
+
+    def _vec(self, x):
+        t = self.torch.as_tensor(x, dtype=self.torch.float64, device=self.device)
+        t = t.contiguous()
+        if t.numel() != self.N:
+            raise ValueError("vector of length %d expected" % self.N)
+        return t
+
+    def empty(self):
+        return self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
+
+    def sync(self):
+        self._check(lib().xrb_sync(self.h))
+
+    def rhs(self, u):
+        self._stream()
+        u = self._vec(u)
+        f = self.empty()
+        self._check(lib().xrb_rhs(self.h, _ptr(u), _ptr(f)))
+        return f
+
+    def jv(self, u, v):
+        self._stream()
+        u, v = self._vec(u), self._vec(v)
+        out = self.empty()
+        self._check(lib().xrb_jv(self.h, _ptr(u), _ptr(v), _ptr(out)))
+        return out
+
+    def phi_combo(self, u, dt, vs, rho, return_stats=False):
+        """W_i = sum_l rho_i^l phi_l(rho_i dt J(u)) v_l (vs: list, None = 0)."""
+        self._stream()
+        u = self._vec(u)
+        keep = [None if v is None else self._vec(v) for v in vs]
+        va = (C.c_void_p * len(vs))(*[None if v is None else v.data_ptr() for v in keep])
+        outs = [self.empty() for _ in rho]
+        oa = (C.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        r = np.ascontiguousarray(rho, dtype=np.float64)
+        st = PhiStats()
+        self._check(lib().xrb_phi_combo(self.h, float(dt), _ptr(u), len(vs) - 1, va, len(outs),
+                                        r.ctypes.data_as(_dp), oa, C.byref(st)))
+        return (outs, st.asdict()) if return_stats else outs
+
+    def step(self, method, u, dt):
+        """Advance u (a float64 device tensor, updated in place) by one step."""
+        self._stream()
+        if not (u.is_contiguous() and u.dtype == self.torch.float64 and u.numel() == self.N
+                and u.device == self.device):
+            raise ValueError("u must be a contiguous float64 tensor of length 4N on the device")
+        mid = METHODS[method] if isinstance(method, str) else int(method)
+        self._check(lib().xrb_step(self.h, mid, _ptr(u), float(dt)))
+        return u
+
+    def step_stats(self):
+        st = (PhiStats * 3)()
+        self._check(lib().xrb_step_stats(self.h, st))
+        return [s.asdict() for s in st]
+
+    def reset_history(self):
+        self._check(lib().xrb_reset_history(self.h))
+
+    def schedule_mode(self, mode):
+        self._check(lib().xrb_schedule_mode(self.h, int(mode)))
+
+    def schedule_set(self, arr):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(-1, 3))
+        self._check(lib().xrb_schedule_set(self.h, a.ctypes.data_as(_dp), len(a)))
+
+    def schedule_get(self):
+        n = C.c_int()
+        self._check(lib().xrb_schedule_get(self.h, None, 0, C.byref(n)))
+        a = np.zeros((max(1, n.value), 3))
+        self._check(lib().xrb_schedule_get(self.h, a.ctypes.data_as(_dp), n.value, C.byref(n)))
+        return a[:n.value]

@@ -1,0 +1,118 @@
+// Host-side preparation of the finite-volume stencil weights (Sec. 2).
+//
+// The paper writes the semi-discrete model with sparse gradient, divergence,
+// vorticity and Laplacian matrices on the Voronoi cells of the icosahedral
+// grid.  Here each cell i keeps, per neighbour slot s (edge e to cell j):
+//   a_s = l_e n_e / (2 A_i)   (flux divergence: sum_s a_s . (F_i + F_j);
+//                              gradient: P_i sum_s a_s (psi_j - psi_i))
+//   b_s = l_e t_e / (2 A_i)   (circulation: sum_s b_s . (u_i + u_j))
+//   c_s = l_e / (d_e A_i)     (Laplacian: sum_s c_s (psi_j - psi_i))
+// with l_e the great-circle length of the Voronoi edge (between the two
+// corners that bound it), d_e the great-circle distance of the centres,
+// A_i the spherical area of the cell, n_e the unit tangent normal at the
+// edge direction (x_i + x_j)/|x_i + x_j| pointing from i to j, and
+// t_e = rhat_e x n_e.  Pentagon slot 5 gets zero weights.
+#include <cmath>
+
+#include "xrb_internal.h"
+
+namespace xrb {
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 mul(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) {
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double len(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 unit(V3 a) {
+    double l = len(a);
+    return {a.x / l, a.y / l, a.z / l};
+}
+// angle between two unit vectors
+inline double angle(V3 a, V3 b) { return std::atan2(len(cross(a, b)), dot(a, b)); }
+// spherical excess of the unit-sphere triangle (a, b, c)
+inline double excess(V3 a, V3 b, V3 c) {
+    double num = std::fabs(dot(a, cross(b, c)));
+    double den = 1.0 + dot(a, b) + dot(b, c) + dot(c, a);
+    return 2.0 * std::atan2(num, den);
+}
+
+}  // namespace
+
+int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,
+                   std::string &err) {
+    const int64_t n = mesh.n_cells;
+    if (n < 12 || !mesh.xyz || !mesh.deg || !mesh.nbr || !mesh.corners) {
+        err = "mesh: null array or fewer than 12 cells";
+        return XRB_EINVAL;
+    }
+    if (n > (int64_t)1 << 28) {
+        err = "mesh: too many cells";
+        return XRB_EINVAL;
+    }
+    const double R = prm.radius;
+    geo.n = (int)n;
+    auto resize6 = [&](std::vector<double> &v) { v.assign(6 * (size_t)n, 0.0); };
+    geo.nbr.assign(6 * (size_t)n, 0);
+    resize6(geo.ax); resize6(geo.ay); resize6(geo.az);
+    resize6(geo.bx); resize6(geo.by); resize6(geo.bz);
+    resize6(geo.cl);
+    geo.nx.resize(n); geo.ny.resize(n); geo.nz.resize(n); geo.cor.resize(n);
+
+    auto X = [&](int64_t i) { return V3{mesh.xyz[3 * i], mesh.xyz[3 * i + 1], mesh.xyz[3 * i + 2]}; };
+    auto CRN = [&](int64_t i, int s) {
+        const double *c = mesh.corners + 18 * i + 3 * s;
+        return V3{c[0], c[1], c[2]};
+    };
+
+    for (int64_t i = 0; i < n; ++i) {
+        const int d = mesh.deg[i];
+        if (d != 5 && d != 6) {
+            err = "mesh: degree must be 5 or 6";
+            return XRB_EINVAL;
+        }
+        const V3 xi = X(i);
+        // cell area first (needed by every weight)
+        double ex = 0.0;
+        for (int s = 0; s < d; ++s) ex += excess(xi, CRN(i, (s + d - 1) % d), CRN(i, s));
+        const double area = R * R * ex;
+        for (int s = 0; s < 6; ++s) {
+            const size_t k = (size_t)s * n + i;
+            if (s >= d) {                      // pentagon padding: self, zero weights
+                geo.nbr[k] = (int32_t)i;
+                continue;
+            }
+            const int32_t j = mesh.nbr[6 * i + s];
+            if (j < 0 || j >= n || j == i) {
+                err = "mesh: neighbour index out of range";
+                return XRB_EINVAL;
+            }
+            geo.nbr[k] = j;
+            const V3 xj = X(j);
+            const double le = R * angle(CRN(i, (s + d - 1) % d), CRN(i, s));
+            const double de = R * angle(xi, xj);
+            const V3 rh = unit(add(xi, xj));
+            V3 dv = sub(xj, xi);
+            dv = sub(dv, mul(dot(dv, rh), rh));
+            const V3 ne = unit(dv);
+            const V3 te = cross(rh, ne);
+            const double w = le / (2.0 * area);
+            geo.ax[k] = w * ne.x; geo.ay[k] = w * ne.y; geo.az[k] = w * ne.z;
+            geo.bx[k] = w * te.x; geo.by[k] = w * te.y; geo.bz[k] = w * te.z;
+            geo.cl[k] = le / (de * area);
+        }
+        geo.nx[i] = xi.x; geo.ny[i] = xi.y; geo.nz[i] = xi.z;
+        geo.cor[i] = 2.0 * prm.omega * xi.z;
+    }
+    const double dxbar = std::sqrt(4.0 * M_PI * R * R / (double)n);
+    geo.nu = prm.gamma_h * dxbar * dxbar * dxbar * dxbar / prm.dt_e;
+    return XRB_OK;
+}
+
+}  // namespace xrb

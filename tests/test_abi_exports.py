@@ -1,0 +1,50 @@
+"""CPU checks of the boundary: the HIP library loads and exports every
+function that include/exprb.h declares; the binding declares the same set;
+the oracle and the library share no source."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "exprb.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(xrb_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1805_02144_amd as X
+    if not os.path.exists(X.LIBPATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(X.LIBPATH)
+    names = declared()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(X.EXPORTS) == names
+
+
+def test_default_params_without_gpu():
+    import paper_1805_02144_amd as X
+    if not os.path.exists(X.LIBPATH):
+        pytest.skip("library not built")
+    p = X.default_params()
+    assert p.m_max == 40 and p.m_init == 1 and p.tol == 1e-10 and p.delta == 1.4
+    assert p.radius == 6.371e6 and p.gravity == 9.80616
+
+
+def test_oracle_and_library_share_no_source():
+    csrc = os.path.join(ROOT, "paper_1805_02144_amd", "csrc")
+    osrc = os.path.join(ROOT, "oracle")
+    for f in os.listdir(csrc):
+        txt = open(os.path.join(csrc, f)).read()
+        assert "orc_" not in txt and "oracle" not in txt.lower(), f
+    for f in os.listdir(osrc):
+        if f.endswith((".c", ".h")):
+            txt = open(os.path.join(osrc, f)).read()
+            assert "xrb_" not in txt and "exprb.h" not in txt, f

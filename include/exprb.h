@@ -171,6 +171,31 @@ xrb_status xrb_schedule_mode(xrb_ctx *ctx, int mode);
 xrb_status xrb_schedule_set(xrb_ctx *ctx, const double *entries, int len);
 xrb_status xrb_schedule_get(const xrb_ctx *ctx, double *entries, int cap, int *len);
 
+/* Optional per-kernel timing.  xrb_profile(ctx, N) with N >= 1 zeroes the
+ * counters and brackets every N-th launch of each kernel below (made by
+ * xrb_phi_combo / xrb_step) with a pair of HIP events on the context's
+ * stream; N = 1 times every launch, a larger N samples and keeps the event
+ * overhead out of most launches.  Times are collected at the
+ * synchronisation points the calls already have.  xrb_profile(ctx, 0)
+ * disables.  Kernel ids: */
+enum {
+    XRB_K_JV_IOM2 = 0,   /* Jacobian product fused with the IOM2 dots   */
+    XRB_K_LAP = 1,       /* one-ring Laplacian pass (L x)               */
+    XRB_K_IOM2_UPD = 2,  /* IOM2 two-term update + norm                 */
+    XRB_K_CTL = 3,       /* augmented exponential + controller          */
+    XRB_K_COMBINE = 4,   /* substep combination y_{k+1}                 */
+    XRB_K_JV_OTHER = 5,  /* Jacobian products of the w_j recurrence/stages */
+    XRB_K_RHS = 6,       /* right-hand side F(u)                        */
+    XRB_K_VEC = 7,       /* linear combinations, norms                  */
+    XRB_K_COUNT = 8
+};
+xrb_status xrb_profile(xrb_ctx *ctx, int enable);
+/* Since the last xrb_profile(ctx, N >= 1): device milliseconds summed over
+ * the timed launches of kernel `kernel`, the number of timed launches, and
+ * the number of all launches of that kernel. */
+xrb_status xrb_profile_get(const xrb_ctx *ctx, int kernel, double *timed_ms, int64_t *timed,
+                           int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

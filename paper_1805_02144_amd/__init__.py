@@ -22,7 +22,9 @@ PMAX = 4
 EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
            "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
-           "xrb_schedule_get"]
+           "xrb_schedule_get", "xrb_profile", "xrb_profile_get"]
+
+KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
 _dp = C.POINTER(C.c_double)
 
@@ -78,6 +80,9 @@ def lib():
         L.xrb_schedule_mode.argtypes = [vp, C.c_int]
         L.xrb_schedule_set.argtypes = [vp, _dp, C.c_int]
         L.xrb_schedule_get.argtypes = [vp, _dp, C.c_int, C.POINTER(C.c_int)]
+        L.xrb_profile.argtypes = [vp, C.c_int]
+        L.xrb_profile_get.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
         for f in EXPORTS:
             if f not in ("xrb_last_error", "xrb_n_cells"):
                 getattr(L, f).restype = C.c_int
@@ -217,6 +222,23 @@ class Context:
     def schedule_set(self, arr):
         a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(-1, 3))
         self._check(lib().xrb_schedule_set(self.h, a.ctypes.data_as(_dp), len(a)))
+
+    def profile(self, every=1):
+        """Time every `every`-th launch of each kernel with HIP events
+        (counters zeroed); every = 0 disables."""
+        self._check(lib().xrb_profile(self.h, int(every)))
+
+    def profile_get(self):
+        """{kernel: (device ms over the timed launches, timed launches, all launches)}."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms = C.c_double()
+            cnt = C.c_int64()
+            allc = C.c_int64()
+            self._check(lib().xrb_profile_get(self.h, k, C.byref(ms), C.byref(cnt),
+                                              C.byref(allc)))
+            out[name] = (ms.value, cnt.value, allc.value)
+        return out
 
     def schedule_get(self):
         n = C.c_int()

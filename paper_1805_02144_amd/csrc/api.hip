@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 
+#include "reduce.h"
 #include "xrb_internal.h"
 
 using namespace xrb;
@@ -32,7 +33,9 @@ struct xrb_ctx {
     double *lap = nullptr;      // L x scratch
     double *eta = nullptr;      // V.u + f at the current linearisation point
     double *stage = nullptr;    // 16 stage vectors of the schemes
-    double *partials = nullptr;
+    double *dot_parts = nullptr;   // IOM2 dot partials (2 per block)
+    double *nrm_parts = nullptr;   // norm partials, two buffers: column j uses buffer j % 2
+    double *v_parts = nullptr;     // norm partials of the phi_combo inputs
     double *vnorm2 = nullptr;
     PhiCtl *ctl = nullptr;
     Decision *dec_host = nullptr;
@@ -44,6 +47,17 @@ struct xrb_ctx {
     int m_warm[3] = {0, 0, 0};
     int have_prev = 0;
     xrb_phi_stats last_stats[3]{};
+    // optional per-kernel event timing
+    struct Pending {
+        int id;
+        hipEvent_t a, b;
+    };
+    int prof_every = 0;            // 0 = off, N = time every N-th launch of each kernel
+    int64_t prof_seen[XRB_K_COUNT] = {};
+    std::vector<hipEvent_t> ev_free;
+    std::vector<Pending> ev_pend;
+    double prof_ms[XRB_K_COUNT] = {};
+    int64_t prof_n[XRB_K_COUNT] = {};
 
     double *sv(int k) { return stage + (size_t)k * n4; }
 };
@@ -64,13 +78,56 @@ int fail(xrb_ctx *ctx, int code, const char *msg) {
     return code;
 }
 
+hipEvent_t ev_get(xrb_ctx *ctx) {
+    if (!ctx->ev_free.empty()) {
+        hipEvent_t e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Bracket a launch with events when profiling is on.
+template <class F>
+void timed(xrb_ctx *ctx, int id, F &&launch) {
+    if (ctx->prof_every <= 0 || (ctx->prof_seen[id]++ % ctx->prof_every) != 0) {
+        launch();
+        return;
+    }
+    hipEvent_t a = ev_get(ctx), b = ev_get(ctx);
+    if (!a || !b) {
+        launch();
+        return;
+    }
+    (void)hipEventRecord(a, ctx->stream);
+    launch();
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->ev_pend.push_back({id, a, b});
+}
+
+// Collect finished event pairs (called after a stream synchronisation).
+void prof_drain(xrb_ctx *ctx) {
+    for (auto &p : ctx->ev_pend) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->prof_ms[p.id] += ms;
+            ctx->prof_n[p.id] += 1;
+        }
+        ctx->ev_free.push_back(p.a);
+        ctx->ev_free.push_back(p.b);
+    }
+    ctx->ev_pend.clear();
+}
+
 // stage slots used by xrb_step
 enum { S_FN, S_V, S_W1, S_W2, S_X1, S_X2, S_U2, S_U3, S_D2, S_D3, S_A3, S_A4, S_T1, S_T2,
        S_UPREV, S_FPREV, S_COUNT };
 
 // J(u) x into out (kernel chain: L x, then the fused product); eta must hold V.u + f
 void jv_plain(xrb_ctx *ctx, const double *u, const double *x, double *out, double dt) {
-    launch_lap4(ctx->M, x, ctx->lap, ctx->stream);
+    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, x, ctx->lap, ctx->stream); });
     JvArgs a;
     a.u = u;
     a.eta = ctx->eta;
@@ -78,12 +135,12 @@ void jv_plain(xrb_ctx *ctx, const double *u, const double *x, double *out, doubl
     a.lx = ctx->lap;
     a.dt = dt;
     a.out = out;
-    launch_jv(ctx->M, a, kEpiNone, ctx->stream);
+    timed(ctx, XRB_K_JV_OTHER, [&] { launch_jv(ctx->M, a, kEpiNone, ctx->stream); });
 }
 
 void rhs_plain(xrb_ctx *ctx, const double *u, double *f) {
-    launch_lap4(ctx->M, u, ctx->lap, ctx->stream);
-    launch_rhs(ctx->M, u, ctx->lap, f, ctx->stream);
+    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, u, ctx->lap, ctx->stream); });
+    timed(ctx, XRB_K_RHS, [&] { launch_rhs(ctx->M, u, ctx->lap, f, ctx->stream); });
 }
 
 void lincomb(xrb_ctx *ctx, double *out, std::initializer_list<const double *> vs,
@@ -97,7 +154,7 @@ void lincomb(xrb_ctx *ctx, double *out, std::initializer_list<const double *> vs
         cc[k] = *ci++;
         ++k;
     }
-    launch_lincomb(ctx->n4, out, k, vv, cc, ctx->stream);
+    timed(ctx, XRB_K_VEC, [&] { launch_lincomb(ctx->n4, out, k, vv, cc, ctx->stream); });
 }
 
 // phipm_simul_iom2 with eta = V.u + f already computed for u.
@@ -118,16 +175,21 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
             if (v[l] && v[l] == w_out[i]) return fail(ctx, XRB_EINVAL, "phi_combo: output aliases input");
     }
     // scale = max_l ||v_l||; all-zero inputs give W = 0 exactly
+    const int n = ctx->n;
+    int np_r0 = 0, np_dot = 0, np_upd = 0;   // partial counts of the last producers
     const double *vl[kPmax + 1];
     int nv = 0;
     for (int l = 0; l <= p; ++l)
-        if (v[l]) {
-            launch_norm2(n4, v[l], ctx->vnorm2 + nv, ctx->partials, &ctx->ctl->counters[3], s);
-            vl[nv++] = v[l];
-        }
+        if (v[l]) vl[nv++] = v[l];
+    int m = m_start > 0 ? m_start : P.m_init;
+    m = std::min(std::max(m, 1), P.m_max);
+    int npv = 0;
+    if (nv > 0) timed(ctx, XRB_K_VEC, [&] { npv = launch_norms(n, nv, vl, ctx->v_parts, s); });
+    launch_phi_init(ctx->ctl, m, rho[0], P.tol, ctx->v_parts, npv, nv, ctx->vnorm2, s);
     HIPCHK(hipMemcpyAsync(ctx->vn_host, ctx->vnorm2, sizeof(double) * (kPmax + 1),
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    prof_drain(ctx);
     double smax = 0.0;
     for (int k = 0; k < nv; ++k) {
         if (ctx->vn_host[k] != ctx->vn_host[k]) return fail(ctx, XRB_ENAN, "phi_combo: NaN input");
@@ -138,10 +200,6 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
         if (st_out) *st_out = st;
         return XRB_OK;
     }
-    int m = m_start > 0 ? m_start : P.m_init;
-    m = std::min(std::max(m, 1), P.m_max);
-    launch_phi_init(ctx->ctl, m, rho[0], P.tol, ctx->vnorm2, nv, s);
-
     int y_zero = 1;
     if (v[0]) {
         HIPCHK(hipMemcpyAsync(ctx->y, v[0], sizeof(double) * n4, hipMemcpyDeviceToDevice, s));
@@ -149,6 +207,7 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
     }
     int wzero[kPmax + 1];
     const double *wptr[kPmax + 1];
+    auto nrm_buf = [&](int col) { return ctx->nrm_parts + (size_t)(col & 1) * kRedBlocks; };
     bool point_ready = false;
     int built = 0, wp_zero = 0;
 
@@ -185,7 +244,7 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
                     }
                     const int epi = (j == p) ? kEpiNorm : kEpiNone;
                     if (!wzero[j - 1]) {
-                        launch_lap4(ctx->M, wptr[j - 1], ctx->lap, s);
+                        timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, wptr[j - 1], ctx->lap, s); });
                         a.u = u;
                         a.eta = ctx->eta;
                         a.x = wptr[j - 1];
@@ -193,14 +252,20 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
                         a.dt = dt;
                         a.out = dst;
                         a.ctl = ctx->ctl;
-                        a.partials = ctx->partials;
-                        launch_jv(ctx->M, a, epi, s);
+                        a.nrm_out = ctx->nrm_parts;
+                        timed(ctx, XRB_K_JV_OTHER, [&] {
+                            const int g = launch_jv(ctx->M, a, epi, s);
+                            if (j == p) np_r0 = g;
+                        });
                         st.matvecs++;
                         st.rec_matvecs++;
                         wzero[j] = 0;
                     } else if (a.naxpy > 0) {
-                        launch_lincomb_dev(n4, dst, a.naxpy, a.axv, a.axc, ctx->ctl, ctx->partials,
-                                           j == p, s);
+                        timed(ctx, XRB_K_VEC, [&] {
+                            const int g = launch_lincomb_dev(n, dst, a.naxpy, a.axv, a.axc,
+                                                             j == p ? ctx->nrm_parts : nullptr, s);
+                            if (j == p) np_r0 = g;
+                        });
                         wzero[j] = 0;
                     } else {
                         wzero[j] = 1;
@@ -213,7 +278,7 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
                     if (!y_zero) {
                         const double *one[1] = {ctx->y};
                         const double *cf[1] = {&ctx->ctl->rec_coef[0]};
-                        launch_lincomb_dev(n4, ctx->V, 1, one, cf, ctx->ctl, ctx->partials, 1, s);
+                        np_r0 = launch_lincomb_dev(n, ctx->V, 1, one, cf, ctx->nrm_parts, s);
                     }
                     wp_zero = y_zero;
                 }
@@ -226,22 +291,24 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
                     double *rj = ctx->V + (size_t)j * n4;
                     double *rn = ctx->V + (size_t)(j + 1) * n4;
                     const double *rm = j > 0 ? ctx->V + (size_t)(j - 1) * n4 : nullptr;
-                    launch_lap4(ctx->M, rj, ctx->lap, s);
+                    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, ctx->lap, s); });
                     JvArgs a;
                     a.u = u;
                     a.eta = ctx->eta;
                     a.x = rj;
                     a.lx = ctx->lap;
-                    a.scale_ptr = &ctx->ctl->sigma[j];
                     a.dt = dt;
                     a.out = rn;
                     a.j = j;
-                    a.rj = rj;
                     a.rjm1 = rm;
                     a.ctl = ctx->ctl;
-                    a.partials = ctx->partials;
-                    launch_jv(ctx->M, a, kEpiIom2, s);
-                    launch_iom2_update(n4, j, rn, rj, rm, ctx->ctl, ctx->partials, s);
+                    a.dot_out = ctx->dot_parts;
+                    timed(ctx, XRB_K_JV_IOM2, [&] { np_dot = launch_jv(ctx->M, a, kEpiIom2, s); });
+                    const int np_in = (j == 0) ? np_r0 : np_upd;
+                    timed(ctx, XRB_K_IOM2_UPD, [&] {
+                        np_upd = launch_iom2_update(n, j, rn, rj, rm, ctx->ctl, nrm_buf(j), np_in,
+                                                    ctx->dot_parts, np_dot, nrm_buf(j + 1), s);
+                    });
                     st.matvecs++;
                 }
                 built = std::max(built, m);
@@ -253,14 +320,18 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
             ca.mode = ctx->mode;
             ca.m_max = P.m_max;
             ca.wp_zero = wp_zero;
+            ca.built = built;
+            ca.nrm_in = nrm_buf(built);
+            ca.n_nrm_in = np_upd;
             ca.n4 = (double)n4;
             ca.delta = P.delta;
             ca.gamma = P.gamma;
             ca.rep = rep;
-            launch_controller(ctx->ctl, ca, nullptr, s);
+            timed(ctx, XRB_K_CTL, [&] { launch_controller(ctx->ctl, ca, s); });
             HIPCHK(hipMemcpyAsync(ctx->dec_host, &ctx->ctl->dec, sizeof(Decision),
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
+            prof_drain(ctx);
             const Decision d = *ctx->dec_host;
             if (d.status == XRB_ENAN) return fail(ctx, XRB_ENAN, "phi_combo: NaN in Krylov process");
             if (d.status != 0) return fail(ctx, d.status, "phi_combo: device error");
@@ -272,8 +343,10 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
             if (ctx->mode == XRB_RECORD)
                 ctx->sched.push_back({d.tau_u, m, (d.accept ? 1 : 0) | (d.lands ? 2 : 0)});
             if (d.accept) {
-                launch_combine(n4, ctx->y, p, wptr, wzero, ctx->V, d.m_eff, d.m_eff > 0 ? 1 : 0,
-                               ctx->ctl, s);
+                timed(ctx, XRB_K_COMBINE, [&] {
+                    launch_combine(n4, ctx->y, p, wptr, wzero, ctx->V, d.m_eff, d.m_eff > 0 ? 1 : 0,
+                                   ctx->ctl, s);
+                });
                 st.accepted++;
                 st.last_m = m;
                 y_zero = 0;
@@ -292,8 +365,11 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
 }
 
 int free_all(xrb_ctx *ctx) {
+    prof_drain(ctx);
+    for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
+    ctx->ev_free.clear();
     void *dev[] = {ctx->geo_mem, ctx->V, ctx->W, ctx->y, ctx->lap, ctx->eta, ctx->stage,
-                   ctx->partials, ctx->vnorm2, ctx->ctl};
+                   ctx->dot_parts, ctx->nrm_parts, ctx->v_parts, ctx->vnorm2, ctx->ctl};
     int rc = XRB_OK;
     for (void *p : dev)
         if (p && hipFree(p) != hipSuccess) rc = XRB_EDEVICE;
@@ -360,7 +436,9 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ck(hipMalloc((void **)&ctx->lap, sizeof(double) * n4));
     ck(hipMalloc((void **)&ctx->eta, sizeof(double) * nd));
     ck(hipMalloc((void **)&ctx->stage, sizeof(double) * n4 * S_COUNT));
-    ck(hipMalloc((void **)&ctx->partials, sizeof(double) * 2 * kMaxBlocks));
+    ck(hipMalloc((void **)&ctx->dot_parts, sizeof(double) * 2 * kRedBlocks));
+    ck(hipMalloc((void **)&ctx->nrm_parts, sizeof(double) * 2 * kRedBlocks));
+    ck(hipMalloc((void **)&ctx->v_parts, sizeof(double) * (kPmax + 1) * kRedBlocks));
     ck(hipMalloc((void **)&ctx->vnorm2, sizeof(double) * (kPmax + 1)));
     ck(hipMalloc((void **)&ctx->ctl, sizeof(PhiCtl)));
     ck(hipHostMalloc((void **)&ctx->dec_host, sizeof(Decision), hipHostMallocDefault));
@@ -554,6 +632,7 @@ xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    prof_drain(ctx);
     return XRB_OK;
 }
 
@@ -597,6 +676,30 @@ xrb_status xrb_schedule_get(const xrb_ctx *ctx, double *entries, int cap, int *l
         entries[3 * i + 1] = ctx->sched[i].m;
         entries[3 * i + 2] = ctx->sched[i].flags;
     }
+    return XRB_OK;
+}
+
+xrb_status xrb_profile(xrb_ctx *ctx, int enable) {
+    if (!ctx) return XRB_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    prof_drain(ctx);
+    ctx->prof_every = enable > 0 ? enable : 0;
+    if (enable > 0)
+        for (int k = 0; k < XRB_K_COUNT; ++k) {
+            ctx->prof_ms[k] = 0.0;
+            ctx->prof_n[k] = 0;
+            ctx->prof_seen[k] = 0;
+        }
+    return XRB_OK;
+}
+
+xrb_status xrb_profile_get(const xrb_ctx *ctx, int kernel, double *timed_ms, int64_t *timed,
+                           int64_t *launches) {
+    if (!ctx || kernel < 0 || kernel >= XRB_K_COUNT || !timed_ms || !timed || !launches)
+        return XRB_EINVAL;
+    *timed_ms = ctx->prof_ms[kernel];
+    *timed = ctx->prof_n[kernel];
+    *launches = ctx->prof_seen[kernel];
     return XRB_OK;
 }
 

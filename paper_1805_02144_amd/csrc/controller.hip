@@ -11,6 +11,7 @@
 //     combination kernel and t^l/l! for the next w_j recurrence (eq. 3.18).
 // Matrices live in LDS (K <= 49, padded to 52); products use one 4x4
 // register tile per thread.
+#include "column.h"
 #include "reduce.h"
 #include "xrb_internal.h"
 
@@ -22,33 +23,39 @@ constexpr int kLd = 52;                 // padded order, multiple of 4, >= kKmax
 constexpr int kMat = kLd * kLd;
 static_assert(kLd >= kKmax && kLd % 4 == 0, "LDS matrix padding");
 
-// C = A B over the leading K4 x K4 block (K4 multiple of 4)
-__device__ void mat_mul(const double *A, const double *B, double *C, int K4) {
-    const int nt = K4 >> 2;
-    const int tid = threadIdx.x;
-    if (tid < nt * nt) {
-        const int r0 = (tid / nt) * 4, c0 = (tid % nt) * 4;
-        double acc[4][4];
+// C = A B over the leading K4 x K4 block (K4 multiple of 4).  Register tiles
+// of T x T per thread: T = 2 while (K4/2)^2 threads fit the block, else 4.
+template <int T>
+__device__ inline void mat_mul_tiles(const double *A, const double *B, double *C, int K4) {
+    const int nt = K4 / T;
+    for (int tile = threadIdx.x; tile < nt * nt; tile += blockDim.x) {
+        const int r0 = (tile / nt) * T, c0 = (tile % nt) * T;
+        double acc[T][T];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < T; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+            for (int c = 0; c < T; ++c) acc[r][c] = 0.0;
         for (int k = 0; k < K4; ++k) {
-            double a[4], b[4];
+            double a[T], b[T];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = A[(r0 + r) * kLd + k];
+            for (int r = 0; r < T; ++r) a[r] = A[(r0 + r) * kLd + k];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = B[k * kLd + c0 + c];
+            for (int c = 0; c < T; ++c) b[c] = B[k * kLd + c0 + c];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < T; ++r)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+                for (int c = 0; c < T; ++c) acc[r][c] += a[r] * b[c];
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < T; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) C[(r0 + r) * kLd + c0 + c] = acc[r][c];
+            for (int c = 0; c < T; ++c) C[(r0 + r) * kLd + c0 + c] = acc[r][c];
     }
+}
+
+__device__ void mat_mul(const double *A, const double *B, double *C, int K4) {
+    if ((K4 / 2) * (K4 / 2) <= (int)blockDim.x) mat_mul_tiles<2>(A, B, C, K4);
+    else mat_mul_tiles<4>(A, B, C, K4);
     __syncthreads();
 }
 
@@ -85,9 +92,21 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
     __shared__ double mult[kLd];
     __shared__ double sh_tau_u, sh_norm, sh_hsub;
     __shared__ int sh_lands, sh_meff, sh_s, sh_piv, sh_status;
+    __shared__ double red[32];
     const int tid = threadIdx.x;
     const int p = a.p;
     const int m = a.m;
+
+    // finish the norm of the last IOM2 column (h_{built,built-1} or beta)
+    if (!a.wp_zero && a.built >= 1) {
+        const bool live = (c->brk == 0) && !c->beta_zero;
+        if (live) {
+            double tot[1];
+            sum_partials<1>(tot, a.nrm_in, a.n_nrm_in, red);
+            finalize_column(c, a.built, tot[0], tid == 0, red);
+        }
+        __syncthreads();
+    }
 
     if (tid == 0) {
 #pragma clang fp contract(off)
@@ -202,21 +221,33 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
         __syncthreads();
         double *Mt = B4, *R = Vm;
         for (int col = 0; col < K; ++col) {
-            if (tid == 0) {
-                int piv = col;
-                double best = fabs(Mt[col * kLd + col]);
-                for (int r = col + 1; r < K; ++r) {
+            // partial pivoting: first row of largest |M(r, col)|, one wave
+            if (tid < 64) {
+                double best = -1.0;
+                int piv = K;
+                for (int r = col + tid; r < K; r += 64) {
                     const double v = fabs(Mt[r * kLd + col]);
                     if (v > best) {
                         best = v;
                         piv = r;
                     }
                 }
-                sh_piv = piv;
-                if (best == 0.0) sh_status = XRB_ENAN;
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ob = __shfl_down(best, off, 64);
+                    const int op = __shfl_down(piv, off, 64);
+                    if (ob > best || (ob == best && op < piv)) {
+                        best = ob;
+                        piv = op;
+                    }
+                }
+                if (tid == 0) {
+                    sh_piv = piv;
+                    if (!(best > 0.0)) sh_status = XRB_ENAN;
+                }
             }
             __syncthreads();
-            const int piv = sh_piv;
+            const int piv = sh_piv < K ? sh_piv : col;
             if (piv != col) {
                 for (int q = tid; q < K; q += blockDim.x) {
                     double t = Mt[col * kLd + q];
@@ -228,23 +259,32 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
                 }
                 __syncthreads();
             }
-            for (int r = col + 1 + tid; r < K; r += blockDim.x)
-                mult[r] = Mt[r * kLd + col] / Mt[col * kLd + col];
-            __syncthreads();
+            const double dinv = 1.0 / Mt[col * kLd + col];
             const int rows = K - col - 1;
-            for (int e = tid; e < rows * K; e += blockDim.x) {
-                const int r = col + 1 + e / K, q = e % K;
-                const double l = mult[r];
-                if (q > col) Mt[r * kLd + q] -= l * Mt[col * kLd + q];
-                R[r * kLd + q] -= l * R[col * kLd + q];
+            // rank-1 update of the trailing rows of M (columns > col) and R
+            const int width = (K - col - 1) + K;
+            for (int e = tid; e < rows * width; e += blockDim.x) {
+                const int r = col + 1 + e / width, q = e % width;
+                const double l = Mt[r * kLd + col] * dinv;
+                if (q < K - col - 1) {
+                    const int qq = col + 1 + q;
+                    Mt[r * kLd + qq] -= l * Mt[col * kLd + qq];
+                } else {
+                    const int qq = q - (K - col - 1);
+                    R[r * kLd + qq] -= l * R[col * kLd + qq];
+                }
             }
             __syncthreads();
         }
+        // back substitution, column-oriented: X(r,:) = R(r,:)/M(r,r), then
+        // R(i,:) -= M(i,r) X(r,:) for i < r
         for (int r = K - 1; r >= 0; --r) {
-            for (int q = tid; q < K; q += blockDim.x) {
-                double acc = R[r * kLd + q];
-                for (int cc = r + 1; cc < K; ++cc) acc -= Mt[r * kLd + cc] * R[cc * kLd + q];
-                R[r * kLd + q] = acc / Mt[r * kLd + r];
+            const double dinv = 1.0 / Mt[r * kLd + r];
+            for (int q = tid; q < K; q += blockDim.x) R[r * kLd + q] *= dinv;
+            __syncthreads();
+            for (int e = tid; e < r * K; e += blockDim.x) {
+                const int i = e / K, q = e % K;
+                R[i * kLd + q] -= Mt[i * kLd + r] * R[r * kLd + q];
             }
             __syncthreads();
         }
@@ -359,7 +399,7 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
 
 }  // namespace
 
-void launch_controller(PhiCtl *ctl, const CtlArgs &a, double * /*scratch*/, hipStream_t s) {
+void launch_controller(PhiCtl *ctl, const CtlArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_controller, dim3(1), dim3(kBlock), 0, s, ctl, a);
 }
 

@@ -83,7 +83,7 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
         for (int s = 0; s < d; ++s) ex += excess(xi, CRN(i, (s + d - 1) % d), CRN(i, s));
         const double area = R * R * ex;
         for (int s = 0; s < 6; ++s) {
-            const size_t k = (size_t)s * n + i;
+            const size_t k = 6 * (size_t)i + s;     // cell-major: the 6 slots of a cell are contiguous
             if (s >= d) {                      // pentagon padding: self, zero weights
                 geo.nbr[k] = (int32_t)i;
                 continue;

@@ -1,7 +1,9 @@
 // Vector kernels of phipm_simul_iom2 (Alg. 1): the IOM2 two-term update
 // with the norm that yields h_{j+1,j}, the w_j recurrence when no product is
-// needed, the substep combination y_{k+1} (eq. 3.17) and stage linear
-// combinations of the schemes.  All reductions are deterministic.
+// needed, the substep combination y_{k+1} (eq. 3.17), input norms, and stage
+// linear combinations of the schemes.  Reductions are deterministic
+// (partials summed in block order by the consuming kernel).
+#include "column.h"
 #include "reduce.h"
 #include "xrb_internal.h"
 
@@ -9,10 +11,12 @@ namespace xrb {
 
 namespace {
 
-inline int grid_capped(int n) {
+constexpr int kRedBlock = 512;   // threads per block of the element-wise reducing kernels
+
+inline int grid_elems(int n) {
     int g = (n + kBlock - 1) / kBlock;
     if (g < 1) g = 1;
-    return g > kMaxBlocks ? kMaxBlocks : g;
+    return g > 4096 ? 4096 : g;
 }
 
 constexpr int kMaxLin = 6;
@@ -40,10 +44,9 @@ struct LinDevArgs {
 };
 
 template <bool NORM>
-__global__ void __launch_bounds__(kBlock) k_lincomb_dev(int n4, double *__restrict__ out,
-                                                        LinDevArgs a, PhiCtl *ctl,
-                                                        double *partials) {
-    __shared__ double lds[8];
+__global__ void __launch_bounds__(kRedBlock) k_lincomb_dev(int n4, double *__restrict__ out,
+                                                           LinDevArgs a, double *nrm_out) {
+    __shared__ double lds[16];
     double c[kPmax + 1];
 #pragma unroll
     for (int k = 0; k <= kPmax; ++k) c[k] = (k < a.k) ? *a.coef[k] : 0.0;
@@ -58,59 +61,46 @@ __global__ void __launch_bounds__(kBlock) k_lincomb_dev(int n4, double *__restri
     }
     if (!NORM) return;
     double v[1] = {r};
-    block_sum<1>(v, lds);
-    if (!grid_arrive<1>(v, partials, &ctl->counters[1])) return;
-    double tot[1];
-    grid_finish<1>(tot, partials, &ctl->counters[1], lds);
-    if (threadIdx.x == 0) {
-        const double beta = sqrt(tot[0]);
-        ctl->beta = beta;
-        ctl->beta_zero = (beta == 0.0) ? 1 : 0;
-        ctl->sigma[0] = beta > 0.0 ? 1.0 / beta : 0.0;
-        ctl->brk = 0;
-    }
+    block_sum_all<1>(v, lds);
+    put_partials<1>(v, nrm_out);
 }
 
 // IOM2 update of column j (classical two-term Gram-Schmidt) and its norm.
-__global__ void __launch_bounds__(kBlock) k_iom2_update(int n4, int j, double *__restrict__ w,
-                                                        const double *__restrict__ rj,
-                                                        const double *__restrict__ rjm1,
-                                                        PhiCtl *ctl, double *partials) {
-    __shared__ double lds[8];
-    if (ctl->brk != 0 || ctl->beta_zero) return;
-    const double cj = ctl->H[j * kMmax + j] * ctl->sigma[j];
-    const double cm = (j > 0) ? ctl->H[(j - 1) * kMmax + j] * ctl->sigma[j - 1] : 0.0;
+__global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double *__restrict__ w,
+                                                           const double *__restrict__ rj,
+                                                           const double *__restrict__ rjm1,
+                                                           PhiCtl *ctl, const double *nrm_in,
+                                                           int np_nrm, const double *dot_in,
+                                                           int np_dot, double *nrm_out) {
+    __shared__ double lds[64];
+    // a new basis (j = 0) starts fresh; later columns stop after a breakdown
+    if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
+    double nn[1], dd[2];
+    sum_partials<1>(nn, nrm_in, np_nrm, lds);
+    sum_partials<2>(dd, dot_in, np_dot, lds);
+    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
+    const ColumnScale cs = finalize_column(ctl, j, nn[0], writer, lds);
+    if (cs.stop) return;
+    const double sj = cs.sigma;
+    const double sm = j > 0 ? ctl->sigma[j - 1] : 0.0;
+    const double hjj = sj * sj * dd[0];
+    const double hmj = j > 0 ? sj * sm * dd[1] : 0.0;
+    if (writer) {
+        ctl->H[j * kMmax + j] = hjj;
+        if (j > 0) ctl->H[(j - 1) * kMmax + j] = hmj;
+    }
+    const double cj = hjj * sj;
+    const double cm = hmj * sm;
     double r = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
-        double x = w[i] - cj * rj[i];
+        double x = sj * w[i] - cj * rj[i];
         if (j > 0) x -= cm * rjm1[i];
         w[i] = x;
         r += x * x;
     }
     double v[1] = {r};
-    block_sum<1>(v, lds);
-    if (!grid_arrive<1>(v, partials, &ctl->counters[2])) return;
-    double tot[1];
-    grid_finish<1>(tot, partials, &ctl->counters[2], lds);
-    if (threadIdx.x == 0) {
-        const double hn = sqrt(tot[0]);
-        if (hn != hn) ctl->dec.status = XRB_ENAN;
-        // breakdown when h_{j+1,j} <= 1e-14 * ||H_j||_1 (square leading block)
-        double bn = 0.0;
-        for (int c = 0; c <= j; ++c) {
-            double cs = 0.0;
-            for (int rr = 0; rr <= j; ++rr) cs += fabs(ctl->H[rr * kMmax + c]);
-            bn = cs > bn ? cs : bn;
-        }
-        if (!(hn > 1e-14 * bn)) {
-            ctl->H[(j + 1) * kMmax + j] = 0.0;
-            ctl->sigma[j + 1] = 0.0;
-            ctl->brk = j + 1;
-        } else {
-            ctl->H[(j + 1) * kMmax + j] = hn;
-            ctl->sigma[j + 1] = 1.0 / hn;
-        }
-    }
+    block_sum_all<1>(v, lds);
+    put_partials<1>(v, nrm_out);
 }
 
 struct CombArgs {
@@ -135,27 +125,45 @@ __global__ void __launch_bounds__(kBlock) k_combine(int n4, double *__restrict__
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm2(int n4, const double *__restrict__ x,
-                                                  double *out, double *partials,
-                                                  uint32_t *counter) {
-    __shared__ double lds[8];
-    double r = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x)
-        r += x[i] * x[i];
-    double v[1] = {r};
-    block_sum<1>(v, lds);
-    if (!grid_arrive<1>(v, partials, counter)) return;
-    double tot[1];
-    grid_finish<1>(tot, partials, counter, lds);
-    if (threadIdx.x == 0) *out = tot[0];
+struct NormArgs {
+    int nv;
+    const double *vec[kPmax + 1];
+};
+
+__global__ void __launch_bounds__(kRedBlock) k_norms(int n4, NormArgs a, double *parts) {
+    __shared__ double lds[16 * (kPmax + 1)];
+    double r[kPmax + 1];
+#pragma unroll
+    for (int k = 0; k <= kPmax; ++k) r[k] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k <= kPmax; ++k) {
+            if (k < a.nv) {
+                const double v = a.vec[k][i];
+                r[k] += v * v;
+            }
+        }
+    }
+    block_sum_all<kPmax + 1>(r, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < a.nv; ++k) parts[blockIdx.x * a.nv + k] = r[k];
 }
 
-__global__ void k_phi_init(PhiCtl *c, int m0, double tau0, double tol_rel, const double *vn2,
-                           int nv) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(kBlock) k_phi_init(PhiCtl *c, int m0, double tau0,
+                                                     double tol_rel, const double *parts, int np,
+                                                     int nv, double *vn2) {
+    __shared__ double lds[16 * (kPmax + 1)];
+    double tot[kPmax + 1];
+#pragma unroll
+    for (int k = 0; k <= kPmax; ++k) tot[k] = 0.0;
+    for (int b = threadIdx.x; b < np; b += blockDim.x)
+        for (int k = 0; k < nv; ++k) tot[k] += parts[b * nv + k];
+    block_sum_all<kPmax + 1>(tot, lds);
+    if (threadIdx.x != 0) return;
     double s = 0.0;
     for (int k = 0; k < nv; ++k) {
-        double r = sqrt(vn2[k]);
+        vn2[k] = tot[k];
+        const double r = sqrt(tot[k]);
         s = r > s ? r : s;
     }
     c->tol_abs = tol_rel * s;
@@ -189,30 +197,36 @@ void launch_lincomb(int n4, double *out, int k, const double *const *vec, const 
         a.vec[i] = vec[i];
         a.c[i] = c[i];
     }
-    hipLaunchKernelGGL(k_lincomb, dim3(grid_capped(n4)), dim3(kBlock), 0, s, n4, out, a);
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_elems(n4)), dim3(kBlock), 0, s, n4, out, a);
 }
 
-void launch_lincomb_dev(int n4, double *out, int k, const double *const *vec,
-                        const double *const *coef, PhiCtl *ctl, double *partials, int norm,
-                        hipStream_t s) {
+int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
+                       const double *const *coef, double *nrm_out, hipStream_t s) {
     LinDevArgs a{};
     a.k = k;
     for (int i = 0; i < k && i <= kPmax; ++i) {
         a.vec[i] = vec[i];
         a.coef[i] = coef[i];
     }
-    if (norm)
-        hipLaunchKernelGGL(k_lincomb_dev<true>, dim3(grid_capped(n4)), dim3(kBlock), 0, s, n4,
-                           out, a, ctl, partials);
+    const int n4 = 4 * n;
+    const int grid = red_grid(n4, kRedBlock);
+    if (nrm_out)
+        hipLaunchKernelGGL(k_lincomb_dev<true>, dim3(grid), dim3(kRedBlock), 0, s, n4, out, a,
+                           nrm_out);
     else
-        hipLaunchKernelGGL(k_lincomb_dev<false>, dim3(grid_capped(n4)), dim3(kBlock), 0, s, n4,
-                           out, a, ctl, partials);
+        hipLaunchKernelGGL(k_lincomb_dev<false>, dim3(grid), dim3(kRedBlock), 0, s, n4, out, a,
+                           nrm_out);
+    return grid;
 }
 
-void launch_iom2_update(int n4, int j, double *rjp1, const double *rj, const double *rjm1,
-                        PhiCtl *ctl, double *partials, hipStream_t s) {
-    hipLaunchKernelGGL(k_iom2_update, dim3(grid_capped(n4)), dim3(kBlock), 0, s, n4, j, rjp1, rj,
-                       rjm1, ctl, partials);
+int launch_iom2_update(int n, int j, double *rjp1, const double *rj, const double *rjm1,
+                       PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
+                       int np_dot, double *nrm_out, hipStream_t s) {
+    const int n4 = 4 * n;
+    const int grid = red_grid(n4, kRedBlock);
+    hipLaunchKernelGGL(k_iom2_update, dim3(grid), dim3(kRedBlock), 0, s, n4, j, rjp1, rj, rjm1,
+                       ctl, nrm_in, np_nrm, dot_in, np_dot, nrm_out);
+    return grid;
 }
 
 void launch_combine(int n4, double *y, int p, const double *const *w, const int *wzero,
@@ -223,18 +237,22 @@ void launch_combine(int n4, double *y, int p, const double *const *w, const int 
     a.corr = corr;
     for (int j = 0; j < p; ++j) a.w[j] = wzero[j] ? nullptr : w[j];
     a.V = V;
-    hipLaunchKernelGGL(k_combine, dim3(grid_capped(n4)), dim3(kBlock), 0, s, n4, y, a, ctl);
+    hipLaunchKernelGGL(k_combine, dim3(grid_elems(n4)), dim3(kBlock), 0, s, n4, y, a, ctl);
 }
 
-void launch_norm2(int n4, const double *x, double *out, double *partials, uint32_t *counter,
-                  hipStream_t s) {
-    hipLaunchKernelGGL(k_norm2, dim3(grid_capped(n4)), dim3(kBlock), 0, s, n4, x, out, partials,
-                       counter);
+int launch_norms(int n, int nv, const double *const *vec, double *parts, hipStream_t s) {
+    NormArgs a{};
+    a.nv = nv;
+    for (int k = 0; k < nv && k <= kPmax; ++k) a.vec[k] = vec[k];
+    const int grid = red_grid(4 * n, kRedBlock);
+    hipLaunchKernelGGL(k_norms, dim3(grid), dim3(kRedBlock), 0, s, 4 * n, a, parts);
+    return grid;
 }
 
-void launch_phi_init(PhiCtl *ctl, int m0, double tau0, double tol_rel, const double *vnorm2,
-                     int nv, hipStream_t s) {
-    hipLaunchKernelGGL(k_phi_init, dim3(1), dim3(64), 0, s, ctl, m0, tau0, tol_rel, vnorm2, nv);
+void launch_phi_init(PhiCtl *ctl, int m0, double tau0, double tol_rel, const double *parts,
+                     int np, int nv, double *vnorm2_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_phi_init, dim3(1), dim3(kBlock), 0, s, ctl, m0, tau0, tol_rel, parts, np,
+                       nv, vnorm2_out);
 }
 
 void launch_set_tout(PhiCtl *ctl, double t_out, hipStream_t s) {

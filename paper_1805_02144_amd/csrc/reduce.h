@@ -1,11 +1,25 @@
-// Deterministic block and grid reductions (fixed summation order, no
-// floating-point atomics).  A grid reduction writes one partial per block;
-// the last block to arrive (integer ticket) sums the partials in block order.
+// Deterministic reductions without floating-point atomics or fences.
+//
+// A producing kernel writes one partial per block (fixed in-block order).
+// The consuming kernel -- the next one on the stream, so the kernel boundary
+// makes the partials visible -- sums them in block order; every block of the
+// consumer that needs the total computes it redundantly and bitwise
+// identically.  (A device-scope fence per block, the usual "last block"
+// pattern, costs an L2 write-back per block on a multi-XCD part.)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace xrb {
+
+constexpr int kRedBlocks = 512;    // cap on partials (blocks) per reduction
+
+// blocks of a reducing kernel over `items` work items, `block` per block
+inline int red_grid(int items, int block) {
+    int g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    return g > kRedBlocks ? kRedBlocks : g;
+}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -13,59 +27,46 @@ __device__ inline double wave_sum(double v) {
     return v;  // valid in lane 0
 }
 
-// Sums NV values over a 256-thread block; result valid in thread 0.
+// Sums NV values over the block (blockDim.x a multiple of 64, <= 1024);
+// the result is returned in every thread.  lds must hold 16*NV doubles.
 template <int NV>
-__device__ inline void block_sum(double (&v)[NV], double *lds /* >= 4*NV */) {
+__device__ inline void block_sum_all(double (&v)[NV], double *lds) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double s = wave_sum(v[k]);
         if (lane == 0) lds[wid * NV + k] = s;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
-            v[k] = ((lds[k] + lds[NV + k]) + lds[2 * NV + k]) + lds[3 * NV + k];
-    }
-}
-
-__device__ inline double load_coherent(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Publish this block's NV partials; returns true in every thread of the last
-// block to arrive (which then owns the final sum).  Thread 0 must hold the
-// block sums in v.
-template <int NV>
-__device__ inline bool grid_arrive(const double (&v)[NV], double *partials, uint32_t *counter) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) partials[blockIdx.x * NV + k] = v[k];
-        __threadfence();
-        uint32_t t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1);
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * NV + k];
+        v[k] = s;
     }
     __syncthreads();
-    if (last) __threadfence();
-    return last;
 }
 
-// In the last block: total[k] = sum_b partials[b*NV+k], summed by a fixed
-// tree (each thread a fixed strided slice, then block_sum).  Result in
-// thread 0.  Resets the ticket counter.
+// Write this block's partials (thread 0 after block_sum_all).
 template <int NV>
-__device__ inline void grid_finish(double (&tot)[NV], const double *partials, uint32_t *counter,
-                                   double *lds) {
+__device__ inline void put_partials(const double (&v)[NV], double *parts) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
+    }
+}
+
+// Total of partials written by a previous kernel: fixed strided slices per
+// thread, then block_sum_all.  Result in every thread.
+template <int NV>
+__device__ inline void sum_partials(double (&tot)[NV], const double *parts, int np, double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) tot[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+    for (int b = threadIdx.x; b < np; b += blockDim.x)
 #pragma unroll
-        for (int k = 0; k < NV; ++k) tot[k] += load_coherent(partials + b * NV + k);
-    __syncthreads();
-    block_sum<NV>(tot, lds);
-    if (threadIdx.x == 0) *counter = 0u;
+        for (int k = 0; k < NV; ++k) tot[k] += parts[b * NV + k];
+    block_sum_all<NV>(tot, lds);
 }
 
 }  // namespace xrb

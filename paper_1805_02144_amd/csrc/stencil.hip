@@ -2,9 +2,14 @@
 //   F(u)    eq. sweqsinv with D_f = -nu L^2 (eq. swdis)
 //   J(u) x  eqs. dynjs-dynjc, fused with the IOM2 dot products or the w_j
 //           recurrence axpys of Alg. 1
-// One thread per cell, neighbours gathered through the slot-major table.
-// The two-ring dissipation stencil L(L x) takes L x from a preceding
-// one-ring pass (launch_lap4).
+//
+// Edge-parallel mapping: eight consecutive lanes serve one cell, lane s < 6
+// handling the edge to neighbour slot s (lanes 6 and 7 carry zero weights).
+// Each lane gathers its neighbour, forms its edge terms, and a fixed xor
+// butterfly over the eight lanes sums them (bitwise identical in all eight).
+// This gives eight times the memory-level parallelism of one thread per
+// cell, which the small grids need.  The two-ring dissipation stencil
+// L(L x) takes L x from a preceding one-ring pass (launch_lap4).
 #include "reduce.h"
 #include "xrb_internal.h"
 
@@ -12,226 +17,198 @@ namespace xrb {
 
 namespace {
 
-inline int grid_for(int n) {
-    int g = (n + kBlock - 1) / kBlock;
+constexpr int kLanes = 8;
+
+inline int cells_grid(int n, int block) {
+    const int cpb = block / kLanes;
+    int g = (n + cpb - 1) / cpb;
     return g < 1 ? 1 : g;
 }
-inline int grid_capped(int n) {
-    int g = grid_for(n);
-    return g > kMaxBlocks ? kMaxBlocks : g;
+
+__device__ inline double grp_sum(double v) {
+    v += __shfl_xor(v, 1, kLanes);
+    v += __shfl_xor(v, 2, kLanes);
+    v += __shfl_xor(v, 4, kLanes);
+    return v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_lap4(DevMesh M, const double *__restrict__ psi,
-                                                 double *__restrict__ out) {
+// first cell of this thread's group and the stride, in cells
+__device__ inline int cell0() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) / kLanes); }
+__device__ inline int cell_stride() { return (int)((gridDim.x * blockDim.x) / kLanes); }
+
+__global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restrict__ psi,
+                                              double *__restrict__ out) {
     const int n = M.n;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double p0 = psi[i], p1 = psi[n + i], p2 = psi[2 * n + i], p3 = psi[3 * n + i];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int s = threadIdx.x & (kLanes - 1);
+    for (int i = cell0(); i < n; i += cell_stride()) {
+        const int e = 6 * i + (s < 6 ? s : 0);
+        const int j = s < 6 ? M.nbr[e] : i;
+        const double c = s < 6 ? M.cl[e] : 0.0;
+        double a[4];
 #pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const int j = M.nbr[s * n + i];
-        const double c = M.cl[s * n + i];
-        a0 += c * (psi[j] - p0);
-        a1 += c * (psi[n + j] - p1);
-        a2 += c * (psi[2 * n + j] - p2);
-        a3 += c * (psi[3 * n + j] - p3);
+        for (int b = 0; b < 4; ++b) a[b] = grp_sum(c * (psi[b * n + j] - psi[b * n + i]));
+        if (s < 4) out[s * n + i] = a[s];
     }
-    out[i] = a0;
-    out[n + i] = a1;
-    out[2 * n + i] = a2;
-    out[3 * n + i] = a3;
 }
 
-__global__ void __launch_bounds__(kBlock) k_linearize(DevMesh M, const double *__restrict__ u,
-                                                      double *__restrict__ eta) {
+__global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__restrict__ u,
+                                                   double *__restrict__ eta) {
     const int n = M.n;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double ux = u[i], uy = u[n + i], uz = u[2 * n + i];
-    double z = 0.0;
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const int j = M.nbr[s * n + i];
-        const int k = s * n + i;
-        z += M.bx[k] * (ux + u[j]) + M.by[k] * (uy + u[n + j]) + M.bz[k] * (uz + u[2 * n + j]);
+    const int s = threadIdx.x & (kLanes - 1);
+    for (int i = cell0(); i < n; i += cell_stride()) {
+        const int e = 6 * i + (s < 6 ? s : 0);
+        const int j = s < 6 ? M.nbr[e] : i;
+        double z = 0.0;
+        if (s < 6)
+            z = M.bx[e] * (u[i] + u[j]) + M.by[e] * (u[n + i] + u[n + j]) +
+                M.bz[e] * (u[2 * n + i] + u[2 * n + j]);
+        z = grp_sum(z);
+        if (s == 0) eta[i] = z + M.cor[i];
     }
-    eta[i] = z + M.cor[i];
 }
 
-__global__ void __launch_bounds__(kBlock) k_rhs(DevMesh M, const double *__restrict__ u,
-                                                const double *__restrict__ lu,
-                                                double *__restrict__ f) {
+__global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict__ u,
+                                             const double *__restrict__ lu,
+                                             double *__restrict__ f) {
     const int n = M.n;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const double g = M.g;
-    const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], h = u[3 * n + i];
-    const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * h;
-    const double l0 = lu[i], l1 = lu[n + i], l2 = lu[2 * n + i], l3 = lu[3 * n + i];
-    double gx = 0.0, gy = 0.0, gz = 0.0, dv = 0.0, zt = 0.0;
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const int j = M.nbr[s * n + i];
-        const int k = s * n + i;
+    const int s = threadIdx.x & (kLanes - 1);
+    for (int i = cell0(); i < n; i += cell_stride()) {
+        const bool edge = s < 6;
+        const int e = 6 * i + (edge ? s : 0);
+        const int j = edge ? M.nbr[e] : i;
+        const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], h = u[3 * n + i];
         const double vx = u[j], vy = u[n + j], vz = u[2 * n + j], hj = u[3 * n + j];
-        const double ax = M.ax[k], ay = M.ay[k], az = M.az[k];
+        const double ax = edge ? M.ax[e] : 0.0, ay = edge ? M.ay[e] : 0.0, az = edge ? M.az[e] : 0.0;
+        const double bx = edge ? M.bx[e] : 0.0, by = edge ? M.by[e] : 0.0, bz = edge ? M.bz[e] : 0.0;
+        const double c = edge ? M.cl[e] : 0.0;
+        const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * h;
         const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * hj;
         const double dE = Ej - Ei;
-        gx += ax * dE;
-        gy += ay * dE;
-        gz += az * dE;
-        dv += ax * (h * ux + hj * vx) + ay * (h * uy + hj * vy) + az * (h * uz + hj * vz);
-        zt += M.bx[k] * (ux + vx) + M.by[k] * (uy + vy) + M.bz[k] * (uz + vz);
-        const double c = M.cl[k];
-        d0 += c * (lu[j] - l0);
-        d1 += c * (lu[n + j] - l1);
-        d2 += c * (lu[2 * n + j] - l2);
-        d3 += c * (lu[3 * n + j] - l3);
+        const double gx = grp_sum(ax * dE), gy0 = grp_sum(ay * dE), gz0 = grp_sum(az * dE);
+        const double dv = grp_sum(ax * (h * ux + hj * vx) + ay * (h * uy + hj * vy) +
+                                  az * (h * uz + hj * vz));
+        const double zt = grp_sum(bx * (ux + vx) + by * (uy + vy) + bz * (uz + vz));
+        double d[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[b] = grp_sum(c * (lu[b * n + j] - lu[b * n + i]));
+        const double nx = M.nx[i], ny = M.ny[i], nz = M.nz[i];
+        const double gr = nx * gx + ny * gy0 + nz * gz0;       // tangent projection of grad E
+        const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
+        const double eta = zt + M.cor[i];
+        const double px = ny * uz - nz * uy, py = nz * ux - nx * uz, pz = nx * uy - ny * ux;
+        const double nu = M.nu;
+        double o[4];
+        o[0] = -eta * px - Gx - nu * d[0];
+        o[1] = -eta * py - Gy - nu * d[1];
+        o[2] = -eta * pz - Gz - nu * d[2];
+        o[3] = -dv - nu * d[3];
+        if (s < 4) f[s * n + i] = o[s];
     }
-    const double nx = M.nx[i], ny = M.ny[i], nz = M.nz[i];
-    const double gr = nx * gx + ny * gy + nz * gz;       // tangent projection of grad E
-    gx -= gr * nx;
-    gy -= gr * ny;
-    gz -= gr * nz;
-    const double eta = zt + M.cor[i];
-    const double px = ny * uz - nz * uy, py = nz * ux - nx * uz, pz = nx * uy - ny * ux;
-    const double nu = M.nu;
-    f[i] = -eta * px - gx - nu * d0;
-    f[n + i] = -eta * py - gy - nu * d1;
-    f[2 * n + i] = -eta * pz - gz - nu * d2;
-    f[3 * n + i] = -dv - nu * d3;
 }
 
-// out = dt*scale*J(u) x + sum_k c_k v_k, with optional reduction epilogue.
+// out = dt*J(u) x + sum_k c_k v_k, with an optional reduction epilogue
+// (IOM2: raw dot partials; recurrence: norm partials).
 template <int EPI>
-__global__ void __launch_bounds__(kBlock) k_jv(DevMesh M, JvArgs a) {
-    __shared__ double lds[16];
-    if (EPI == kEpiIom2) {
-        if (a.ctl->brk != 0 || a.ctl->beta_zero) return;
-    }
+__global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a) {
+    __shared__ double lds[64];
     const int n = M.n;
-    const double g = M.g, nu = M.nu;
-    const double sc = a.dt * (a.scale_ptr ? *a.scale_ptr : 1.0);
+    const double g = M.g, nu = M.nu, sc = a.dt;
+    const int s = threadIdx.x & (kLanes - 1);
     double cax[kPmax];
 #pragma unroll
     for (int k = 0; k < kPmax; ++k) cax[k] = (k < a.naxpy) ? *a.axc[k] : 0.0;
     const double *__restrict__ u = a.u;
     const double *__restrict__ x = a.x;
     const double *__restrict__ lx = a.lx;
-    double r0 = 0.0, r1 = 0.0;   // reduction partials
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double r0 = 0.0, r1 = 0.0;   // this lane's reduction partials
+    for (int i = cell0(); i < n; i += cell_stride()) {
+        const bool edge = s < 6;
+        const int e = 6 * i + (edge ? s : 0);
+        const int j = edge ? M.nbr[e] : i;
         const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], uh = u[3 * n + i];
         const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
-        const double l0 = lx[i], l1 = lx[n + i], l2 = lx[2 * n + i], l3 = lx[3 * n + i];
+        const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
+        const double wx = u[j], wy = u[n + j], wz = u[2 * n + j], wh = u[3 * n + j];
+        const double ax = edge ? M.ax[e] : 0.0, ay = edge ? M.ay[e] : 0.0, az = edge ? M.az[e] : 0.0;
+        const double bx = edge ? M.bx[e] : 0.0, by = edge ? M.by[e] : 0.0, bz = edge ? M.bz[e] : 0.0;
+        const double c = edge ? M.cl[e] : 0.0;
         const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
+        const double sj = wx * vx + wy * vy + wz * vz + g * vh;
+        const double ds = sj - si;
         const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
-        double gx = 0.0, gy = 0.0, gz = 0.0, dv = 0.0, zt = 0.0;
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        const double gx = grp_sum(ax * ds), gy0 = grp_sum(ay * ds), gz0 = grp_sum(az * ds);
+        const double dv = grp_sum(ax * (fx + (wh * vx + vh * wx)) + ay * (fy + (wh * vy + vh * wy)) +
+                                  az * (fz + (wh * vz + vh * wz)));
+        const double zt = grp_sum(bx * (xx + vx) + by * (xy + vy) + bz * (xz + vz));
+        double d[4];
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            const int j = M.nbr[s * n + i];
-            const int k = s * n + i;
-            const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
-            const double wx = u[j], wy = u[n + j], wz = u[2 * n + j], wh = u[3 * n + j];
-            const double ax = M.ax[k], ay = M.ay[k], az = M.az[k];
-            const double sj = wx * vx + wy * vy + wz * vz + g * vh;
-            const double ds = sj - si;
-            gx += ax * ds;
-            gy += ay * ds;
-            gz += az * ds;
-            dv += ax * (fx + (wh * vx + vh * wx)) + ay * (fy + (wh * vy + vh * wy)) +
-                  az * (fz + (wh * vz + vh * wz));
-            zt += M.bx[k] * (xx + vx) + M.by[k] * (xy + vy) + M.bz[k] * (xz + vz);
-            const double c = M.cl[k];
-            d0 += c * (lx[j] - l0);
-            d1 += c * (lx[n + j] - l1);
-            d2 += c * (lx[2 * n + j] - l2);
-            d3 += c * (lx[3 * n + j] - l3);
-        }
+        for (int b = 0; b < 4; ++b) d[b] = grp_sum(c * (lx[b * n + j] - lx[b * n + i]));
         const double nx = M.nx[i], ny = M.ny[i], nz = M.nz[i];
-        const double gr = nx * gx + ny * gy + nz * gz;
-        gx -= gr * nx;
-        gy -= gr * ny;
-        gz -= gr * nz;
+        const double gr = nx * gx + ny * gy0 + nz * gz0;
+        const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
         const double eta = a.eta[i];
-        // J_v x: -(V.x) (n x u);  J_r x: -eta (n x x) - nu L^2 x;  J_m x: -G(u.x + g x_h), -D(h x + x_h u)
+        // J_v x: -(V.x) (n x u);  J_r x: -eta (n x x) - nu L^2 x;
+        // J_m x: -G(u.x + g x_h), -D(h x + x_h u)
         const double pux = ny * uz - nz * uy, puy = nz * ux - nx * uz, puz = nx * uy - ny * ux;
         const double pxx = ny * xz - nz * xy, pxy = nz * xx - nx * xz, pxz = nx * xy - ny * xx;
-        double o0 = sc * (-zt * pux - eta * pxx - gx - nu * d0);
-        double o1 = sc * (-zt * puy - eta * pxy - gy - nu * d1);
-        double o2 = sc * (-zt * puz - eta * pxz - gz - nu * d2);
-        double o3 = sc * (-dv - nu * d3);
+        double o[4];
+        o[0] = sc * (-zt * pux - eta * pxx - Gx - nu * d[0]);
+        o[1] = sc * (-zt * puy - eta * pxy - Gy - nu * d[1]);
+        o[2] = sc * (-zt * puz - eta * pxz - Gz - nu * d[2]);
+        o[3] = sc * (-dv - nu * d[3]);
+        if (s < 4) {
+            const int oi = s * n + i;
+            double ob = o[s];
 #pragma unroll
-        for (int k = 0; k < kPmax; ++k) {
-            if (k < a.naxpy) {
-                const double *v = a.axv[k];
-                o0 += cax[k] * v[i];
-                o1 += cax[k] * v[n + i];
-                o2 += cax[k] * v[2 * n + i];
-                o3 += cax[k] * v[3 * n + i];
+            for (int k = 0; k < kPmax; ++k)
+                if (k < a.naxpy) ob += cax[k] * a.axv[k][oi];
+            a.out[oi] = ob;
+            if (EPI == kEpiIom2) {
+                const double xs = s == 0 ? xx : (s == 1 ? xy : (s == 2 ? xz : xh));
+                r0 += ob * xs;
+                if (a.rjm1) r1 += ob * a.rjm1[oi];
+            } else if (EPI == kEpiNorm) {
+                r0 += ob * ob;
             }
-        }
-        a.out[i] = o0;
-        a.out[n + i] = o1;
-        a.out[2 * n + i] = o2;
-        a.out[3 * n + i] = o3;
-        if (EPI == kEpiIom2) {
-            const double *rj = a.rj;
-            r0 += o0 * rj[i] + o1 * rj[n + i] + o2 * rj[2 * n + i] + o3 * rj[3 * n + i];
-            if (a.rjm1) {
-                const double *rm = a.rjm1;
-                r1 += o0 * rm[i] + o1 * rm[n + i] + o2 * rm[2 * n + i] + o3 * rm[3 * n + i];
-            }
-        } else if (EPI == kEpiNorm) {
-            r0 += o0 * o0 + o1 * o1 + o2 * o2 + o3 * o3;
         }
     }
-    if (EPI == kEpiNone) return;
-    double v[2] = {r0, r1};
-    block_sum<2>(v, lds);
-    uint32_t *ctr = &a.ctl->counters[EPI == kEpiIom2 ? 0 : 1];
-    if (!grid_arrive<2>(v, a.partials, ctr)) return;
-    double tot[2];
-    grid_finish<2>(tot, a.partials, ctr, lds);
-    if (threadIdx.x == 0) {
-        PhiCtl *c = a.ctl;
-        if (EPI == kEpiIom2) {
-            const int j = a.j;
-            c->H[j * kMmax + j] = c->sigma[j] * tot[0];
-            if (j > 0) c->H[(j - 1) * kMmax + j] = c->sigma[j - 1] * tot[1];
-        } else {
-            const double beta = sqrt(tot[0]);
-            c->beta = beta;
-            c->beta_zero = (beta == 0.0) ? 1 : 0;
-            c->sigma[0] = beta > 0.0 ? 1.0 / beta : 0.0;
-            c->brk = 0;
-        }
+    if (EPI == kEpiIom2) {
+        double v[2] = {r0, r1};
+        block_sum_all<2>(v, lds);
+        put_partials<2>(v, a.dot_out);
+    } else if (EPI == kEpiNorm) {
+        double v[1] = {r0};
+        block_sum_all<1>(v, lds);
+        put_partials<1>(v, a.nrm_out);
     }
 }
 
 }  // namespace
 
 void launch_lap4(const DevMesh &M, const double *psi, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_lap4, dim3(grid_for(M.n)), dim3(kBlock), 0, s, M, psi, out);
+    hipLaunchKernelGGL(k_lap4, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, psi, out);
 }
 
 void launch_linearize(const DevMesh &M, const double *u, double *eta, hipStream_t s) {
-    hipLaunchKernelGGL(k_linearize, dim3(grid_for(M.n)), dim3(kBlock), 0, s, M, u, eta);
+    hipLaunchKernelGGL(k_linearize, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, u, eta);
 }
 
 void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, hipStream_t s) {
-    hipLaunchKernelGGL(k_rhs, dim3(grid_for(M.n)), dim3(kBlock), 0, s, M, u, lu, f);
+    hipLaunchKernelGGL(k_rhs, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, u, lu, f);
 }
 
-void launch_jv(const DevMesh &M, const JvArgs &a, int epi, hipStream_t s) {
-    if (epi == kEpiNone)
-        hipLaunchKernelGGL(k_jv<kEpiNone>, dim3(grid_for(M.n)), dim3(kBlock), 0, s, M, a);
-    else if (epi == kEpiIom2)
-        hipLaunchKernelGGL(k_jv<kEpiIom2>, dim3(grid_capped(M.n)), dim3(kBlock), 0, s, M, a);
+int launch_jv(const DevMesh &M, const JvArgs &a, int epi, hipStream_t s) {
+    if (epi == kEpiNone) {
+        hipLaunchKernelGGL(k_jv<kEpiNone>, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, a);
+        return 0;
+    }
+    const int grid = red_grid(M.n * kLanes, 256);
+    if (epi == kEpiIom2)
+        hipLaunchKernelGGL(k_jv<kEpiIom2>, dim3(grid), dim3(256), 0, s, M, a);
     else
-        hipLaunchKernelGGL(k_jv<kEpiNorm>, dim3(grid_capped(M.n)), dim3(kBlock), 0, s, M, a);
+        hipLaunchKernelGGL(k_jv<kEpiNorm>, dim3(grid), dim3(256), 0, s, M, a);
+    return grid;
 }
 
 }  // namespace xrb

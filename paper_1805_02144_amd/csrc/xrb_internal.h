@@ -13,19 +13,19 @@ constexpr int kBlock = 256;                               // threads per block, 
 constexpr int kMmax = XRB_MMAX_LIMIT;                     // largest Krylov size
 constexpr int kPmax = XRB_PMAX;
 constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix order
-constexpr int kMaxBlocks = 2048;                          // cap of reduction blocks
 
-// Geometry of the finite-volume operators in slot-major layout ([slot][cell]),
-// so that consecutive threads (cells) read consecutive addresses.
+// Geometry of the finite-volume operators, cell-major ([cell][slot], 6
+// slots): the eight lanes that share a cell in the edge-parallel kernels read
+// one contiguous 48-byte record per array.
 //   a_s = l_e n_{e,i} / (2 A_i)   divergence and gradient weights (3 comps)
 //   b_s = l_e t_{e,i} / (2 A_i)   vorticity (circulation) weights (3 comps)
 //   c_s = l_e / (d_e A_i)         Laplacian weights
 struct DevMesh {
     int n = 0;
-    const int32_t *nbr = nullptr;                  // [6][n]
-    const double *ax = nullptr, *ay = nullptr, *az = nullptr;   // [6][n] each
+    const int32_t *nbr = nullptr;                  // [n][6]
+    const double *ax = nullptr, *ay = nullptr, *az = nullptr;   // [n][6] each
     const double *bx = nullptr, *by = nullptr, *bz = nullptr;
-    const double *cl = nullptr;                    // [6][n]
+    const double *cl = nullptr;                    // [n][6]
     const double *nx = nullptr, *ny = nullptr, *nz = nullptr;   // [n] cell normals
     const double *cor = nullptr;                   // [n] Coriolis 2 Omega sin(lat)
     double nu = 0.0, g = 0.0;
@@ -57,7 +57,6 @@ struct PhiCtl {
     double rec_coef[kPmax + 1];      // t^l / l! at the current point
     double ycoef[kPmax + kMmax + 2]; // combine coefficients of an accepted attempt
     Decision dec;
-    uint32_t counters[8];            // last-block reduction tickets
 };
 
 // Replay entry or sentinel passed to the controller kernel.
@@ -69,6 +68,10 @@ struct ReplayIn {
 };
 
 // ---------------- kernel launchers (stream-ordered) ----------------
+// Reductions: a reducing kernel writes one partial per block and its
+// launcher returns the block count; the next kernel that needs the total
+// sums those partials (see reduce.h).
+
 // out = L psi (4 components), raw input
 void launch_lap4(const DevMesh &M, const double *psi, double *out, hipStream_t s);
 // eta = V.u + f
@@ -77,44 +80,54 @@ void launch_linearize(const DevMesh &M, const double *u, double *eta, hipStream_
 void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, hipStream_t s);
 
 // Generic Jacobian product
-//   out = dt * scale * J(u) x  +  sum_k coef[k] * ax_vec[k]
-// where scale = (scale_ptr ? *scale_ptr : 1), coef[k] = *coef_ptr[k]
-// Epilogues: kDotIom2 -> partial dots <out, sigma_j R_j>, <out, sigma_{j-1} R_{j-1}>,
-//            finalised into H by the last block; kNorm -> ||out|| into beta/sigma[0].
+//   out = dt * J(u) x  +  sum_k coef[k] * axv[k]
+// kEpiNone : plain.
+// kEpiNorm : partials of ||out||^2 into nrm_out.
+// kEpiIom2 : column j of IOM2 on the raw basis vector x = R_j: partials of
+//            <out, R_j> and <out, R_{j-1}> into dot_out (the scales are
+//            applied by the IOM2 update that follows).
 enum JvEpi { kEpiNone = 0, kEpiIom2 = 1, kEpiNorm = 2 };
 struct JvArgs {
     const double *u = nullptr;      // linearisation state
     const double *eta = nullptr;    // V.u + f
     const double *x = nullptr;      // direction (raw)
     const double *lx = nullptr;     // L x (raw)
-    const double *scale_ptr = nullptr;
     double dt = 1.0;
     double *out = nullptr;
     int naxpy = 0;
     const double *axv[kPmax] = {};
     const double *axc[kPmax] = {};  // device pointers to coefficients
-    // IOM2 epilogue
-    int j = 0;                      // Krylov column being built
-    const double *rj = nullptr, *rjm1 = nullptr;
+    // IOM2
+    int j = 0;
+    const double *rjm1 = nullptr;
     PhiCtl *ctl = nullptr;
-    double *partials = nullptr;
+    double *dot_out = nullptr;
+    double *nrm_out = nullptr;
 };
-void launch_jv(const DevMesh &M, const JvArgs &a, int epi, hipStream_t s);
+int launch_jv(const DevMesh &M, const JvArgs &a, int epi, hipStream_t s);
 
-// out = sum_k coef[k] * vec[k] (device coefficient pointers), optional norm epilogue
-void launch_lincomb_dev(int n4, double *out, int k, const double *const *vec,
-                        const double *const *coef, PhiCtl *ctl, double *partials, int norm,
-                        hipStream_t s);
-// out = sum_k c[k] * vec[k], host coefficients (k <= 6)
+// out = sum_k coef[k] * vec[k] (device coefficient pointers); nrm_out
+// (nullable) receives partials of ||out||^2
+int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
+                       const double *const *coef, double *nrm_out, hipStream_t s);
+// out = sum_k c[k] * vec[k], host coefficients (k <= 6), length n4
 void launch_lincomb(int n4, double *out, int k, const double *const *vec, const double *c,
                     hipStream_t s);
-// IOM2 update of column j: R_{j+1} -= H[j][j] sigma_j R_j + H[j-1][j] sigma_{j-1} R_{j-1};
-// h_{j+1,j} = ||R_{j+1}||, sigma_{j+1} = 1/h, breakdown test
-void launch_iom2_update(int n4, int j, double *rjp1, const double *rj, const double *rjm1,
-                        PhiCtl *ctl, double *partials, hipStream_t s);
+// IOM2 update of column j.  Prologue: finalise the column scale sigma_j from
+// the norm partials of R_j (beta for j = 0, else h_{j,j-1} with the
+// breakdown test), then H[j][j] = sigma_j^2 <w, R_j>, H[j-1][j] =
+// sigma_j sigma_{j-1} <w, R_{j-1}> from the dot partials.  Body:
+// R_{j+1} = sigma_j w - H[j][j] sigma_j R_j - H[j-1][j] sigma_{j-1} R_{j-1}
+// (w = dt J R_j is stored in the R_{j+1} slot), norm partials to nrm_out.
+// nrm_in and nrm_out are different buffers (ping-pong).
+int launch_iom2_update(int n, int j, double *rjp1, const double *rj, const double *rjm1,
+                       PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
+                       int np_dot, double *nrm_out, hipStream_t s);
 // y = sum_{j<p, !wzero} ycoef[j] w_j + sum_{k<meff} ycoef[p+k] R_k + ycoef[p+meff] R_meff
 void launch_combine(int n4, double *y, int p, const double *const *w, const int *wzero,
                     const double *V, int meff, int corr, PhiCtl *ctl, hipStream_t s);
+// partials of ||vec_k||^2, k < nv (<= kPmax+1), into parts[b*nv + k]
+int launch_norms(int n, int nv, const double *const *vec, double *parts, hipStream_t s);
 
 struct CtlArgs {
     int m;                // Krylov size requested for this attempt
@@ -122,28 +135,29 @@ struct CtlArgs {
     int mode;             // FREE / RECORD / REPLAY
     int m_max;
     int wp_zero;          // w_p is the zero vector (symbolic)
+    int built;            // IOM2 columns built at this point
     double n4;            // vector length (cost model)
     double delta, gamma;
     ReplayIn rep;
+    const double *nrm_in; // partials of the last column's norm
+    int n_nrm_in;
 };
 // Small augmented-Hessenberg exponential + error estimate + (tau, m) controller
 // for the current attempt; writes ctl->dec and, on accept, the combine
 // coefficients and the next point's recurrence coefficients.
-void launch_controller(PhiCtl *ctl, const CtlArgs &a, double *scratch, hipStream_t s);
-// Initialise a call: t = 0, tau = rho_1, m, q, kappa, tol_abs (from ||v_l|| norms)
-void launch_phi_init(PhiCtl *ctl, int m0, double tau0, double tol_rel, const double *vnorm2,
-                     int nv, hipStream_t s);
+void launch_controller(PhiCtl *ctl, const CtlArgs &a, hipStream_t s);
+// Initialise a call: t = 0, tau = rho_1, m, q, kappa, tol_abs from the norm
+// partials of the nv input vectors; vnorm2_out[k] = ||v_k||^2
+void launch_phi_init(PhiCtl *ctl, int m0, double tau0, double tol_rel, const double *parts,
+                     int np, int nv, double *vnorm2_out, hipStream_t s);
 // Start a new output interval
 void launch_set_tout(PhiCtl *ctl, double t_out, hipStream_t s);
-// sum of squares of a vector into out[0] (deterministic, last-block)
-void launch_norm2(int n4, const double *x, double *out, double *partials, uint32_t *counter,
-                  hipStream_t s);
 
 // ---------------- host geometry ----------------
 struct HostGeometry {
     int n = 0;
-    std::vector<int32_t> nbr;                              // [6][n]
-    std::vector<double> ax, ay, az, bx, by, bz, cl;        // [6][n]
+    std::vector<int32_t> nbr;                              // [n][6]
+    std::vector<double> ax, ay, az, bx, by, bz, cl;        // [n][6]
     std::vector<double> nx, ny, nz, cor;                   // [n]
     double nu = 0.0;
 };

@@ -31,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # neighbour ids 24 + centre/area 32 = 160 B) plus the second dot's read of
 # v_{j-1} (32 B).
 JV_IOM2_BYTES_PER_CELL = 192.0
+# IOM2 update per cell: read w, v_j, v_{j-1}, write v_{j+1} (4 x 32 B)
+IOM2_BYTES_PER_CELL = 128.0
 STEPS_PER_METHOD = 24
 DT = 3600.0
 EVALS_PER_STEP = {"pexprb43": 2, "exprb53": 3}
@@ -51,6 +53,89 @@ def run_pass(ctx, u, u0, torch):
             evals += EVALS_PER_STEP[method]
             stats.append(ctx.step_stats())
     return evals, stats
+
+
+def ensemble_leg(X, torch, mesh, reps=3):
+    """64 level-6 members, exprb42, one step each: one batched launch sequence
+    against the per-member loop of single steps (member-steps/s)."""
+    import numpy as np
+    from synth import fields as F
+    U0, dts = F.ensemble_states(6, F.config_seed(3), 64)
+    ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
+    Ub0 = torch.tensor(U0, dtype=torch.float64, device="cuda:0")
+    Ub = Ub0.clone()
+    ctx.reset_history()
+    ctx.step_batch("exprb42", Ub, dts)          # warm-up (allocates the workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Ub.copy_(Ub0)
+        ctx.reset_history()
+        ctx.step_batch("exprb42", Ub, dts)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    u = torch.empty(Ub0.shape[1], dtype=torch.float64, device="cuda:0")
+    u.copy_(Ub0[0])
+    ctx.reset_history()
+    ctx.step("exprb42", u, float(dts[0]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for k in range(64):
+        u.copy_(Ub0[k])
+        ctx.reset_history()
+        ctx.step("exprb42", u, float(dts[k]))
+        if k == 63:
+            last = u.clone()
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    same = bool(torch.equal(last, Ub[63]))
+    ctx.close()
+    return {"workload": "64 members, level-6 grid, exprb42, one step each, dt from "
+                        "{600, 1200, 2400, 3600} s (seeded), FP64",
+            "batched_member_steps_per_s": 64 / tb, "loop_member_steps_per_s": 64 / tl,
+            "speedup": tl / tb, "batched_ms": 1e3 * tb, "loop_ms": 1e3 * tl,
+            "last_member_bitwise_equal": same,
+            "dt_mix": {str(int(d)): int((dts == d).sum()) for d in sorted(set(dts))}}
+
+
+def jet_leg(X, torch, event_every):
+    """Level-8 jet (N = 655362, n = 2621448): exprb53, 6 steps of 1800 s,
+    gamma_h = 1.25e-2 -- the bandwidth-bound roofline run of the Jacobian
+    product and the IOM2 update."""
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(8)
+    n = len(mesh["xyz"])
+    u0 = torch.tensor(F.initial_state("c3_l8_jet"), dtype=torch.float64, device="cuda:0")
+    ctx = X.Context(mesh, "cuda:0", gamma_h=1.25e-2, tol=1e-10, m_max=40)
+    u = u0.clone()
+    ctx.reset_history()
+    ctx.step("exprb53", u, 1800.0)              # warm-up
+    torch.cuda.synchronize()
+    u.copy_(u0)
+    ctx.reset_history()
+    ctx.profile(event_every)
+    t0 = time.perf_counter()
+    for _ in range(6):
+        ctx.step("exprb53", u, 1800.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_get()
+    ctx.profile(0)
+    ctx.close()
+    out = {"workload": "exprb53, 6 steps of 1800 s, level-8 jet + bump, N=655362, "
+                       "n=2621448, FP64, gamma_h 1.25e-2",
+           "phi_evals_per_s": 18 / el, "ms": 1e3 * el}
+    for name, bpc in (("jv_iom2", JV_IOM2_BYTES_PER_CELL), ("iom2_update", IOM2_BYTES_PER_CELL)):
+        ms, tn, an = prof[name]
+        avg = ms * 1e-3 / max(tn, 1)
+        ach = bpc * n / avg / 1e9 if tn else 0.0
+        out["roofline_" + name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                                   "avg_us": 1e6 * avg, "launches": an,
+                                   "bytes_per_cell": bpc}
+    return out
 
 
 def cpu_baseline(mesh, u0_host, steps):
@@ -88,6 +173,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-jet", action="store_true")
+    ap.add_argument("--jet-only", action="store_true",
+                    help="run only the level-8 leg (for profiling it alone)")
     ap.add_argument("--event-every", type=int, default=16,
                     help="time every N-th launch of each kernel with HIP events")
     args = ap.parse_args()
@@ -102,6 +191,10 @@ def main():
     import paper_1805_02144_amd as X
     from synth import fields as F
     from synth.mesh import get_mesh
+
+    if args.jet_only:
+        print(json.dumps({"level8_jet": jet_leg(X, torch, args.event_every)}))
+        return
 
     level = 6
     mesh = get_mesh(level)
@@ -153,6 +246,9 @@ def main():
                     agg[k] = agg.get(k, 0) + v
     per_pass = {k: v / args.steps for k, v in agg.items()}
 
+    ens = None if args.no_ensemble else ensemble_leg(X, torch, mesh)
+    jet = None if args.no_jet else jet_leg(X, torch, args.event_every)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(mesh, u0_host, args.cpu_steps)
@@ -178,6 +274,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "krylov_per_step": per_pass,
+        "ensemble": ens,
+        "level8_jet": jet,
         "device_time_fraction": (tot_ms * 1e-3) / elapsed,
     }
     print(json.dumps(out))

@@ -157,6 +157,22 @@ xrb_status xrb_phi_combo(xrb_ctx *ctx, double dt, const double *u, int p,
  * the first after xrb_reset_history, is an EPI2 step). */
 xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt);
 
+/* One step of `method` for nm independent ensemble members in one batched
+ * sequence of launches: every kernel covers all members, and the members'
+ * substep controllers (Alg. 1) advance in lockstep rounds, each with its own
+ * step size, Krylov sizes and substeps; a member that needs fewer Krylov
+ * columns or substeps skips the launches of the others.
+ *   U      device, nm x 4N, member-major (member k at U + 4N k), in place
+ *   dt     host [nm], positive step sizes
+ *   stats  optional host [nm][3] per-member, per-call-site statistics
+ * The ensemble keeps its own per-member warm starts and epi3 history; the
+ * first call with a given nm allocates an nm-member workspace (about
+ * nm (m_max + 28) 32 N bytes), a call with another nm replaces it.  Results
+ * equal those of xrb_step on each member alone (same kernels, same
+ * reduction order).  Replay scheduling is not available for ensembles. */
+xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, const double *dt,
+                          xrb_phi_stats *stats);
+
 /* Per-call-site statistics of the last xrb_step (3 entries). */
 xrb_status xrb_step_stats(const xrb_ctx *ctx, xrb_phi_stats *out3);
 

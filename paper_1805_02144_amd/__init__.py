@@ -22,7 +22,7 @@ PMAX = 4
 EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
            "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
-           "xrb_schedule_get", "xrb_profile", "xrb_profile_get"]
+           "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
@@ -75,6 +75,7 @@ def lib():
         L.xrb_phi_combo.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(vp), C.c_int, _dp,
                                     C.POINTER(vp), C.POINTER(PhiStats)]
         L.xrb_step.argtypes = [vp, C.c_int, vp, C.c_double]
+        L.xrb_step_batch.argtypes = [vp, C.c_int, C.c_int, vp, _dp, C.POINTER(PhiStats)]
         L.xrb_step_stats.argtypes = [vp, C.POINTER(PhiStats)]
         L.xrb_reset_history.argtypes = [vp]
         L.xrb_schedule_mode.argtypes = [vp, C.c_int]
@@ -207,6 +208,24 @@ class Context:
         mid = METHODS[method] if isinstance(method, str) else int(method)
         self._check(lib().xrb_step(self.h, mid, _ptr(u), float(dt)))
         return u
+
+    def step_batch(self, method, U, dts, return_stats=False):
+        """One step for every member of U (float64 device tensor [nm, 4N],
+        updated in place) with per-member step sizes dts."""
+        self._stream()
+        if not (U.is_contiguous() and U.dtype == self.torch.float64 and U.dim() == 2
+                and U.shape[1] == self.N and U.device == self.device):
+            raise ValueError("U must be a contiguous float64 [nm, 4N] tensor on the device")
+        nm = U.shape[0]
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        if d.shape != (nm,):
+            raise ValueError("one step size per member expected")
+        mid = METHODS[method] if isinstance(method, str) else int(method)
+        st = (PhiStats * (3 * nm))()
+        self._check(lib().xrb_step_batch(self.h, mid, nm, _ptr(U), d.ctypes.data_as(_dp), st))
+        if return_stats:
+            return U, [[st[3 * k + c].asdict() for c in range(3)] for k in range(nm)]
+        return U
 
     def step_stats(self):
         st = (PhiStats * 3)()

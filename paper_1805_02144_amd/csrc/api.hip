@@ -1,10 +1,15 @@
-// C ABI of libexprb: context, phipm_simul_iom2 driver (Alg. 1) and the
-// exponential Rosenbrock scheme drivers (Sec. 4.4).
+// C ABI of libexprb: context, the phipm_simul_iom2 driver (Alg. 1) and the
+// exponential Rosenbrock scheme drivers (Sec. 4.4), for one state or for a
+// batch of independent ensemble members.
 //
 // The substep loop of Alg. 1 runs on the host only as a launcher: every
 // arithmetic step (w_j recurrence, IOM2, augmented exponential, controller,
-// substep update) is a device kernel; the host reads back one small decision
-// record per attempt to know how many Krylov columns the next attempt needs.
+// substep update) is a device kernel.  Members advance in lockstep rounds --
+// one substep attempt per member per round -- and the host reads back one
+// small decision record per member and round to know how many Krylov
+// columns the next round needs.  A single state is the one-member case of
+// the same code, so batched and single results come from the same kernels
+// and the same reduction trees.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -15,11 +20,51 @@
 
 using namespace xrb;
 
+namespace {
+
 struct SchedEntry {
     double tau;
     int32_t m;
     int32_t flags;
 };
+
+// stage slots of the scheme drivers
+enum { S_FN, S_V, S_W1, S_W2, S_X1, S_X2, S_U2, S_U3, S_D2, S_D3, S_A3, S_A4, S_T1, S_T2,
+       S_UPREV, S_FPREV, S_STATE, S_COUNT };
+
+// Device workspace of nm members: member k's vectors sit at member 0's
+// address plus k * ws doubles.
+struct Work {
+    int nm = 0;
+    int64_t ws = 0;
+    double *base = nullptr;
+    double *V = nullptr;        // (m_max + 1) raw Krylov basis vectors
+    double *Wr = nullptr;       // w_1 .. w_{p-1} of the recurrence
+    double *y = nullptr;        // substep solution
+    double *lap = nullptr;      // L x scratch
+    double *eta = nullptr;      // V.u + f at the linearisation point
+    double *stage = nullptr;    // S_COUNT stage vectors
+    PhiCtl *ctl = nullptr;      // [nm]
+    double *dot_parts = nullptr, *nrm_parts = nullptr, *v_parts = nullptr, *vnorm2 = nullptr;
+    double *dtk = nullptr;      // [nm] step sizes
+    int32_t *plan = nullptr;    // [nm][kPlanW]
+    CtlArgs *cargs = nullptr;   // [nm]
+    int32_t *m0k = nullptr;     // [nm] warm starts
+    // pinned host mirrors
+    Decision *h_dec = nullptr;
+    int32_t *h_stage = nullptr;  // [2][nm][kPlanW] pinned staging of plan uploads
+    std::vector<int32_t> h_plan; // [nm][kPlanW] host working copy of the plan
+    CtlArgs *h_cargs = nullptr;
+    double *h_vn = nullptr;
+    double *h_dt = nullptr;
+    int32_t *h_m0 = nullptr;
+    // scheme state per member
+    std::vector<int> m_warm;    // [nm][3]
+    int have_prev = 0;
+    std::vector<xrb_phi_stats> stats;   // [nm][3]
+};
+
+}  // namespace
 
 struct xrb_ctx {
     xrb_params prm{};
@@ -27,26 +72,12 @@ struct xrb_ctx {
     hipStream_t stream = nullptr;
     DevMesh M{};
     void *geo_mem = nullptr;
-    double *V = nullptr;        // (m_max+1) raw basis vectors
-    double *W = nullptr;        // w_1..w_{p-1}
-    double *y = nullptr;
-    double *lap = nullptr;      // L x scratch
-    double *eta = nullptr;      // V.u + f at the current linearisation point
-    double *stage = nullptr;    // 16 stage vectors of the schemes
-    double *dot_parts = nullptr;   // IOM2 dot partials (2 per block)
-    double *nrm_parts = nullptr;   // norm partials, two buffers: column j uses buffer j % 2
-    double *v_parts = nullptr;     // norm partials of the phi_combo inputs
-    double *vnorm2 = nullptr;
-    PhiCtl *ctl = nullptr;
-    Decision *dec_host = nullptr;
-    double *vn_host = nullptr;
+    Work one;                   // single state
+    Work ens;                   // ensemble (allocated on first batched call)
     std::string err;
     int mode = XRB_FREE;
     std::vector<SchedEntry> sched;
     size_t sched_pos = 0;
-    int m_warm[3] = {0, 0, 0};
-    int have_prev = 0;
-    xrb_phi_stats last_stats[3]{};
     // optional per-kernel event timing
     struct Pending {
         int id;
@@ -58,8 +89,6 @@ struct xrb_ctx {
     std::vector<Pending> ev_pend;
     double prof_ms[XRB_K_COUNT] = {};
     int64_t prof_n[XRB_K_COUNT] = {};
-
-    double *sv(int k) { return stage + (size_t)k * n4; }
 };
 
 namespace {
@@ -89,7 +118,7 @@ hipEvent_t ev_get(xrb_ctx *ctx) {
     return e;
 }
 
-// Bracket a launch with events when profiling is on.
+// Bracket a launch with events when profiling samples it.
 template <class F>
 void timed(xrb_ctx *ctx, int id, F &&launch) {
     if (ctx->prof_every <= 0 || (ctx->prof_seen[id]++ % ctx->prof_every) != 0) {
@@ -121,30 +150,44 @@ void prof_drain(xrb_ctx *ctx) {
     ctx->ev_pend.clear();
 }
 
-// stage slots used by xrb_step
-enum { S_FN, S_V, S_W1, S_W2, S_X1, S_X2, S_U2, S_U3, S_D2, S_D3, S_A3, S_A4, S_T1, S_T2,
-       S_UPREV, S_FPREV, S_COUNT };
+Batch batch_of(const Work &W, const int32_t *plan = nullptr, int field = 0, int j = 0) {
+    Batch b;
+    b.nm = W.nm;
+    b.ws = W.ws;
+    b.dtk = W.dtk;
+    if (W.nm > 1) {
+        b.pred.plan = plan;
+        b.pred.field = field;
+        b.pred.j = j;
+    }
+    return b;
+}
 
-// J(u) x into out (kernel chain: L x, then the fused product); eta must hold V.u + f
-void jv_plain(xrb_ctx *ctx, const double *u, const double *x, double *out, double dt) {
-    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, x, ctx->lap, ctx->stream); });
+// J(u) x into out for every member (L x, then the product); eta must hold V.u + f
+void jv_plain(xrb_ctx *ctx, const Work &W, const double *u, const double *x, double *out,
+              bool scale_dt) {
+    Batch b = batch_of(W);
+    if (!scale_dt) b.dtk = nullptr;
+    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, x, W.lap, b, ctx->stream); });
     JvArgs a;
     a.u = u;
-    a.eta = ctx->eta;
+    a.eta = W.eta;
     a.x = x;
-    a.lx = ctx->lap;
-    a.dt = dt;
+    a.lx = W.lap;
+    a.dt = 1.0;
     a.out = out;
-    timed(ctx, XRB_K_JV_OTHER, [&] { launch_jv(ctx->M, a, kEpiNone, ctx->stream); });
+    timed(ctx, XRB_K_JV_OTHER, [&] { launch_jv(ctx->M, a, kEpiNone, b, ctx->stream); });
 }
 
-void rhs_plain(xrb_ctx *ctx, const double *u, double *f) {
-    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, u, ctx->lap, ctx->stream); });
-    timed(ctx, XRB_K_RHS, [&] { launch_rhs(ctx->M, u, ctx->lap, f, ctx->stream); });
+void rhs_plain(xrb_ctx *ctx, const Work &W, const double *u, double *f) {
+    const Batch b = batch_of(W);
+    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, u, W.lap, b, ctx->stream); });
+    timed(ctx, XRB_K_RHS, [&] { launch_rhs(ctx->M, u, W.lap, f, b, ctx->stream); });
 }
 
-void lincomb(xrb_ctx *ctx, double *out, std::initializer_list<const double *> vs,
-             std::initializer_list<double> cs) {
+// out = sum c_i v_i; bit i of dtmask multiplies c_i by the member's dt
+void lincomb(xrb_ctx *ctx, const Work &W, double *out, std::initializer_list<const double *> vs,
+             std::initializer_list<double> cs, unsigned dtmask = 0) {
     const double *vv[6];
     double cc[6];
     int k = 0;
@@ -154,15 +197,40 @@ void lincomb(xrb_ctx *ctx, double *out, std::initializer_list<const double *> vs
         cc[k] = *ci++;
         ++k;
     }
-    timed(ctx, XRB_K_VEC, [&] { launch_lincomb(ctx->n4, out, k, vv, cc, ctx->stream); });
+    const Batch b = batch_of(W);
+    timed(ctx, XRB_K_VEC, [&] { launch_lincomb(ctx->n4, out, k, vv, cc, dtmask, b, ctx->stream); });
 }
 
-// phipm_simul_iom2 with eta = V.u + f already computed for u.
-int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const *v, int ns,
-            const double *rho, double *const *w_out, int m_start, int *m_last,
-            xrb_phi_stats *st_out) {
+struct MemberPhi {
+    bool done = false;
+    bool zero_input = false;
+    bool ready = false;
+    bool y_zero = true;
+    int io = 0, built = 0, m = 1, wp_zero = 0;
+    int wzero[kPmax + 1] = {};
     xrb_phi_stats st{};
-    const int n4 = ctx->n4;
+};
+
+// Upload the plan through staging half `half`: half 0 before the IOM2
+// launches, half 1 after the decisions, so a staging buffer is never
+// rewritten while its asynchronous copy may still be pending (each half is
+// reused only after the next decision synchronisation).
+int upload_plan(xrb_ctx *ctx, Work &W, int half) {
+    if (W.nm <= 1) return XRB_OK;
+    int32_t *stg = W.h_stage + (size_t)half * kPlanW * W.nm;
+    std::memcpy(stg, W.h_plan.data(), sizeof(int32_t) * kPlanW * W.nm);
+    HIPCHK(hipMemcpyAsync(W.plan, stg, sizeof(int32_t) * kPlanW * W.nm, hipMemcpyHostToDevice,
+                          ctx->stream));
+    return XRB_OK;
+}
+
+// phipm_simul_iom2 for the nm members of W (lockstep rounds).  u, v, w_out
+// are member-0 pointers (member stride W.ws); dt of member k is W.dtk[k];
+// eta must hold V.u + f for every member.  m_warm[k*3 + site] holds the
+// warm start in and the last accepted Krylov size out (site < 0: cold start).
+int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const *v, int ns,
+              const double *rho, double *const *w_out, int site, xrb_phi_stats *st_out) {
+    const int nm = W.nm, n = ctx->n, n4 = ctx->n4;
     const hipStream_t s = ctx->stream;
     const xrb_params &P = ctx->prm;
     if (p < 0 || p > kPmax || ns < 1 || ns > 8 || !rho || !w_out || !v)
@@ -171,52 +239,117 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
         if (!(rho[i] > 0.0) || rho[i] > 1.0 || (i > 0 && !(rho[i] > rho[i - 1])))
             return fail(ctx, XRB_EINVAL, "phi_combo: rho must increase within (0, 1]");
         if (!w_out[i]) return fail(ctx, XRB_EINVAL, "phi_combo: null output");
+        if (w_out[i] == u) return fail(ctx, XRB_EINVAL, "phi_combo: output aliases u");
         for (int l = 0; l <= p; ++l)
             if (v[l] && v[l] == w_out[i]) return fail(ctx, XRB_EINVAL, "phi_combo: output aliases input");
     }
-    // scale = max_l ||v_l||; all-zero inputs give W = 0 exactly
-    const int n = ctx->n;
-    int np_r0 = 0, np_dot = 0, np_upd = 0;   // partial counts of the last producers
+    if (ctx->mode == XRB_REPLAY && nm > 1)
+        return fail(ctx, XRB_EINVAL, "phi_combo: replay is available for single states only");
+    const int np = red_parts(n);   // partials of every reducing producer
+    std::vector<MemberPhi> ms(nm);
+    // input norms, warm starts, controller initialisation
     const double *vl[kPmax + 1];
     int nv = 0;
     for (int l = 0; l <= p; ++l)
         if (v[l]) vl[nv++] = v[l];
-    int m = m_start > 0 ? m_start : P.m_init;
-    m = std::min(std::max(m, 1), P.m_max);
-    int npv = 0;
-    if (nv > 0) timed(ctx, XRB_K_VEC, [&] { npv = launch_norms(n, nv, vl, ctx->v_parts, s); });
-    launch_phi_init(ctx->ctl, m, rho[0], P.tol, ctx->v_parts, npv, nv, ctx->vnorm2, s);
-    HIPCHK(hipMemcpyAsync(ctx->vn_host, ctx->vnorm2, sizeof(double) * (kPmax + 1),
+    for (int k = 0; k < nm; ++k) {
+        int m0 = (site >= 0 && W.m_warm[3 * k + site] > 0) ? W.m_warm[3 * k + site] : P.m_init;
+        ms[k].m = std::min(std::max(m0, 1), P.m_max);
+        W.h_m0[k] = ms[k].m;
+    }
+    HIPCHK(hipMemcpyAsync(W.m0k, W.h_m0, sizeof(int32_t) * nm, hipMemcpyHostToDevice, s));
+    const Batch ball = batch_of(W);
+    if (nv > 0) timed(ctx, XRB_K_VEC, [&] { launch_norms(n, nv, vl, W.v_parts, ball, s); });
+    launch_phi_init(W.ctl, ms[0].m, W.m0k, rho[0], P.tol, W.v_parts, np, nv, W.vnorm2, ball, s);
+    HIPCHK(hipMemcpyAsync(W.h_vn, W.vnorm2, sizeof(double) * (kPmax + 1) * nm,
                           hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     prof_drain(ctx);
-    double smax = 0.0;
-    for (int k = 0; k < nv; ++k) {
-        if (ctx->vn_host[k] != ctx->vn_host[k]) return fail(ctx, XRB_ENAN, "phi_combo: NaN input");
-        smax = std::max(smax, ctx->vn_host[k]);
+    int live = 0;
+    for (int k = 0; k < nm; ++k) {
+        double smax = 0.0;
+        for (int l = 0; l < nv; ++l) {
+            const double x = W.h_vn[k * (kPmax + 1) + l];
+            if (x != x) return fail(ctx, XRB_ENAN, "phi_combo: NaN input");
+            smax = std::max(smax, x);
+        }
+        if (smax == 0.0) {
+            ms[k].zero_input = ms[k].done = true;
+        } else {
+            ++live;
+        }
+        for (int f = 0; f < kPlanW; ++f) W.h_plan[kPlanW * k + f] = 0;
+        W.h_plan[kPlanW * k + PF_INIT] = ms[k].zero_input ? 1 : 0;
     }
-    if (smax == 0.0) {
-        for (int i = 0; i < ns; ++i) HIPCHK(hipMemsetAsync(w_out[i], 0, sizeof(double) * n4, s));
-        if (st_out) *st_out = st;
+    // all-zero inputs give W = 0 exactly
+    if (live < nm) {
+        int rc = upload_plan(ctx, W, 0);
+        if (rc) return rc;
+        const Batch bz = batch_of(W, W.plan, PF_INIT);
+        for (int i = 0; i < ns; ++i) {
+            const double *none[1] = {nullptr};
+            const double zc[1] = {0.0};
+            launch_lincomb(n4, w_out[i], 0, none, zc, 0, bz, s);
+        }
+    }
+    if (live == 0) {
+        if (st_out)
+            for (int k = 0; k < nm; ++k) st_out[k] = xrb_phi_stats{};
         return XRB_OK;
     }
-    int y_zero = 1;
     if (v[0]) {
-        HIPCHK(hipMemcpyAsync(ctx->y, v[0], sizeof(double) * n4, hipMemcpyDeviceToDevice, s));
-        y_zero = 0;
+        const double *one[1] = {v[0]};
+        const double c1[1] = {1.0};
+        launch_lincomb(n4, W.y, 1, one, c1, 0, ball, s);
     }
-    int wzero[kPmax + 1];
-    const double *wptr[kPmax + 1];
-    auto nrm_buf = [&](int col) { return ctx->nrm_parts + (size_t)(col & 1) * kRedBlocks; };
-    bool point_ready = false;
-    int built = 0, wp_zero = 0;
+    for (auto &mm : ms) mm.y_zero = (v[0] == nullptr);
 
-    for (int io = 0; io < ns; ++io) {
-        launch_set_tout(ctx->ctl, rho[io], s);
-        bool reached = false;
-        while (!reached) {
-            if (st.attempts >= P.max_attempts) return fail(ctx, XRB_ENOTCONV, "phi_combo: attempt cap");
-            st.attempts++;
+    const double *wptr[kPmax + 1];
+    wptr[0] = W.y;
+    for (int j = 1; j <= p; ++j) wptr[j] = (j == p) ? W.V : W.Wr + (size_t)(j - 1) * n4;
+    auto nrm_buf = [&](int col) { return W.nrm_parts + (size_t)(col & 1) * kRedBlocks; };
+
+    while (true) {
+        bool any_live = false;
+        for (auto &mm : ms) any_live |= !mm.done;
+        if (!any_live) break;
+        for (int k = 0; k < nm; ++k)
+            for (int f = 0; f < kPlanW; ++f) W.h_plan[kPlanW * k + f] = 0;
+        // ---- step 1: w_j recurrence (eq. 3.18) for members at a new point
+        bool any_rec = false;
+        for (int k = 0; k < nm; ++k) {
+            MemberPhi &mm = ms[k];
+            if (mm.done || mm.ready) continue;
+            if (mm.st.attempts >= P.max_attempts)
+                return fail(ctx, XRB_ENOTCONV, "phi_combo: attempt cap");
+            any_rec = true;
+            mm.wzero[0] = mm.y_zero;
+            for (int j = 1; j <= p; ++j) {
+                bool terms = false;
+                for (int l = 0; l <= p - j; ++l)
+                    if (v[j + l] && (l == 0 || mm.st.accepted > 0)) terms = true;
+                const bool prod = !mm.wzero[j - 1];
+                if (prod) {
+                    W.h_plan[kPlanW * k + PF_REC_PROD] |= 1 << (j - 1);
+                    mm.st.matvecs++;
+                    mm.st.rec_matvecs++;
+                } else if (terms) {
+                    W.h_plan[kPlanW * k + PF_REC_SUM] |= 1 << (j - 1);
+                }
+                mm.wzero[j] = (!prod && !terms) ? 1 : 0;
+            }
+            if (p == 0 && !mm.y_zero) W.h_plan[kPlanW * k + PF_REC_SUM] |= 1;
+            mm.wp_zero = (p == 0) ? mm.y_zero : mm.wzero[p];
+        }
+        // ---- IOM2 column ranges and controller arguments
+        int jlo = 1 << 30, jhi = 0;
+        for (int k = 0; k < nm; ++k) {
+            MemberPhi &mm = ms[k];
+            if (mm.done) continue;
+            if (!mm.ready) mm.built = 0;
+            if (mm.st.attempts >= P.max_attempts)
+                return fail(ctx, XRB_ENOTCONV, "phi_combo: attempt cap");
+            mm.st.attempts++;
             ReplayIn rep{};
             if (ctx->mode == XRB_REPLAY) {
                 if (ctx->sched_pos >= ctx->sched.size())
@@ -227,155 +360,386 @@ int phi_run(xrb_ctx *ctx, double dt, const double *u, int p, const double *const
                 rep.m = e.m;
                 rep.flags = e.flags;
                 rep.active = 1;
-                m = e.m;
+                mm.m = e.m;
             }
-            if (!point_ready) {
-                // step 1: w_j recurrence (eq. 3.18) with the zero-skip of Sec. 4.3
-                wzero[0] = y_zero;
-                wptr[0] = ctx->y;
-                for (int j = 1; j <= p; ++j) {
-                    double *dst = (j == p) ? ctx->V : ctx->W + (size_t)(j - 1) * n4;
-                    JvArgs a;
-                    for (int l = 0; l <= p - j; ++l) {
-                        if (!v[j + l] || (l > 0 && st.accepted == 0)) continue;
-                        a.axv[a.naxpy] = v[j + l];
-                        a.axc[a.naxpy] = &ctx->ctl->rec_coef[l];
-                        a.naxpy++;
-                    }
-                    const int epi = (j == p) ? kEpiNorm : kEpiNone;
-                    if (!wzero[j - 1]) {
-                        timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, wptr[j - 1], ctx->lap, s); });
-                        a.u = u;
-                        a.eta = ctx->eta;
-                        a.x = wptr[j - 1];
-                        a.lx = ctx->lap;
-                        a.dt = dt;
-                        a.out = dst;
-                        a.ctl = ctx->ctl;
-                        a.nrm_out = ctx->nrm_parts;
-                        timed(ctx, XRB_K_JV_OTHER, [&] {
-                            const int g = launch_jv(ctx->M, a, epi, s);
-                            if (j == p) np_r0 = g;
-                        });
-                        st.matvecs++;
-                        st.rec_matvecs++;
-                        wzero[j] = 0;
-                    } else if (a.naxpy > 0) {
-                        timed(ctx, XRB_K_VEC, [&] {
-                            const int g = launch_lincomb_dev(n, dst, a.naxpy, a.axv, a.axc,
-                                                             j == p ? ctx->nrm_parts : nullptr, s);
-                            if (j == p) np_r0 = g;
-                        });
-                        wzero[j] = 0;
-                    } else {
-                        wzero[j] = 1;
-                    }
-                    wptr[j] = dst;
-                }
-                wp_zero = wzero[p];
-                if (p == 0) {
-                    // phi_0 only: the basis starts from y itself
-                    if (!y_zero) {
-                        const double *one[1] = {ctx->y};
-                        const double *cf[1] = {&ctx->ctl->rec_coef[0]};
-                        np_r0 = launch_lincomb_dev(n, ctx->V, 1, one, cf, ctx->nrm_parts, s);
-                    }
-                    wp_zero = y_zero;
-                }
-                built = 0;
-                point_ready = true;
+            if (!mm.wp_zero && mm.m > mm.built) {
+                W.h_plan[kPlanW * k + PF_IOM2_LO] = mm.built;
+                W.h_plan[kPlanW * k + PF_IOM2_HI] = mm.m;
+                jlo = std::min(jlo, mm.built);
+                jhi = std::max(jhi, mm.m);
+                mm.st.matvecs += mm.m - mm.built;
+                mm.built = mm.m;
             }
-            // step 2(i): IOM2 columns up to m
-            if (!wp_zero) {
-                for (int j = built; j < m; ++j) {
-                    double *rj = ctx->V + (size_t)j * n4;
-                    double *rn = ctx->V + (size_t)(j + 1) * n4;
-                    const double *rm = j > 0 ? ctx->V + (size_t)(j - 1) * n4 : nullptr;
-                    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, ctx->lap, s); });
-                    JvArgs a;
-                    a.u = u;
-                    a.eta = ctx->eta;
-                    a.x = rj;
-                    a.lx = ctx->lap;
-                    a.dt = dt;
-                    a.out = rn;
-                    a.j = j;
-                    a.rjm1 = rm;
-                    a.ctl = ctx->ctl;
-                    a.dot_out = ctx->dot_parts;
-                    timed(ctx, XRB_K_JV_IOM2, [&] { np_dot = launch_jv(ctx->M, a, kEpiIom2, s); });
-                    const int np_in = (j == 0) ? np_r0 : np_upd;
-                    timed(ctx, XRB_K_IOM2_UPD, [&] {
-                        np_upd = launch_iom2_update(n, j, rn, rj, rm, ctx->ctl, nrm_buf(j), np_in,
-                                                    ctx->dot_parts, np_dot, nrm_buf(j + 1), s);
-                    });
-                    st.matvecs++;
-                }
-                built = std::max(built, m);
-            }
-            // steps 2(ii)-6 on the device
-            CtlArgs ca;
-            ca.m = m;
+            W.h_plan[kPlanW * k + PF_CTL] = 1;
+            CtlArgs &ca = W.h_cargs[k];
+            ca.m = mm.m;
             ca.p = p;
             ca.mode = ctx->mode;
             ca.m_max = P.m_max;
-            ca.wp_zero = wp_zero;
-            ca.built = built;
-            ca.nrm_in = nrm_buf(built);
-            ca.n_nrm_in = np_upd;
+            ca.wp_zero = mm.wp_zero;
+            ca.built = mm.built;
+            ca.nrm_buf = mm.built & 1;
+            ca.n_nrm_in = np;
+            ca.t_out = rho[mm.io];
             ca.n4 = (double)n4;
             ca.delta = P.delta;
             ca.gamma = P.gamma;
             ca.rep = rep;
-            timed(ctx, XRB_K_CTL, [&] { launch_controller(ctx->ctl, ca, s); });
-            HIPCHK(hipMemcpyAsync(ctx->dec_host, &ctx->ctl->dec, sizeof(Decision),
-                                  hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            prof_drain(ctx);
-            const Decision d = *ctx->dec_host;
+        }
+        if (nm > 1) {
+            int rc = upload_plan(ctx, W, 0);
+            if (rc) return rc;
+            HIPCHK(hipMemcpyAsync(W.cargs, W.h_cargs, sizeof(CtlArgs) * nm, hipMemcpyHostToDevice, s));
+        }
+        if (any_rec) {
+            for (int j = 1; j <= p; ++j) {
+                bool any_prod = false, any_sum = false;
+                for (int k = 0; k < nm; ++k) {
+                    any_prod |= ((W.h_plan[kPlanW * k + PF_REC_PROD] >> (j - 1)) & 1) != 0;
+                    any_sum |= ((W.h_plan[kPlanW * k + PF_REC_SUM] >> (j - 1)) & 1) != 0;
+                }
+                JvArgs a;
+                for (int l = 0; l <= p - j; ++l) {
+                    if (!v[j + l]) continue;
+                    a.axv[a.naxpy] = v[j + l];
+                    a.axc[a.naxpy] = &W.ctl[0].rec_coef[l];
+                    a.naxpy++;
+                }
+                double *dst = (double *)wptr[j];
+                if (any_prod) {
+                    const Batch bp = batch_of(W, W.plan, PF_REC_PROD, j);
+                    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, wptr[j - 1], W.lap, bp, s); });
+                    a.u = u;
+                    a.eta = W.eta;
+                    a.x = wptr[j - 1];
+                    a.lx = W.lap;
+                    a.out = dst;
+                    a.nrm_out = W.nrm_parts;
+                    timed(ctx, XRB_K_JV_OTHER,
+                          [&] { launch_jv(ctx->M, a, j == p ? kEpiNorm : kEpiNone, bp, s); });
+                }
+                if (any_sum) {
+                    const Batch bsum = batch_of(W, W.plan, PF_REC_SUM, j);
+                    timed(ctx, XRB_K_VEC, [&] {
+                        launch_lincomb_dev(n, dst, a.naxpy, a.axv, a.axc, W.ctl,
+                                           j == p ? W.nrm_parts : nullptr, bsum, s);
+                    });
+                }
+            }
+            if (p == 0) {
+                const double *one[1] = {W.y};
+                const double *cf[1] = {&W.ctl[0].rec_coef[0]};
+                const Batch bsum = batch_of(W, W.plan, PF_REC_SUM, 1);
+                launch_lincomb_dev(n, W.V, 1, one, cf, W.ctl, W.nrm_parts, bsum, s);
+            }
+            for (auto &mm : ms)
+                if (!mm.done) mm.ready = true;
+        }
+        // ---- step 2(i): IOM2 columns
+        for (int j = jlo; j < jhi; ++j) {
+            const Batch bj = batch_of(W, W.plan, PF_IOM2_LO, j);
+            double *rj = W.V + (size_t)j * n4;
+            double *rn = W.V + (size_t)(j + 1) * n4;
+            const double *rm = j > 0 ? W.V + (size_t)(j - 1) * n4 : nullptr;
+            timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, W.lap, bj, s); });
+            JvArgs a;
+            a.u = u;
+            a.eta = W.eta;
+            a.x = rj;
+            a.lx = W.lap;
+            a.out = rn;
+            a.j = j;
+            a.rjm1 = rm;
+            a.ctl = W.ctl;
+            a.dot_out = W.dot_parts;
+            timed(ctx, XRB_K_JV_IOM2, [&] { launch_jv(ctx->M, a, kEpiIom2, bj, s); });
+            timed(ctx, XRB_K_IOM2_UPD, [&] {
+                launch_iom2_update(n, j, rn, rj, rm, W.ctl, nrm_buf(j), np, W.dot_parts, np,
+                                   nrm_buf(j + 1), bj, s);
+            });
+        }
+        // ---- steps 2(ii)-6 on the device
+        {
+            const Batch bc = batch_of(W, W.plan, PF_CTL);
+            const CtlArgs a0 = W.h_cargs[0];
+            timed(ctx, XRB_K_CTL, [&] {
+                launch_controller(W.ctl, a0, nm > 1 ? W.cargs : nullptr, W.nrm_parts, bc, s);
+            });
+        }
+        HIPCHK(hipMemcpy2DAsync(W.h_dec, sizeof(Decision), &W.ctl[0].dec, sizeof(PhiCtl),
+                                sizeof(Decision), nm, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        prof_drain(ctx);
+        bool any_comb = false;
+        int copy_slot = 0;
+        for (int k = 0; k < nm; ++k) {
+            W.h_plan[kPlanW * k + PF_COMB] = 0;
+            W.h_plan[kPlanW * k + PF_COPY] = 0;
+            MemberPhi &mm = ms[k];
+            if (mm.done) continue;
+            const Decision d = W.h_dec[k];
             if (d.status == XRB_ENAN) return fail(ctx, XRB_ENAN, "phi_combo: NaN in Krylov process");
             if (d.status != 0) return fail(ctx, d.status, "phi_combo: device error");
             if (!(d.tau_u >= 1e-12 * rho[ns - 1]))
                 return fail(ctx, XRB_ENOTCONV, "phi_combo: substep underflow");
-            if (d.m_eff > 0) st.expms++;
-            st.sum_m += m;
-            st.max_m = std::max(st.max_m, m);
-            if (ctx->mode == XRB_RECORD)
-                ctx->sched.push_back({d.tau_u, m, (d.accept ? 1 : 0) | (d.lands ? 2 : 0)});
+            if (d.m_eff > 0) mm.st.expms++;
+            mm.st.sum_m += mm.m;
+            mm.st.max_m = std::max(mm.st.max_m, mm.m);
+            if (ctx->mode == XRB_RECORD && nm == 1)
+                ctx->sched.push_back({d.tau_u, mm.m, (d.accept ? 1 : 0) | (d.lands ? 2 : 0)});
             if (d.accept) {
-                timed(ctx, XRB_K_COMBINE, [&] {
-                    launch_combine(n4, ctx->y, p, wptr, wzero, ctx->V, d.m_eff, d.m_eff > 0 ? 1 : 0,
-                                   ctx->ctl, s);
-                });
-                st.accepted++;
-                st.last_m = m;
-                y_zero = 0;
-                point_ready = false;
+                int zm = 0;
+                for (int j = 0; j < p; ++j) zm |= mm.wzero[j] << j;
+                W.h_plan[kPlanW * k + PF_COMB] = 1 | (zm << 1);
+                any_comb = true;
+                mm.st.accepted++;
+                mm.st.last_m = mm.m;
+                mm.y_zero = false;
+                mm.ready = false;
             } else {
-                st.rejected++;
+                mm.st.rejected++;
             }
-            if (ctx->mode != XRB_REPLAY) m = d.m_next;
-            reached = d.reached != 0;
+            if (ctx->mode != XRB_REPLAY) mm.m = d.m_next;
+            if (d.reached) {
+                W.h_plan[kPlanW * k + PF_COPY] = mm.io + 1;
+                copy_slot = mm.io;
+                mm.io++;
+                if (mm.io == ns) mm.done = true;
+            }
         }
-        HIPCHK(hipMemcpyAsync(w_out[io], ctx->y, sizeof(double) * n4, hipMemcpyDeviceToDevice, s));
+        bool any_copy = false;
+        for (int k = 0; k < nm; ++k) any_copy |= W.h_plan[kPlanW * k + PF_COPY] != 0;
+        if (any_comb || any_copy) {
+            int rc = upload_plan(ctx, W, 1);
+            if (rc) return rc;
+        }
+        if (any_comb) {
+            int wz[kPmax + 1];
+            for (int j = 0; j <= kPmax; ++j) wz[j] = 0;
+            // a w_j that is zero for every combining member may be skipped
+            for (int j = 0; j < p; ++j) {
+                bool allz = true;
+                for (int k = 0; k < nm; ++k)
+                    if (W.h_plan[kPlanW * k + PF_COMB] && !ms[k].wzero[j]) allz = false;
+                wz[j] = allz ? 1 : 0;
+            }
+            const Batch bcomb = batch_of(W, W.plan, PF_COMB);
+            timed(ctx, XRB_K_COMBINE, [&] { launch_combine(n4, W.y, p, wptr, wz, W.V, W.ctl, bcomb, s); });
+        }
+        if (any_copy) {
+            double *slots[8];
+            for (int i = 0; i < 8; ++i) slots[i] = (nm > 1) ? (i < ns ? w_out[i] : nullptr) : nullptr;
+            if (nm == 1) slots[0] = w_out[copy_slot];
+            const Batch bcp = batch_of(W, W.plan, PF_COPY);
+            launch_copy_out(n4, W.y, slots, bcp, s);
+        }
     }
-    if (m_last) *m_last = st.last_m;
-    if (st_out) *st_out = st;
+    for (int k = 0; k < nm; ++k) {
+        if (site >= 0 && ms[k].st.accepted > 0) W.m_warm[3 * k + site] = ms[k].st.last_m;
+        if (st_out) st_out[k] = ms[k].st;
+    }
     return XRB_OK;
 }
 
-int free_all(xrb_ctx *ctx) {
-    prof_drain(ctx);
-    for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
-    ctx->ev_free.clear();
-    void *dev[] = {ctx->geo_mem, ctx->V, ctx->W, ctx->y, ctx->lap, ctx->eta, ctx->stage,
-                   ctx->dot_parts, ctx->nrm_parts, ctx->v_parts, ctx->vnorm2, ctx->ctl};
+int free_work(Work &W) {
     int rc = XRB_OK;
+    void *dev[] = {W.base, W.ctl, W.dot_parts, W.nrm_parts, W.v_parts, W.vnorm2, W.dtk, W.plan,
+                   W.cargs, W.m0k};
     for (void *p : dev)
         if (p && hipFree(p) != hipSuccess) rc = XRB_EDEVICE;
-    if (ctx->dec_host && hipHostFree(ctx->dec_host) != hipSuccess) rc = XRB_EDEVICE;
-    if (ctx->vn_host && hipHostFree(ctx->vn_host) != hipSuccess) rc = XRB_EDEVICE;
+    void *hst[] = {W.h_dec, W.h_stage, W.h_cargs, W.h_vn, W.h_dt, W.h_m0};
+    for (void *p : hst)
+        if (p && hipHostFree(p) != hipSuccess) rc = XRB_EDEVICE;
+    W = Work{};
     return rc;
+}
+
+int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
+    const int64_t n4 = ctx->n4;
+    const int mmax = ctx->prm.m_max;
+    // member block: basis, recurrence, y, lap, eta, stages
+    const int64_t nvec = (mmax + 1) + kPmax + 1 + 1 + 1 + S_COUNT;
+    W.nm = nm;
+    W.ws = nm > 1 ? nvec * n4 : 0;
+    const int64_t member_doubles = nvec * n4;
+    int rc = XRB_OK;
+    auto ck = [&](hipError_t e) {
+        if (e != hipSuccess && rc == XRB_OK) {
+            ctx->err = hipGetErrorString(e);
+            rc = XRB_ENOMEM;
+        }
+    };
+    ck(hipMalloc((void **)&W.base, sizeof(double) * member_doubles * nm));
+    ck(hipMalloc((void **)&W.ctl, sizeof(PhiCtl) * nm));
+    ck(hipMalloc((void **)&W.dot_parts, sizeof(double) * kPartStride * nm));
+    ck(hipMalloc((void **)&W.nrm_parts, sizeof(double) * kPartStride * nm));
+    ck(hipMalloc((void **)&W.v_parts, sizeof(double) * kVPartStride * nm));
+    ck(hipMalloc((void **)&W.vnorm2, sizeof(double) * (kPmax + 1) * nm));
+    ck(hipMalloc((void **)&W.dtk, sizeof(double) * nm));
+    ck(hipMalloc((void **)&W.plan, sizeof(int32_t) * kPlanW * nm));
+    ck(hipMalloc((void **)&W.cargs, sizeof(CtlArgs) * nm));
+    ck(hipMalloc((void **)&W.m0k, sizeof(int32_t) * nm));
+    ck(hipHostMalloc((void **)&W.h_dec, sizeof(Decision) * nm, hipHostMallocDefault));
+    ck(hipHostMalloc((void **)&W.h_stage, sizeof(int32_t) * 2 * kPlanW * nm, hipHostMallocDefault));
+    W.h_plan.assign((size_t)kPlanW * nm, 0);
+    ck(hipHostMalloc((void **)&W.h_cargs, sizeof(CtlArgs) * nm, hipHostMallocDefault));
+    ck(hipHostMalloc((void **)&W.h_vn, sizeof(double) * (kPmax + 1) * nm, hipHostMallocDefault));
+    ck(hipHostMalloc((void **)&W.h_dt, sizeof(double) * nm, hipHostMallocDefault));
+    ck(hipHostMalloc((void **)&W.h_m0, sizeof(int32_t) * nm, hipHostMallocDefault));
+    if (rc) {
+        free_work(W);
+        return rc;
+    }
+    double *p = W.base;
+    W.V = p;
+    p += (size_t)(mmax + 1) * n4;
+    W.Wr = p;
+    p += (size_t)kPmax * n4;
+    W.y = p;
+    p += n4;
+    W.lap = p;
+    p += n4;
+    W.eta = p;
+    p += n4;
+    W.stage = p;
+    ck(hipMemset(W.base, 0, sizeof(double) * member_doubles * nm));
+    ck(hipMemset(W.ctl, 0, sizeof(PhiCtl) * nm));
+    ck(hipMemset(W.plan, 0, sizeof(int32_t) * kPlanW * nm));
+    W.m_warm.assign(3 * nm, 0);
+    W.stats.assign(3 * nm, xrb_phi_stats{});
+    W.have_prev = 0;
+    if (rc) free_work(W);
+    return rc;
+}
+
+double *stage_vec(const xrb_ctx *ctx, const Work &W, int k) { return W.stage + (size_t)k * ctx->n4; }
+
+// One step of `method` for every member of W; u is member 0's state (stride
+// W.ws); the members' step sizes are in W.dtk / W.h_dt.
+int scheme_step(xrb_ctx *ctx, Work &W, int method, double *u) {
+    const int nm = W.nm;
+    const hipStream_t s = ctx->stream;
+    auto SV = [&](int k) { return stage_vec(ctx, W, k); };
+    double *Fn = SV(S_FN), *v = SV(S_V), *W1 = SV(S_W1), *W2 = SV(S_W2), *X1 = SV(S_X1);
+    double *X2 = SV(S_X2), *U2 = SV(S_U2), *U3 = SV(S_U3), *D2 = SV(S_D2), *D3 = SV(S_D3);
+    double *a3 = SV(S_A3), *a4 = SV(S_A4), *t1 = SV(S_T1), *t2 = SV(S_T2);
+    for (auto &st : W.stats) st = xrb_phi_stats{};
+    std::vector<xrb_phi_stats> tmp(nm);
+    auto site_stats = [&](int site) {
+        for (int k = 0; k < nm; ++k) W.stats[3 * k + site] = tmp[k];
+    };
+    rhs_plain(ctx, W, u, Fn);
+    lincomb(ctx, W, v, {Fn}, {1.0}, 1u);                      // v = dt F(u_n)
+    launch_linearize(ctx->M, u, W.eta, batch_of(W), s);
+    // D = F(U) - Fn - J_n (U - u_n)
+    auto nonlin = [&](const double *U, double *D) {
+        lincomb(ctx, W, t1, {U, u}, {1.0, -1.0});
+        jv_plain(ctx, W, u, t1, t2, false);
+        rhs_plain(ctx, W, U, D);
+        lincomb(ctx, W, D, {D, Fn, t2}, {1.0, -1.0, -1.0});
+    };
+    int rc = XRB_OK;
+    if (method == XRB_EXPRB42) {
+        const double r1[1] = {0.75}, r2[1] = {1.0};
+        const double *vi[2] = {nullptr, v};
+        double *o1[1] = {W1};
+        rc = phi_batch(ctx, W, u, 1, vi, 1, r1, o1, 0, tmp.data());
+        if (rc) return rc;
+        site_stats(0);
+        lincomb(ctx, W, U2, {u, W1}, {1.0, 1.0});
+        nonlin(U2, D2);
+        lincomb(ctx, W, a3, {D2}, {32.0 / 9.0}, 1u);
+        const double *vii[4] = {nullptr, v, nullptr, a3};
+        double *o2[1] = {W2};
+        rc = phi_batch(ctx, W, u, 3, vii, 1, r2, o2, 1, tmp.data());
+        if (rc) return rc;
+        site_stats(1);
+        lincomb(ctx, W, u, {u, W2}, {1.0, 1.0});
+    } else if (method == XRB_PEXPRB43) {
+        const double r1[2] = {0.5, 1.0}, r2[1] = {1.0};
+        const double *vi[2] = {nullptr, v};
+        double *o1[2] = {W1, W2};
+        rc = phi_batch(ctx, W, u, 1, vi, 2, r1, o1, 0, tmp.data());
+        if (rc) return rc;
+        site_stats(0);
+        lincomb(ctx, W, U2, {u, W1}, {1.0, 1.0});
+        lincomb(ctx, W, U3, {u, W2}, {1.0, 1.0});
+        nonlin(U2, D2);
+        nonlin(U3, D3);
+        lincomb(ctx, W, a3, {D2, D3}, {16.0, -2.0}, 3u);
+        lincomb(ctx, W, a4, {D2, D3}, {-48.0, 12.0}, 3u);
+        const double *vii[5] = {nullptr, nullptr, nullptr, a3, a4};
+        double *o2[1] = {X1};
+        rc = phi_batch(ctx, W, u, 4, vii, 1, r2, o2, 1, tmp.data());
+        if (rc) return rc;
+        site_stats(1);
+        lincomb(ctx, W, u, {U3, X1}, {1.0, 1.0});
+    } else if (method == XRB_EXPRB53) {
+        const double r1[2] = {0.5, 0.9}, r3[1] = {1.0};
+        const double *vi[2] = {nullptr, v};
+        double *o1[2] = {W1, W2};
+        rc = phi_batch(ctx, W, u, 1, vi, 2, r1, o1, 0, tmp.data());
+        if (rc) return rc;
+        site_stats(0);
+        lincomb(ctx, W, U2, {u, W1}, {1.0, 1.0});
+        nonlin(U2, D2);
+        lincomb(ctx, W, a3, {D2}, {1.0}, 1u);
+        const double *vii[4] = {nullptr, nullptr, nullptr, a3};
+        double *o2[2] = {X1, X2};
+        rc = phi_batch(ctx, W, u, 3, vii, 2, r1, o2, 1, tmp.data());
+        if (rc) return rc;
+        site_stats(1);
+        // U3 = u + W(i)_2 + (27/25)(2^3) W(ii)_1 + (729/125)(10/9)^3 W(ii)_2
+        lincomb(ctx, W, U3, {u, W2, X1, X2}, {1.0, 1.0, 216.0 / 25.0, 8.0});
+        nonlin(U3, D3);
+        lincomb(ctx, W, a3, {D2, D3}, {18.0, -250.0 / 81.0}, 3u);
+        lincomb(ctx, W, a4, {D2, D3}, {-60.0, 500.0 / 27.0}, 3u);
+        const double *viii[5] = {nullptr, v, nullptr, a3, a4};
+        double *o3[1] = {W1};
+        rc = phi_batch(ctx, W, u, 4, viii, 1, r3, o3, 2, tmp.data());
+        if (rc) return rc;
+        site_stats(2);
+        lincomb(ctx, W, u, {u, W1}, {1.0, 1.0});
+    } else if (method == XRB_EPI3 || method == XRB_EPI2) {
+        const double r1[1] = {1.0};
+        double *uprev = SV(S_UPREV), *fprev = SV(S_FPREV);
+        double *o1[1] = {W1};
+        if (method == XRB_EPI3 && W.have_prev) {
+            // R_{n-1} = F(u_{n-1}) - F(u_n) - J_n (u_{n-1} - u_n)
+            lincomb(ctx, W, t1, {uprev, u}, {1.0, -1.0});
+            jv_plain(ctx, W, u, t1, t2, false);
+            lincomb(ctx, W, a3, {fprev, Fn, t2}, {2.0 / 3.0, -2.0 / 3.0, -2.0 / 3.0}, 7u);
+            const double *vi[3] = {nullptr, v, a3};
+            rc = phi_batch(ctx, W, u, 2, vi, 1, r1, o1, 0, tmp.data());
+            if (rc) return rc;
+            site_stats(0);
+        } else {
+            const double *vi[2] = {nullptr, v};
+            rc = phi_batch(ctx, W, u, 1, vi, 1, r1, o1, 1, tmp.data());
+            if (rc) return rc;
+            site_stats(1);
+        }
+        lincomb(ctx, W, uprev, {u}, {1.0});
+        lincomb(ctx, W, fprev, {Fn}, {1.0});
+        W.have_prev = 1;
+        lincomb(ctx, W, u, {u, W1}, {1.0, 1.0});
+    } else {
+        return fail(ctx, XRB_EINVAL, "step: unknown method");
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    prof_drain(ctx);
+    return XRB_OK;
+}
+
+int set_dt(xrb_ctx *ctx, Work &W, const double *dt) {
+    for (int k = 0; k < W.nm; ++k) {
+        if (!(dt[k] > 0.0) && !(dt[k] < 0.0))
+            return fail(ctx, XRB_EINVAL, "step: dt must be nonzero");
+        W.h_dt[k] = dt[k];
+    }
+    HIPCHK(hipMemcpyAsync(W.dtk, W.h_dt, sizeof(double) * W.nm, hipMemcpyHostToDevice, ctx->stream));
+    return XRB_OK;
 }
 
 }  // namespace
@@ -419,35 +783,25 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ctx->n = n;
     ctx->n4 = 4 * n;
     const size_t nd = (size_t)n;
-    // geometry in one allocation: 7 x [6][n] weights, 4 x [n] cell fields, [6][n] int32
+    // geometry in one allocation: 7 x [n][6] weights, 4 x [n] cell fields, [n][6] int32
     const size_t dbl = 7 * 6 * nd + 4 * nd;
     const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t);
-    auto ck = [&](hipError_t e) {
-        if (e != hipSuccess && rc == 0) {
-            ctx->err = hipGetErrorString(e);
-            rc = XRB_ENOMEM;
-        }
-    };
-    ck(hipMalloc(&ctx->geo_mem, bytes));
-    const size_t n4 = 4 * nd;
-    ck(hipMalloc((void **)&ctx->V, sizeof(double) * n4 * (params->m_max + 1)));
-    ck(hipMalloc((void **)&ctx->W, sizeof(double) * n4 * kPmax));
-    ck(hipMalloc((void **)&ctx->y, sizeof(double) * n4));
-    ck(hipMalloc((void **)&ctx->lap, sizeof(double) * n4));
-    ck(hipMalloc((void **)&ctx->eta, sizeof(double) * nd));
-    ck(hipMalloc((void **)&ctx->stage, sizeof(double) * n4 * S_COUNT));
-    ck(hipMalloc((void **)&ctx->dot_parts, sizeof(double) * 2 * kRedBlocks));
-    ck(hipMalloc((void **)&ctx->nrm_parts, sizeof(double) * 2 * kRedBlocks));
-    ck(hipMalloc((void **)&ctx->v_parts, sizeof(double) * (kPmax + 1) * kRedBlocks));
-    ck(hipMalloc((void **)&ctx->vnorm2, sizeof(double) * (kPmax + 1)));
-    ck(hipMalloc((void **)&ctx->ctl, sizeof(PhiCtl)));
-    ck(hipHostMalloc((void **)&ctx->dec_host, sizeof(Decision), hipHostMallocDefault));
-    ck(hipHostMalloc((void **)&ctx->vn_host, sizeof(double) * (kPmax + 1), hipHostMallocDefault));
-    if (rc) {
-        free_all(ctx);
+    if (hipMalloc(&ctx->geo_mem, bytes) != hipSuccess) {
         delete ctx;
         return XRB_ENOMEM;
     }
+    rc = alloc_work(ctx, ctx->one, 1);
+    if (rc) {
+        (void)hipFree(ctx->geo_mem);
+        delete ctx;
+        return (xrb_status)rc;
+    }
+    auto ck = [&](hipError_t e) {
+        if (e != hipSuccess && rc == 0) {
+            ctx->err = hipGetErrorString(e);
+            rc = XRB_EDEVICE;
+        }
+    };
     double *g = (double *)ctx->geo_mem;
     const std::vector<double> *srcs[7] = {&geo.ax, &geo.ay, &geo.az, &geo.bx, &geo.by, &geo.bz, &geo.cl};
     double *dst[7];
@@ -461,11 +815,9 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
         ck(hipMemcpy(cellf + k * nd, cs[k]->data(), sizeof(double) * nd, hipMemcpyHostToDevice));
     int32_t *nb = (int32_t *)(g + dbl);
     ck(hipMemcpy(nb, geo.nbr.data(), sizeof(int32_t) * 6 * nd, hipMemcpyHostToDevice));
-    ck(hipMemset(ctx->ctl, 0, sizeof(PhiCtl)));
-    ck(hipMemset(ctx->stage, 0, sizeof(double) * n4 * S_COUNT));
-    ck(hipMemset(ctx->V, 0, sizeof(double) * n4 * (params->m_max + 1)));
     if (rc) {
-        free_all(ctx);
+        free_work(ctx->one);
+        (void)hipFree(ctx->geo_mem);
         delete ctx;
         return XRB_EDEVICE;
     }
@@ -485,7 +837,11 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
 xrb_status xrb_destroy(xrb_ctx *ctx) {
     if (!ctx) return XRB_EINVAL;
     const hipError_t e = hipStreamSynchronize(ctx->stream);
-    const int rc = free_all(ctx);
+    prof_drain(ctx);
+    for (hipEvent_t ev : ctx->ev_free) (void)hipEventDestroy(ev);
+    int rc = free_work(ctx->one);
+    rc |= free_work(ctx->ens);
+    if (ctx->geo_mem && hipFree(ctx->geo_mem) != hipSuccess) rc = XRB_EDEVICE;
     delete ctx;
     return (e != hipSuccess || rc) ? XRB_EDEVICE : XRB_OK;
 }
@@ -508,7 +864,7 @@ int64_t xrb_n_cells(const xrb_ctx *ctx) { return ctx ? ctx->n : 0; }
 
 xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f) {
     if (!ctx || !u || !f || u == f) return (xrb_status)fail(ctx, XRB_EINVAL, "rhs: bad pointers");
-    rhs_plain(ctx, u, f);
+    rhs_plain(ctx, ctx->one, u, f);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -516,8 +872,8 @@ xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f) {
 xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
     if (!ctx || !u || !v || !jv || jv == u || jv == v)
         return (xrb_status)fail(ctx, XRB_EINVAL, "jv: bad pointers");
-    launch_linearize(ctx->M, u, ctx->eta, ctx->stream);
-    jv_plain(ctx, u, v, jv, 1.0);
+    launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    jv_plain(ctx, ctx->one, u, v, jv, false);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -525,127 +881,70 @@ xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
 xrb_status xrb_phi_combo(xrb_ctx *ctx, double dt, const double *u, int p, const double *const *v,
                          int ns, const double *rho, double *const *w_out, xrb_phi_stats *stats) {
     if (!ctx || !u) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: null");
-    if (!(dt == dt)) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: dt");
-    for (int i = 0; i < ns && w_out; ++i)
-        if (w_out[i] == u) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: output aliases u");
-    launch_linearize(ctx->M, u, ctx->eta, ctx->stream);
-    int rc = phi_run(ctx, dt, u, p, v, ns, rho, w_out, 0, nullptr, stats);
+    if (!(dt == dt) || dt == 0.0) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: dt");
+    int rc = set_dt(ctx, ctx->one, &dt);
+    if (rc) return (xrb_status)rc;
+    launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    rc = phi_batch(ctx, ctx->one, u, p, v, ns, rho, w_out, -1, stats);
     if (rc == XRB_OK) HIPCHK(hipGetLastError());
     return (xrb_status)rc;
 }
 
 xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt) {
     if (!ctx || !u || !(dt > 0.0)) return (xrb_status)fail(ctx, XRB_EINVAL, "step: bad argument");
-    const hipStream_t s = ctx->stream;
-    double *Fn = ctx->sv(S_FN), *v = ctx->sv(S_V), *W1 = ctx->sv(S_W1), *W2 = ctx->sv(S_W2);
-    double *X1 = ctx->sv(S_X1), *X2 = ctx->sv(S_X2), *U2 = ctx->sv(S_U2), *U3 = ctx->sv(S_U3);
-    double *D2 = ctx->sv(S_D2), *D3 = ctx->sv(S_D3), *a3 = ctx->sv(S_A3), *a4 = ctx->sv(S_A4);
-    double *t1 = ctx->sv(S_T1), *t2 = ctx->sv(S_T2);
-    for (auto &st : ctx->last_stats) st = xrb_phi_stats{};
-    rhs_plain(ctx, u, Fn);
-    lincomb(ctx, v, {Fn}, {dt});
-    launch_linearize(ctx->M, u, ctx->eta, s);
-    // D = F(U) - Fn - J_n (U - u_n)
-    auto nonlin = [&](const double *U, double *D) {
-        lincomb(ctx, t1, {U, u}, {1.0, -1.0});
-        jv_plain(ctx, u, t1, t2, 1.0);
-        rhs_plain(ctx, U, D);
-        lincomb(ctx, D, {D, Fn, t2}, {1.0, -1.0, -1.0});
-    };
-    int rc = XRB_OK;
-    if (method == XRB_EXPRB42) {
-        const double r1[1] = {0.75}, r2[1] = {1.0};
-        const double *vi[2] = {nullptr, v};
-        double *o1[1] = {W1};
-        rc = phi_run(ctx, dt, u, 1, vi, 1, r1, o1, ctx->m_warm[0], &ctx->m_warm[0], &ctx->last_stats[0]);
+    int rc = set_dt(ctx, ctx->one, &dt);
+    if (rc) return (xrb_status)rc;
+    return (xrb_status)scheme_step(ctx, ctx->one, (int)method, u);
+}
+
+xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, const double *dt,
+                          xrb_phi_stats *stats) {
+    if (!ctx || !U || !dt || nm < 1) return (xrb_status)fail(ctx, XRB_EINVAL, "step_batch: bad argument");
+    for (int k = 0; k < nm; ++k)
+        if (!(dt[k] > 0.0)) return (xrb_status)fail(ctx, XRB_EINVAL, "step_batch: dt must be positive");
+    if (ctx->ens.nm != nm) {
+        free_work(ctx->ens);
+        int rc = alloc_work(ctx, ctx->ens, nm);
         if (rc) return (xrb_status)rc;
-        lincomb(ctx, U2, {u, W1}, {1.0, 1.0});
-        nonlin(U2, D2);
-        lincomb(ctx, a3, {D2}, {32.0 / 9.0 * dt});
-        const double *vii[4] = {nullptr, v, nullptr, a3};
-        double *o2[1] = {W2};
-        rc = phi_run(ctx, dt, u, 3, vii, 1, r2, o2, ctx->m_warm[1], &ctx->m_warm[1], &ctx->last_stats[1]);
-        if (rc) return (xrb_status)rc;
-        lincomb(ctx, u, {u, W2}, {1.0, 1.0});
-    } else if (method == XRB_PEXPRB43) {
-        const double r1[2] = {0.5, 1.0}, r2[1] = {1.0};
-        const double *vi[2] = {nullptr, v};
-        double *o1[2] = {W1, W2};
-        rc = phi_run(ctx, dt, u, 1, vi, 2, r1, o1, ctx->m_warm[0], &ctx->m_warm[0], &ctx->last_stats[0]);
-        if (rc) return (xrb_status)rc;
-        lincomb(ctx, U2, {u, W1}, {1.0, 1.0});
-        lincomb(ctx, U3, {u, W2}, {1.0, 1.0});
-        nonlin(U2, D2);
-        nonlin(U3, D3);
-        lincomb(ctx, a3, {D2, D3}, {16.0 * dt, -2.0 * dt});
-        lincomb(ctx, a4, {D2, D3}, {-48.0 * dt, 12.0 * dt});
-        const double *vii[5] = {nullptr, nullptr, nullptr, a3, a4};
-        double *o2[1] = {X1};
-        rc = phi_run(ctx, dt, u, 4, vii, 1, r2, o2, ctx->m_warm[1], &ctx->m_warm[1], &ctx->last_stats[1]);
-        if (rc) return (xrb_status)rc;
-        lincomb(ctx, u, {U3, X1}, {1.0, 1.0});
-    } else if (method == XRB_EXPRB53) {
-        const double r1[2] = {0.5, 0.9}, r3[1] = {1.0};
-        const double *vi[2] = {nullptr, v};
-        double *o1[2] = {W1, W2};
-        rc = phi_run(ctx, dt, u, 1, vi, 2, r1, o1, ctx->m_warm[0], &ctx->m_warm[0], &ctx->last_stats[0]);
-        if (rc) return (xrb_status)rc;
-        lincomb(ctx, U2, {u, W1}, {1.0, 1.0});
-        nonlin(U2, D2);
-        lincomb(ctx, a3, {D2}, {dt});
-        const double *vii[4] = {nullptr, nullptr, nullptr, a3};
-        double *o2[2] = {X1, X2};
-        rc = phi_run(ctx, dt, u, 3, vii, 2, r1, o2, ctx->m_warm[1], &ctx->m_warm[1], &ctx->last_stats[1]);
-        if (rc) return (xrb_status)rc;
-        // U3 = u + W(i)_2 + (27/25)(2^3) W(ii)_1 + (729/125)(10/9)^3 W(ii)_2
-        lincomb(ctx, U3, {u, W2, X1, X2}, {1.0, 1.0, 216.0 / 25.0, 8.0});
-        nonlin(U3, D3);
-        lincomb(ctx, a3, {D2, D3}, {18.0 * dt, -250.0 / 81.0 * dt});
-        lincomb(ctx, a4, {D2, D3}, {-60.0 * dt, 500.0 / 27.0 * dt});
-        const double *viii[5] = {nullptr, v, nullptr, a3, a4};
-        double *o3[1] = {W1};
-        rc = phi_run(ctx, dt, u, 4, viii, 1, r3, o3, ctx->m_warm[2], &ctx->m_warm[2], &ctx->last_stats[2]);
-        if (rc) return (xrb_status)rc;
-        lincomb(ctx, u, {u, W1}, {1.0, 1.0});
-    } else if (method == XRB_EPI3 || method == XRB_EPI2) {
-        const double r1[1] = {1.0};
-        double *uprev = ctx->sv(S_UPREV), *fprev = ctx->sv(S_FPREV);
-        double *o1[1] = {W1};
-        if (method == XRB_EPI3 && ctx->have_prev) {
-            // R_{n-1} = F(u_{n-1}) - F(u_n) - J_n (u_{n-1} - u_n)
-            lincomb(ctx, t1, {uprev, u}, {1.0, -1.0});
-            jv_plain(ctx, u, t1, t2, 1.0);
-            lincomb(ctx, a3, {fprev, Fn, t2}, {2.0 / 3.0 * dt, -2.0 / 3.0 * dt, -2.0 / 3.0 * dt});
-            const double *vi[3] = {nullptr, v, a3};
-            rc = phi_run(ctx, dt, u, 2, vi, 1, r1, o1, ctx->m_warm[0], &ctx->m_warm[0], &ctx->last_stats[0]);
-        } else {
-            const double *vi[2] = {nullptr, v};
-            rc = phi_run(ctx, dt, u, 1, vi, 1, r1, o1, ctx->m_warm[1], &ctx->m_warm[1], &ctx->last_stats[1]);
-        }
-        if (rc) return (xrb_status)rc;
-        HIPCHK(hipMemcpyAsync(uprev, u, sizeof(double) * ctx->n4, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipMemcpyAsync(fprev, Fn, sizeof(double) * ctx->n4, hipMemcpyDeviceToDevice, s));
-        ctx->have_prev = 1;
-        lincomb(ctx, u, {u, W1}, {1.0, 1.0});
-    } else {
-        return (xrb_status)fail(ctx, XRB_EINVAL, "step: unknown method");
     }
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-    prof_drain(ctx);
+    Work &W = ctx->ens;
+    int rc = set_dt(ctx, W, dt);
+    if (rc) return (xrb_status)rc;
+    // member states into the workspace, one step, and back
+    double *ust = stage_vec(ctx, W, S_STATE);
+    const size_t row = sizeof(double) * ctx->n4;
+    if (nm == 1) {
+        HIPCHK(hipMemcpyAsync(ust, U, row, hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+        HIPCHK(hipMemcpy2DAsync(ust, sizeof(double) * W.ws, U, row, row, nm,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    rc = scheme_step(ctx, W, (int)method, ust);
+    if (rc) return (xrb_status)rc;
+    if (nm == 1) {
+        HIPCHK(hipMemcpyAsync(U, ust, row, hipMemcpyDeviceToDevice, ctx->stream));
+    } else {
+        HIPCHK(hipMemcpy2DAsync(U, row, ust, sizeof(double) * W.ws, row, nm,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (stats)
+        for (int k = 0; k < 3 * nm; ++k) stats[k] = W.stats[k];
     return XRB_OK;
 }
 
 xrb_status xrb_step_stats(const xrb_ctx *ctx, xrb_phi_stats *out3) {
     if (!ctx || !out3) return XRB_EINVAL;
-    for (int k = 0; k < 3; ++k) out3[k] = ctx->last_stats[k];
+    for (int k = 0; k < 3; ++k) out3[k] = ctx->one.stats[k];
     return XRB_OK;
 }
 
 xrb_status xrb_reset_history(xrb_ctx *ctx) {
     if (!ctx) return XRB_EINVAL;
-    ctx->m_warm[0] = ctx->m_warm[1] = ctx->m_warm[2] = 0;
-    ctx->have_prev = 0;
+    for (Work *W : {&ctx->one, &ctx->ens}) {
+        std::fill(W->m_warm.begin(), W->m_warm.end(), 0);
+        W->have_prev = 0;
+    }
     ctx->sched.clear();
     ctx->sched_pos = 0;
     return XRB_OK;

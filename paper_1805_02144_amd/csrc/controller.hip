@@ -87,7 +87,14 @@ __device__ double work_estimate(double tau, int m, int p, double t, double t_out
     return steps * m * (n + nA) + 2.0 * (p - 1) * (nA + n) + M * K * K * K + (2.0 * p + 1.0) * n;
 }
 
-__global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
+__global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
+                                                       const CtlArgs *dargs, double *nrm_parts,
+                                                       Batch bt) {
+    const int mk = blockIdx.x;
+    if (!member_active(bt.pred, mk)) return;
+    PhiCtl *c = ctl0 + mk;
+    const CtlArgs a = dargs ? dargs[mk] : a0;
+    const double *nrm_in = nrm_parts + (size_t)mk * kPartStride + (size_t)a.nrm_buf * kRedBlocks;
     __shared__ double Bm[kMat], B2[kMat], B4[kMat], B6[kMat], Um[kMat], Vm[kMat];
     __shared__ double mult[kLd];
     __shared__ double sh_tau_u, sh_norm, sh_hsub;
@@ -102,7 +109,7 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
         const bool live = (c->brk == 0) && !c->beta_zero;
         if (live) {
             double tot[1];
-            sum_partials<1>(tot, a.nrm_in, a.n_nrm_in, red);
+            sum_partials<1>(tot, nrm_in, a.n_nrm_in, red);
             finalize_column(c, a.built, tot[0], tid == 0, red);
         }
         __syncthreads();
@@ -110,13 +117,14 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
 
     if (tid == 0) {
 #pragma clang fp contract(off)
+        c->t_out = a.t_out;
         double tau_u;
         int lands;
         if (a.mode == XRB_REPLAY) {
             tau_u = a.rep.tau;
             lands = (a.rep.flags >> 1) & 1;
         } else {
-            const double rem = c->t_out - c->t;
+            const double rem = a.t_out - c->t;
             if (c->tau >= rem * (1.0 - 1e-12)) {
                 tau_u = rem;
                 lands = 1;
@@ -399,8 +407,9 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *c, CtlArgs a) {
 
 }  // namespace
 
-void launch_controller(PhiCtl *ctl, const CtlArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(k_controller, dim3(1), dim3(kBlock), 0, s, ctl, a);
+void launch_controller(PhiCtl *ctl, const CtlArgs &a, const CtlArgs *dargs, double *nrm_parts,
+                       const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_controller, dim3(b.nm), dim3(kBlock), 0, s, ctl, a, dargs, nrm_parts, b);
 }
 
 }  // namespace xrb

@@ -1,8 +1,9 @@
 // Vector kernels of phipm_simul_iom2 (Alg. 1): the IOM2 two-term update
 // with the norm that yields h_{j+1,j}, the w_j recurrence when no product is
-// needed, the substep combination y_{k+1} (eq. 3.17), input norms, and stage
-// linear combinations of the schemes.  Reductions are deterministic
-// (partials summed in block order by the consuming kernel).
+// needed, the substep combination y_{k+1} (eq. 3.17), input norms, output
+// copies and stage linear combinations of the schemes.  Reductions are
+// deterministic (partials summed in block order by the consuming kernel).
+// All kernels run over nm members (blockIdx.y), see Batch.
 #include "column.h"
 #include "reduce.h"
 #include "xrb_internal.h"
@@ -23,16 +24,29 @@ constexpr int kMaxLin = 6;
 
 struct LinArgs {
     int k;
+    unsigned dtmask;
     const double *vec[kMaxLin];
     double c[kMaxLin];
 };
 
-__global__ void __launch_bounds__(kBlock) k_lincomb(int n4, double *__restrict__ out, LinArgs a) {
+__global__ void __launch_bounds__(kBlock) k_lincomb(int n4, double *__restrict__ out, LinArgs a,
+                                                    Batch bt) {
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    double c[kMaxLin];
+    const double *v[kMaxLin];
+    const double dk = bt.dtk ? bt.dtk[mk] : 1.0;
+#pragma unroll
+    for (int k = 0; k < kMaxLin; ++k) {
+        c[k] = ((a.dtmask >> k) & 1) ? a.c[k] * dk : a.c[k];
+        v[k] = (k < a.k) ? member_ptr(a.vec[k], bt.ws, mk) : nullptr;
+    }
+    out = member_ptr(out, bt.ws, mk);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kMaxLin; ++k)
-            if (k < a.k) acc += a.c[k] * a.vec[k][i];
+            if (k < a.k) acc += c[k] * v[k][i];
         out[i] = acc;
     }
 }
@@ -45,39 +59,53 @@ struct LinDevArgs {
 
 template <bool NORM>
 __global__ void __launch_bounds__(kRedBlock) k_lincomb_dev(int n4, double *__restrict__ out,
-                                                           LinDevArgs a, double *nrm_out) {
+                                                           LinDevArgs a, double *nrm_out,
+                                                           Batch bt) {
     __shared__ double lds[16];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
     double c[kPmax + 1];
+    const double *v[kPmax + 1];
 #pragma unroll
-    for (int k = 0; k <= kPmax; ++k) c[k] = (k < a.k) ? *a.coef[k] : 0.0;
+    for (int k = 0; k <= kPmax; ++k) {
+        c[k] = (k < a.k) ? *ctl_field(a.coef[k], mk) : 0.0;
+        v[k] = (k < a.k) ? member_ptr(a.vec[k], bt.ws, mk) : nullptr;
+    }
+    out = member_ptr(out, bt.ws, mk);
     double r = 0.0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k <= kPmax; ++k)
-            if (k < a.k) acc += c[k] * a.vec[k][i];
+            if (k < a.k) acc += c[k] * v[k][i];
         out[i] = acc;
         if (NORM) r += acc * acc;
     }
     if (!NORM) return;
-    double v[1] = {r};
-    block_sum_all<1>(v, lds);
-    put_partials<1>(v, nrm_out);
+    double vv[1] = {r};
+    block_sum_all<1>(vv, lds);
+    put_partials<1>(vv, nrm_out + (size_t)mk * kPartStride);
 }
 
 // IOM2 update of column j (classical two-term Gram-Schmidt) and its norm.
 __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double *__restrict__ w,
                                                            const double *__restrict__ rj,
                                                            const double *__restrict__ rjm1,
-                                                           PhiCtl *ctl, const double *nrm_in,
+                                                           PhiCtl *ctl0, const double *nrm_in,
                                                            int np_nrm, const double *dot_in,
-                                                           int np_dot, double *nrm_out) {
+                                                           int np_dot, double *nrm_out, Batch bt) {
     __shared__ double lds[64];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    PhiCtl *ctl = ctl_member(ctl0, mk);
     // a new basis (j = 0) starts fresh; later columns stop after a breakdown
     if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
+    w = member_ptr(w, bt.ws, mk);
+    rj = member_ptr(rj, bt.ws, mk);
+    rjm1 = member_ptr(rjm1, bt.ws, mk);
     double nn[1], dd[2];
-    sum_partials<1>(nn, nrm_in, np_nrm, lds);
-    sum_partials<2>(dd, dot_in, np_dot, lds);
+    sum_partials<1>(nn, nrm_in + (size_t)mk * kPartStride, np_nrm, lds);
+    sum_partials<2>(dd, dot_in + (size_t)mk * kPartStride, np_dot, lds);
     const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
     const ColumnScale cs = finalize_column(ctl, j, nn[0], writer, lds);
     if (cs.stop) return;
@@ -100,26 +128,38 @@ __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double
     }
     double v[1] = {r};
     block_sum_all<1>(v, lds);
-    put_partials<1>(v, nrm_out);
+    put_partials<1>(v, nrm_out + (size_t)mk * kPartStride);
 }
 
 struct CombArgs {
-    int p, meff, corr;
+    int p;
     const double *w[kPmax];   // w_0..w_{p-1}, nullptr = zero (skipped)
     const double *V;          // raw basis, vectors of length n4
 };
 
 __global__ void __launch_bounds__(kBlock) k_combine(int n4, double *__restrict__ y, CombArgs a,
-                                                    const PhiCtl *__restrict__ ctl) {
+                                                    const PhiCtl *__restrict__ ctl0, Batch bt) {
     __shared__ double cf[kPmax + kMmax + 2];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const PhiCtl *ctl = ctl0 + mk;
     for (int k = threadIdx.x; k < kPmax + kMmax + 2; k += blockDim.x) cf[k] = ctl->ycoef[k];
+    const int meff = ctl->dec.m_eff;
     __syncthreads();
-    const int nb = a.meff + (a.corr ? 1 : 0);
+    const int nb = meff > 0 ? meff + 1 : 0;
+    y = member_ptr(y, bt.ws, mk);
+    // per-member zero flags of w_j ride in the plan entry (bit j+1)
+    const int zmask = bt.pred.plan ? (bt.pred.plan[kPlanW * mk + PF_COMB] >> 1) : 0;
+    const double *w[kPmax];
+#pragma unroll
+    for (int j = 0; j < kPmax; ++j)
+        w[j] = (j < a.p && !((zmask >> j) & 1)) ? member_ptr(a.w[j], bt.ws, mk) : nullptr;
+    const double *V = member_ptr(a.V, bt.ws, mk);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int j = 0; j < a.p; ++j)
-            if (a.w[j]) acc += cf[j] * a.w[j][i];
-        const double *vb = a.V + i;
+            if (w[j]) acc += cf[j] * w[j][i];
+        const double *vb = V + i;
         for (int k = 0; k < nb; ++k) acc += cf[a.p + k] * vb[(size_t)k * n4];
         y[i] = acc;
     }
@@ -130,47 +170,75 @@ struct NormArgs {
     const double *vec[kPmax + 1];
 };
 
-__global__ void __launch_bounds__(kRedBlock) k_norms(int n4, NormArgs a, double *parts) {
+__global__ void __launch_bounds__(kRedBlock) k_norms(int n4, NormArgs a, double *parts, Batch bt) {
     __shared__ double lds[16 * (kPmax + 1)];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const double *v[kPmax + 1];
     double r[kPmax + 1];
 #pragma unroll
-    for (int k = 0; k <= kPmax; ++k) r[k] = 0.0;
+    for (int k = 0; k <= kPmax; ++k) {
+        r[k] = 0.0;
+        v[k] = (k < a.nv) ? member_ptr(a.vec[k], bt.ws, mk) : nullptr;
+    }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
 #pragma unroll
         for (int k = 0; k <= kPmax; ++k) {
             if (k < a.nv) {
-                const double v = a.vec[k][i];
-                r[k] += v * v;
+                const double x = v[k][i];
+                r[k] += x * x;
             }
         }
     }
     block_sum_all<kPmax + 1>(r, lds);
+    double *pk = parts + (size_t)mk * kVPartStride;
     if (threadIdx.x == 0)
-        for (int k = 0; k < a.nv; ++k) parts[blockIdx.x * a.nv + k] = r[k];
+        for (int k = 0; k < a.nv; ++k) pk[blockIdx.x * a.nv + k] = r[k];
 }
 
-__global__ void __launch_bounds__(kBlock) k_phi_init(PhiCtl *c, int m0, double tau0,
-                                                     double tol_rel, const double *parts, int np,
-                                                     int nv, double *vn2) {
+struct CopyArgs {
+    double *slot[8];
+};
+
+__global__ void __launch_bounds__(kBlock) k_copy_out(int n4, const double *__restrict__ y,
+                                                     CopyArgs a, Batch bt) {
+    const int mk = blockIdx.y;
+    const int which = bt.pred.plan ? bt.pred.plan[kPlanW * mk + PF_COPY] - 1 : 0;
+    if (which < 0 || which >= 8) return;
+    y = member_ptr(y, bt.ws, mk);
+    double *o = member_ptr(a.slot[which], bt.ws, mk);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x)
+        o[i] = y[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_phi_init(PhiCtl *ctl0, int m0, const int32_t *m0k,
+                                                     double tau0, double tol_rel,
+                                                     const double *parts, int np, int nv,
+                                                     double *vn2, Batch bt) {
     __shared__ double lds[16 * (kPmax + 1)];
+    const int mk = blockIdx.x;
+    if (!member_active(bt.pred, mk)) return;
+    PhiCtl *c = ctl0 + mk;
+    const double *pk = parts + (size_t)mk * kVPartStride;
     double tot[kPmax + 1];
 #pragma unroll
     for (int k = 0; k <= kPmax; ++k) tot[k] = 0.0;
     for (int b = threadIdx.x; b < np; b += blockDim.x)
-        for (int k = 0; k < nv; ++k) tot[k] += parts[b * nv + k];
+        for (int k = 0; k < nv; ++k) tot[k] += pk[b * nv + k];
     block_sum_all<kPmax + 1>(tot, lds);
     if (threadIdx.x != 0) return;
     double s = 0.0;
     for (int k = 0; k < nv; ++k) {
-        vn2[k] = tot[k];
+        vn2[mk * (kPmax + 1) + k] = tot[k];
         const double r = sqrt(tot[k]);
         s = r > s ? r : s;
     }
+    const int m = m0k ? m0k[mk] : m0;
     c->tol_abs = tol_rel * s;
     c->t = 0.0;
     c->tau = tau0;
-    c->m = m0;
-    c->q = (m0 / 4.0 > 1.0) ? m0 / 4.0 : 1.0;
+    c->m = m;
+    c->q = (m / 4.0 > 1.0) ? m / 4.0 : 1.0;
     c->kappa = 2.0;
     c->have_prev = 0;
     c->prev_m = 0;
@@ -181,27 +249,27 @@ __global__ void __launch_bounds__(kBlock) k_phi_init(PhiCtl *c, int m0, double t
     c->brk = 0;
     c->beta_zero = 0;
     c->dec.status = 0;
-}
-
-__global__ void k_set_tout(PhiCtl *c, double t_out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) c->t_out = t_out;
+    c->dec.m_eff = 0;
 }
 
 }  // namespace
 
 void launch_lincomb(int n4, double *out, int k, const double *const *vec, const double *c,
-                    hipStream_t s) {
+                    unsigned dtmask, const Batch &b, hipStream_t s) {
     LinArgs a{};
     a.k = k;
+    a.dtmask = dtmask;
     for (int i = 0; i < k && i < kMaxLin; ++i) {
         a.vec[i] = vec[i];
         a.c[i] = c[i];
     }
-    hipLaunchKernelGGL(k_lincomb, dim3(grid_elems(n4)), dim3(kBlock), 0, s, n4, out, a);
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_elems(n4), b.nm), dim3(kBlock), 0, s, n4, out, a, b);
 }
 
 int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
-                       const double *const *coef, double *nrm_out, hipStream_t s) {
+                       const double *const *coef, PhiCtl *ctl0, double *nrm_out, const Batch &b,
+                       hipStream_t s) {
+    (void)ctl0;
     LinDevArgs a{};
     a.k = k;
     for (int i = 0; i < k && i <= kPmax; ++i) {
@@ -209,54 +277,57 @@ int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
         a.coef[i] = coef[i];
     }
     const int n4 = 4 * n;
-    const int grid = red_grid(n4, kRedBlock);
+    const int grid = red_parts(n);
     if (nrm_out)
-        hipLaunchKernelGGL(k_lincomb_dev<true>, dim3(grid), dim3(kRedBlock), 0, s, n4, out, a,
-                           nrm_out);
+        hipLaunchKernelGGL(k_lincomb_dev<true>, dim3(grid, b.nm), dim3(kRedBlock), 0, s, n4, out,
+                           a, nrm_out, b);
     else
-        hipLaunchKernelGGL(k_lincomb_dev<false>, dim3(grid), dim3(kRedBlock), 0, s, n4, out, a,
-                           nrm_out);
+        hipLaunchKernelGGL(k_lincomb_dev<false>, dim3(grid, b.nm), dim3(kRedBlock), 0, s, n4, out,
+                           a, nrm_out, b);
     return grid;
 }
 
 int launch_iom2_update(int n, int j, double *rjp1, const double *rj, const double *rjm1,
                        PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
-                       int np_dot, double *nrm_out, hipStream_t s) {
+                       int np_dot, double *nrm_out, const Batch &b, hipStream_t s) {
     const int n4 = 4 * n;
-    const int grid = red_grid(n4, kRedBlock);
-    hipLaunchKernelGGL(k_iom2_update, dim3(grid), dim3(kRedBlock), 0, s, n4, j, rjp1, rj, rjm1,
-                       ctl, nrm_in, np_nrm, dot_in, np_dot, nrm_out);
+    const int grid = red_parts(n);
+    hipLaunchKernelGGL(k_iom2_update, dim3(grid, b.nm), dim3(kRedBlock), 0, s, n4, j, rjp1, rj,
+                       rjm1, ctl, nrm_in, np_nrm, dot_in, np_dot, nrm_out, b);
     return grid;
 }
 
 void launch_combine(int n4, double *y, int p, const double *const *w, const int *wzero,
-                    const double *V, int meff, int corr, PhiCtl *ctl, hipStream_t s) {
+                    const double *V, PhiCtl *ctl, const Batch &b, hipStream_t s) {
     CombArgs a{};
     a.p = p;
-    a.meff = meff;
-    a.corr = corr;
     for (int j = 0; j < p; ++j) a.w[j] = wzero[j] ? nullptr : w[j];
     a.V = V;
-    hipLaunchKernelGGL(k_combine, dim3(grid_elems(n4)), dim3(kBlock), 0, s, n4, y, a, ctl);
+    hipLaunchKernelGGL(k_combine, dim3(grid_elems(n4), b.nm), dim3(kBlock), 0, s, n4, y, a, ctl, b);
 }
 
-int launch_norms(int n, int nv, const double *const *vec, double *parts, hipStream_t s) {
+int launch_norms(int n, int nv, const double *const *vec, double *parts, const Batch &b,
+                 hipStream_t s) {
     NormArgs a{};
     a.nv = nv;
     for (int k = 0; k < nv && k <= kPmax; ++k) a.vec[k] = vec[k];
-    const int grid = red_grid(4 * n, kRedBlock);
-    hipLaunchKernelGGL(k_norms, dim3(grid), dim3(kRedBlock), 0, s, 4 * n, a, parts);
+    const int grid = red_parts(n);
+    hipLaunchKernelGGL(k_norms, dim3(grid, b.nm), dim3(kRedBlock), 0, s, 4 * n, a, parts, b);
     return grid;
 }
 
-void launch_phi_init(PhiCtl *ctl, int m0, double tau0, double tol_rel, const double *parts,
-                     int np, int nv, double *vnorm2_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_phi_init, dim3(1), dim3(kBlock), 0, s, ctl, m0, tau0, tol_rel, parts, np,
-                       nv, vnorm2_out);
+void launch_copy_out(int n4, const double *y, double *const *slots, const Batch &b,
+                     hipStream_t s) {
+    CopyArgs a{};
+    for (int k = 0; k < 8; ++k) a.slot[k] = slots[k];
+    hipLaunchKernelGGL(k_copy_out, dim3(grid_elems(n4), b.nm), dim3(kBlock), 0, s, n4, y, a, b);
 }
 
-void launch_set_tout(PhiCtl *ctl, double t_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_tout, dim3(1), dim3(64), 0, s, ctl, t_out);
+void launch_phi_init(PhiCtl *ctl, int m0, const int32_t *m0k, double tau0, double tol_rel,
+                     const double *parts, int np, int nv, double *vnorm2, const Batch &b,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_phi_init, dim3(b.nm), dim3(kBlock), 0, s, ctl, m0, m0k, tau0, tol_rel,
+                       parts, np, nv, vnorm2, b);
 }
 
 }  // namespace xrb

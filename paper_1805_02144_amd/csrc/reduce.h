@@ -10,16 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "xrb_internal.h"
+
 namespace xrb {
-
-constexpr int kRedBlocks = 512;    // cap on partials (blocks) per reduction
-
-// blocks of a reducing kernel over `items` work items, `block` per block
-inline int red_grid(int items, int block) {
-    int g = (items + block - 1) / block;
-    if (g < 1) g = 1;
-    return g > kRedBlocks ? kRedBlocks : g;
-}
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -48,7 +41,8 @@ __device__ inline void block_sum_all(double (&v)[NV], double *lds) {
     __syncthreads();
 }
 
-// Write this block's partials (thread 0 after block_sum_all).
+// Write this block's partials (thread 0 after block_sum_all); parts is the
+// calling member's buffer.
 template <int NV>
 __device__ inline void put_partials(const double (&v)[NV], double *parts) {
     if (threadIdx.x == 0) {

@@ -37,7 +37,11 @@ __device__ inline int cell0() { return (int)((blockIdx.x * blockDim.x + threadId
 __device__ inline int cell_stride() { return (int)((gridDim.x * blockDim.x) / kLanes); }
 
 __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restrict__ psi,
-                                              double *__restrict__ out) {
+                                              double *__restrict__ out, Batch bt) {
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    psi = member_ptr(psi, bt.ws, mk);
+    out = member_ptr(out, bt.ws, mk);
     const int n = M.n;
     const int s = threadIdx.x & (kLanes - 1);
     for (int i = cell0(); i < n; i += cell_stride()) {
@@ -52,7 +56,11 @@ __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restric
 }
 
 __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__restrict__ u,
-                                                   double *__restrict__ eta) {
+                                                   double *__restrict__ eta, Batch bt) {
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    u = member_ptr(u, bt.ws, mk);
+    eta = member_ptr(eta, bt.ws, mk);
     const int n = M.n;
     const int s = threadIdx.x & (kLanes - 1);
     for (int i = cell0(); i < n; i += cell_stride()) {
@@ -69,7 +77,12 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
 
 __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict__ u,
                                              const double *__restrict__ lu,
-                                             double *__restrict__ f) {
+                                             double *__restrict__ f, Batch bt) {
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    u = member_ptr(u, bt.ws, mk);
+    lu = member_ptr(lu, bt.ws, mk);
+    f = member_ptr(f, bt.ws, mk);
     const int n = M.n;
     const double g = M.g;
     const int s = threadIdx.x & (kLanes - 1);
@@ -110,17 +123,27 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 // out = dt*J(u) x + sum_k c_k v_k, with an optional reduction epilogue
 // (IOM2: raw dot partials; recurrence: norm partials).
 template <int EPI>
-__global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a) {
+__global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
     const int n = M.n;
-    const double g = M.g, nu = M.nu, sc = a.dt;
+    const double g = M.g, nu = M.nu;
+    const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
     const int s = threadIdx.x & (kLanes - 1);
     double cax[kPmax];
+    const double *axv[kPmax];
 #pragma unroll
-    for (int k = 0; k < kPmax; ++k) cax[k] = (k < a.naxpy) ? *a.axc[k] : 0.0;
-    const double *__restrict__ u = a.u;
-    const double *__restrict__ x = a.x;
-    const double *__restrict__ lx = a.lx;
+    for (int k = 0; k < kPmax; ++k) {
+        cax[k] = (k < a.naxpy) ? *ctl_field(a.axc[k], mk) : 0.0;
+        axv[k] = (k < a.naxpy) ? member_ptr(a.axv[k], bt.ws, mk) : nullptr;
+    }
+    const double *__restrict__ u = member_ptr(a.u, bt.ws, mk);
+    const double *__restrict__ x = member_ptr(a.x, bt.ws, mk);
+    const double *__restrict__ lx = member_ptr(a.lx, bt.ws, mk);
+    const double *__restrict__ etak = member_ptr(a.eta, bt.ws, mk);
+    double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
+    const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
     double r0 = 0.0, r1 = 0.0;   // this lane's reduction partials
     for (int i = cell0(); i < n; i += cell_stride()) {
         const bool edge = s < 6;
@@ -147,7 +170,7 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a) {
         const double nx = M.nx[i], ny = M.ny[i], nz = M.nz[i];
         const double gr = nx * gx + ny * gy0 + nz * gz0;
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
-        const double eta = a.eta[i];
+        const double eta = etak[i];
         // J_v x: -(V.x) (n x u);  J_r x: -eta (n x x) - nu L^2 x;
         // J_m x: -G(u.x + g x_h), -D(h x + x_h u)
         const double pux = ny * uz - nz * uy, puy = nz * ux - nx * uz, puz = nx * uy - ny * ux;
@@ -162,12 +185,12 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a) {
             double ob = o[s];
 #pragma unroll
             for (int k = 0; k < kPmax; ++k)
-                if (k < a.naxpy) ob += cax[k] * a.axv[k][oi];
-            a.out[oi] = ob;
+                if (k < a.naxpy) ob += cax[k] * axv[k][oi];
+            outk[oi] = ob;
             if (EPI == kEpiIom2) {
                 const double xs = s == 0 ? xx : (s == 1 ? xy : (s == 2 ? xz : xh));
                 r0 += ob * xs;
-                if (a.rjm1) r1 += ob * a.rjm1[oi];
+                if (rjm1) r1 += ob * rjm1[oi];
             } else if (EPI == kEpiNorm) {
                 r0 += ob * ob;
             }
@@ -176,38 +199,41 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a) {
     if (EPI == kEpiIom2) {
         double v[2] = {r0, r1};
         block_sum_all<2>(v, lds);
-        put_partials<2>(v, a.dot_out);
+        put_partials<2>(v, a.dot_out + (size_t)mk * kPartStride);
     } else if (EPI == kEpiNorm) {
         double v[1] = {r0};
         block_sum_all<1>(v, lds);
-        put_partials<1>(v, a.nrm_out);
+        put_partials<1>(v, a.nrm_out + (size_t)mk * kPartStride);
     }
 }
 
 }  // namespace
 
-void launch_lap4(const DevMesh &M, const double *psi, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_lap4, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, psi, out);
+void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_lap4, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, psi, out, b);
 }
 
-void launch_linearize(const DevMesh &M, const double *u, double *eta, hipStream_t s) {
-    hipLaunchKernelGGL(k_linearize, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, u, eta);
+void launch_linearize(const DevMesh &M, const double *u, double *eta, const Batch &b,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_linearize, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, u, eta, b);
 }
 
-void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, hipStream_t s) {
-    hipLaunchKernelGGL(k_rhs, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, u, lu, f);
+void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, const Batch &b,
+                hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, u, lu, f, b);
 }
 
-int launch_jv(const DevMesh &M, const JvArgs &a, int epi, hipStream_t s) {
+int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
     if (epi == kEpiNone) {
-        hipLaunchKernelGGL(k_jv<kEpiNone>, dim3(cells_grid(M.n, 256)), dim3(256), 0, s, M, a);
+        hipLaunchKernelGGL(k_jv<kEpiNone>, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, a,
+                           b);
         return 0;
     }
-    const int grid = red_grid(M.n * kLanes, 256);
+    const int grid = red_parts(M.n);
     if (epi == kEpiIom2)
-        hipLaunchKernelGGL(k_jv<kEpiIom2>, dim3(grid), dim3(256), 0, s, M, a);
+        hipLaunchKernelGGL(k_jv<kEpiIom2>, dim3(grid, b.nm), dim3(256), 0, s, M, a, b);
     else
-        hipLaunchKernelGGL(k_jv<kEpiNorm>, dim3(grid), dim3(256), 0, s, M, a);
+        hipLaunchKernelGGL(k_jv<kEpiNorm>, dim3(grid, b.nm), dim3(256), 0, s, M, a, b);
     return grid;
 }
 

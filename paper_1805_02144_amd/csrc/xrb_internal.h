@@ -57,6 +57,7 @@ struct PhiCtl {
     double rec_coef[kPmax + 1];      // t^l / l! at the current point
     double ycoef[kPmax + kMmax + 2]; // combine coefficients of an accepted attempt
     Decision dec;
+    double pad[6];                   // keeps sizeof a multiple of 64 bytes
 };
 
 // Replay entry or sentinel passed to the controller kernel.
@@ -67,20 +68,95 @@ struct ReplayIn {
     int32_t active;
 };
 
+// ---------------- batching ----------------
+// Every kernel runs over nm members (member k = blockIdx.y).  Vector
+// arguments of member k are the member-0 pointer plus k * ws doubles, the
+// phi state is ctl + k, reduction partials are offset by k * kPartStride.
+// A launch may carry a per-member predicate read from a plan table that the
+// host uploads once per round; members for which it is false return at once.
+enum PlanField {
+    PF_IOM2_LO = 0,   // IOM2 column j runs iff plan[lo] <= j < plan[hi]
+    PF_IOM2_HI = 1,
+    PF_REC_PROD = 2,  // bit (j-1): w_j of the recurrence needs the product A w_{j-1}
+    PF_REC_SUM = 3,   // bit (j-1): w_j is a pure sum of input terms
+    PF_CTL = 4,       // member attempts a substep this round
+    PF_COMB = 5,      // member accepted: combine
+    PF_COPY = 6,      // member reached an output time: copy y out (value = slot + 1)
+    PF_INIT = 7,      // member starts this phi evaluation
+    kPlanW = 8
+};
+constexpr int kRedBlocks = 512;                    // cap on blocks (partials) of a reduction
+constexpr int kPartStride = 2 * kRedBlocks;        // per-member doubles: dot or norm partials
+constexpr int kVPartStride = (kPmax + 1) * kRedBlocks;   // per-member doubles: input norms
+
+// blocks of a reducing kernel over `items` work items, `block` per block
+inline int red_grid(int items, int block) {
+    int g = (items + block - 1) / block;
+    if (g < 1) g = 1;
+    return g > kRedBlocks ? kRedBlocks : g;
+}
+
+// Every reducing kernel launches red_parts(n) blocks on an n-cell grid (so
+// every producer of a partial family writes the same number of partials).
+inline int red_parts(int n) { return red_grid(8 * n, 256); }
+
+template <class T>
+__host__ __device__ inline T *member_ptr(T *p, int64_t stride, int k) {
+    return p ? p + stride * k : p;
+}
+template <class T>
+__device__ inline T *ctl_member(T *c, int k) {
+    return c + k;
+}
+// a coefficient that lives inside member 0's PhiCtl, moved to member k's
+__device__ inline const double *ctl_field(const double *p, int k) {
+    return (const double *)((const char *)p + (size_t)k * sizeof(PhiCtl));
+}
+
+struct Pred {
+    const int32_t *plan = nullptr;   // [nm][kPlanW]; nullptr = all members active
+    int field = 0;
+    int j = 0;
+};
+
+__device__ inline bool member_active(const Pred &p, int k) {
+    if (!p.plan) return true;
+    const int32_t *q = p.plan + kPlanW * k;
+    switch (p.field) {
+        case PF_IOM2_LO:
+            return q[PF_IOM2_LO] <= p.j && p.j < q[PF_IOM2_HI];
+        case PF_REC_PROD:
+        case PF_REC_SUM:
+            return ((q[p.field] >> (p.j - 1)) & 1) != 0;
+        default:
+            return q[p.field] != 0;
+    }
+}
+
+struct Batch {
+    int nm = 1;
+    int64_t ws = 0;        // member stride of vector arguments (doubles)
+    Pred pred;
+    const double *dtk = nullptr;   // per-member step sizes (device), used where noted
+};
+
 // ---------------- kernel launchers (stream-ordered) ----------------
 // Reductions: a reducing kernel writes one partial per block and its
 // launcher returns the block count; the next kernel that needs the total
 // sums those partials (see reduce.h).
 
 // out = L psi (4 components), raw input
-void launch_lap4(const DevMesh &M, const double *psi, double *out, hipStream_t s);
+void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s);
 // eta = V.u + f
-void launch_linearize(const DevMesh &M, const double *u, double *eta, hipStream_t s);
+void launch_linearize(const DevMesh &M, const double *u, double *eta, const Batch &b,
+                      hipStream_t s);
 // f = F(u), needs lu = L u (4 components)
-void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, hipStream_t s);
+void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, const Batch &b,
+                hipStream_t s);
 
 // Generic Jacobian product
-//   out = dt * J(u) x  +  sum_k coef[k] * axv[k]
+//   out = dt_k * J(u) x  +  sum_k coef[k] * axv[k]
+// (dt_k = b.dtk[member] when b.dtk is set, else a.dt)
 // kEpiNone : plain.
 // kEpiNorm : partials of ||out||^2 into nrm_out.
 // kEpiIom2 : column j of IOM2 on the raw basis vector x = R_j: partials of
@@ -96,7 +172,7 @@ struct JvArgs {
     double *out = nullptr;
     int naxpy = 0;
     const double *axv[kPmax] = {};
-    const double *axc[kPmax] = {};  // device pointers to coefficients
+    const double *axc[kPmax] = {};  // device pointers to coefficients, in PhiCtl of member 0
     // IOM2
     int j = 0;
     const double *rjm1 = nullptr;
@@ -104,15 +180,16 @@ struct JvArgs {
     double *dot_out = nullptr;
     double *nrm_out = nullptr;
 };
-int launch_jv(const DevMesh &M, const JvArgs &a, int epi, hipStream_t s);
+int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s);
 
-// out = sum_k coef[k] * vec[k] (device coefficient pointers); nrm_out
-// (nullable) receives partials of ||out||^2
+// out = sum_k coef[k] * vec[k] (coefficients inside PhiCtl, offset per member);
+// nrm_out (nullable) receives partials of ||out||^2
 int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
-                       const double *const *coef, double *nrm_out, hipStream_t s);
-// out = sum_k c[k] * vec[k], host coefficients (k <= 6), length n4
+                       const double *const *coef, PhiCtl *ctl0, double *nrm_out,
+                       const Batch &b, hipStream_t s);
+// out = sum_i c[i] * vec[i] (c[i] times dt_k when bit i of dtmask is set), length n4
 void launch_lincomb(int n4, double *out, int k, const double *const *vec, const double *c,
-                    hipStream_t s);
+                    unsigned dtmask, const Batch &b, hipStream_t s);
 // IOM2 update of column j.  Prologue: finalise the column scale sigma_j from
 // the norm partials of R_j (beta for j = 0, else h_{j,j-1} with the
 // breakdown test), then H[j][j] = sigma_j^2 <w, R_j>, H[j-1][j] =
@@ -122,12 +199,17 @@ void launch_lincomb(int n4, double *out, int k, const double *const *vec, const 
 // nrm_in and nrm_out are different buffers (ping-pong).
 int launch_iom2_update(int n, int j, double *rjp1, const double *rj, const double *rjm1,
                        PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
-                       int np_dot, double *nrm_out, hipStream_t s);
+                       int np_dot, double *nrm_out, const Batch &b, hipStream_t s);
 // y = sum_{j<p, !wzero} ycoef[j] w_j + sum_{k<meff} ycoef[p+k] R_k + ycoef[p+meff] R_meff
+// (meff read from the member's decision)
 void launch_combine(int n4, double *y, int p, const double *const *w, const int *wzero,
-                    const double *V, int meff, int corr, PhiCtl *ctl, hipStream_t s);
+                    const double *V, PhiCtl *ctl, const Batch &b, hipStream_t s);
 // partials of ||vec_k||^2, k < nv (<= kPmax+1), into parts[b*nv + k]
-int launch_norms(int n, int nv, const double *const *vec, double *parts, hipStream_t s);
+int launch_norms(int n, int nv, const double *const *vec, double *parts, const Batch &b,
+                 hipStream_t s);
+// out_slot[plan[PF_COPY]-1] <- y for members whose plan[PF_COPY] > 0
+void launch_copy_out(int n4, const double *y, double *const *slots, const Batch &b,
+                     hipStream_t s);
 
 struct CtlArgs {
     int m;                // Krylov size requested for this attempt
@@ -136,22 +218,25 @@ struct CtlArgs {
     int m_max;
     int wp_zero;          // w_p is the zero vector (symbolic)
     int built;            // IOM2 columns built at this point
+    int nrm_buf;          // which norm-partials buffer holds the last column's norm
+    int n_nrm_in;         // number of those partials
+    double t_out;         // output time of this substep
     double n4;            // vector length (cost model)
     double delta, gamma;
     ReplayIn rep;
-    const double *nrm_in; // partials of the last column's norm
-    int n_nrm_in;
 };
 // Small augmented-Hessenberg exponential + error estimate + (tau, m) controller
 // for the current attempt; writes ctl->dec and, on accept, the combine
-// coefficients and the next point's recurrence coefficients.
-void launch_controller(PhiCtl *ctl, const CtlArgs &a, hipStream_t s);
+// coefficients and the next point's recurrence coefficients.  Per-member
+// arguments come from `dargs` (device, [nm]) when set, else from `a`.
+void launch_controller(PhiCtl *ctl, const CtlArgs &a, const CtlArgs *dargs, double *nrm_parts,
+                       const Batch &b, hipStream_t s);
 // Initialise a call: t = 0, tau = rho_1, m, q, kappa, tol_abs from the norm
-// partials of the nv input vectors; vnorm2_out[k] = ||v_k||^2
-void launch_phi_init(PhiCtl *ctl, int m0, double tau0, double tol_rel, const double *parts,
-                     int np, int nv, double *vnorm2_out, hipStream_t s);
-// Start a new output interval
-void launch_set_tout(PhiCtl *ctl, double t_out, hipStream_t s);
+// partials of the nv input vectors; vnorm2[k*(kPmax+1) + l] = ||v_l||^2.
+// m0 per member from m0k (device, [nm]) when set, else m0.
+void launch_phi_init(PhiCtl *ctl, int m0, const int32_t *m0k, double tau0, double tol_rel,
+                     const double *parts, int np, int nv, double *vnorm2, const Batch &b,
+                     hipStream_t s);
 
 // ---------------- host geometry ----------------
 struct HostGeometry {

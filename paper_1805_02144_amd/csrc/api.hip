@@ -783,8 +783,8 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ctx->n = n;
     ctx->n4 = 4 * n;
     const size_t nd = (size_t)n;
-    // geometry in one allocation: 7 x [n][6] weights, 4 x [n] cell fields, [n][6] int32
-    const size_t dbl = 7 * 6 * nd + 4 * nd;
+    // geometry in one allocation: 3 x [n][6] edge scalars, [n][4] cell records, [n][6] int32
+    const size_t dbl = 3 * 6 * nd + 4 * nd;
     const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t);
     if (hipMalloc(&ctx->geo_mem, bytes) != hipSuccess) {
         delete ctx;
@@ -803,16 +803,14 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
         }
     };
     double *g = (double *)ctx->geo_mem;
-    const std::vector<double> *srcs[7] = {&geo.ax, &geo.ay, &geo.az, &geo.bx, &geo.by, &geo.bz, &geo.cl};
-    double *dst[7];
-    for (int k = 0; k < 7; ++k) {
+    const std::vector<double> *srcs[3] = {&geo.alpha, &geo.beta, &geo.cl};
+    double *dst[3];
+    for (int k = 0; k < 3; ++k) {
         dst[k] = g + (size_t)k * 6 * nd;
         ck(hipMemcpy(dst[k], srcs[k]->data(), sizeof(double) * 6 * nd, hipMemcpyHostToDevice));
     }
-    double *cellf = g + 7 * 6 * nd;
-    const std::vector<double> *cs[4] = {&geo.nx, &geo.ny, &geo.nz, &geo.cor};
-    for (int k = 0; k < 4; ++k)
-        ck(hipMemcpy(cellf + k * nd, cs[k]->data(), sizeof(double) * nd, hipMemcpyHostToDevice));
+    double *cen = g + 3 * 6 * nd;     // byte offset 144 n: 16-byte aligned
+    ck(hipMemcpy(cen, geo.cen.data(), sizeof(double) * 4 * nd, hipMemcpyHostToDevice));
     int32_t *nb = (int32_t *)(g + dbl);
     ck(hipMemcpy(nb, geo.nbr.data(), sizeof(int32_t) * 6 * nd, hipMemcpyHostToDevice));
     if (rc) {
@@ -824,10 +822,10 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     DevMesh &M = ctx->M;
     M.n = n;
     M.nbr = nb;
-    M.ax = dst[0]; M.ay = dst[1]; M.az = dst[2];
-    M.bx = dst[3]; M.by = dst[4]; M.bz = dst[5];
-    M.cl = dst[6];
-    M.nx = cellf; M.ny = cellf + nd; M.nz = cellf + 2 * nd; M.cor = cellf + 3 * nd;
+    M.alpha = dst[0];
+    M.beta = dst[1];
+    M.cl = dst[2];
+    M.cen = cen;
     M.nu = geo.nu;
     M.g = params->gravity;
     *out = ctx;

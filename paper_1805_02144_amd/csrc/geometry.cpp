@@ -2,7 +2,7 @@
 //
 // The paper writes the semi-discrete model with sparse gradient, divergence,
 // vorticity and Laplacian matrices on the Voronoi cells of the icosahedral
-// grid.  Here each cell i keeps, per neighbour slot s (edge e to cell j):
+// grid.  The flux-form operators use, per edge e from cell i to j,
 //   a_s = l_e n_e / (2 A_i)   (flux divergence: sum_s a_s . (F_i + F_j);
 //                              gradient: P_i sum_s a_s (psi_j - psi_i))
 //   b_s = l_e t_e / (2 A_i)   (circulation: sum_s b_s . (u_i + u_j))
@@ -10,8 +10,13 @@
 // with l_e the great-circle length of the Voronoi edge (between the two
 // corners that bound it), d_e the great-circle distance of the centres,
 // A_i the spherical area of the cell, n_e the unit tangent normal at the
-// edge direction (x_i + x_j)/|x_i + x_j| pointing from i to j, and
-// t_e = rhat_e x n_e.  Pentagon slot 5 gets zero weights.
+// edge direction rhat_e = (x_i + x_j)/|x_i + x_j| pointing from i to j, and
+// t_e = rhat_e x n_e.  On the unit sphere x_j - x_i is orthogonal to
+// x_i + x_j, so n_e = (x_j - x_i)/|x_j - x_i| and t_e = 2 (x_i x x_j) /
+// (|x_i + x_j| |x_j - x_i|): the kernels rebuild a_s and b_s from two
+// scalars per edge and the centres they already load,
+//   alpha_s = l_e / (2 A_i |x_j - x_i|),  beta_s = 2 alpha_s / |x_i + x_j|.
+// Pentagon slot 5 gets zero weights.
 #include <cmath>
 
 #include "xrb_internal.h"
@@ -24,16 +29,11 @@ struct V3 {
 };
 inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-inline V3 mul(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
 inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline V3 cross(V3 a, V3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 inline double len(V3 a) { return std::sqrt(dot(a, a)); }
-inline V3 unit(V3 a) {
-    double l = len(a);
-    return {a.x / l, a.y / l, a.z / l};
-}
 // angle between two unit vectors
 inline double angle(V3 a, V3 b) { return std::atan2(len(cross(a, b)), dot(a, b)); }
 // spherical excess of the unit-sphere triangle (a, b, c)
@@ -60,10 +60,8 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
     geo.n = (int)n;
     auto resize6 = [&](std::vector<double> &v) { v.assign(6 * (size_t)n, 0.0); };
     geo.nbr.assign(6 * (size_t)n, 0);
-    resize6(geo.ax); resize6(geo.ay); resize6(geo.az);
-    resize6(geo.bx); resize6(geo.by); resize6(geo.bz);
-    resize6(geo.cl);
-    geo.nx.resize(n); geo.ny.resize(n); geo.nz.resize(n); geo.cor.resize(n);
+    resize6(geo.alpha); resize6(geo.beta); resize6(geo.cl);
+    geo.cen.assign(4 * (size_t)n, 0.0);
 
     auto X = [&](int64_t i) { return V3{mesh.xyz[3 * i], mesh.xyz[3 * i + 1], mesh.xyz[3 * i + 2]}; };
     auto CRN = [&](int64_t i, int s) {
@@ -97,18 +95,15 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
             const V3 xj = X(j);
             const double le = R * angle(CRN(i, (s + d - 1) % d), CRN(i, s));
             const double de = R * angle(xi, xj);
-            const V3 rh = unit(add(xi, xj));
-            V3 dv = sub(xj, xi);
-            dv = sub(dv, mul(dot(dv, rh), rh));
-            const V3 ne = unit(dv);
-            const V3 te = cross(rh, ne);
-            const double w = le / (2.0 * area);
-            geo.ax[k] = w * ne.x; geo.ay[k] = w * ne.y; geo.az[k] = w * ne.z;
-            geo.bx[k] = w * te.x; geo.by[k] = w * te.y; geo.bz[k] = w * te.z;
+            const double chord = len(sub(xj, xi));
+            const double alpha = le / (2.0 * area * chord);
+            geo.alpha[k] = alpha;
+            geo.beta[k] = 2.0 * alpha / len(add(xi, xj));
             geo.cl[k] = le / (de * area);
         }
-        geo.nx[i] = xi.x; geo.ny[i] = xi.y; geo.nz[i] = xi.z;
-        geo.cor[i] = 2.0 * prm.omega * xi.z;
+        double *ce = &geo.cen[4 * (size_t)i];
+        ce[0] = xi.x; ce[1] = xi.y; ce[2] = xi.z;
+        ce[3] = 2.0 * prm.omega * xi.z;
     }
     const double dxbar = std::sqrt(4.0 * M_PI * R * R / (double)n);
     geo.nu = prm.gamma_h * dxbar * dxbar * dxbar * dxbar / prm.dt_e;

@@ -5,7 +5,7 @@
 //
 // Edge-parallel mapping: eight consecutive lanes serve one cell, lane s < 6
 // handling the edge to neighbour slot s (lanes 6 and 7 carry zero weights).
-// Each lane gathers its neighbour, forms its edge terms, and a fixed xor
+// Each lane gathers its neighbour, forms its edge terms, and a fixed DPP
 // butterfly over the eight lanes sums them (bitwise identical in all eight).
 // This gives eight times the memory-level parallelism of one thread per
 // cell, which the small grids need.  The two-ring dissipation stencil
@@ -25,11 +25,50 @@ inline int cells_grid(int n, int block) {
     return g < 1 ? 1 : g;
 }
 
+// Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the eight lanes of a cell: half-row mirror (lane i with 7-i),
+// then xor 1 and xor 2 inside each quad.  Every lane ends with the same
+// operands added in the same pairs (only commuted), so the eight results
+// are bitwise identical.
 __device__ inline double grp_sum(double v) {
-    v += __shfl_xor(v, 1, kLanes);
-    v += __shfl_xor(v, 2, kLanes);
-    v += __shfl_xor(v, 4, kLanes);
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
     return v;
+}
+
+// Cell record: unit centre and Coriolis parameter, two 16-byte loads.
+struct Cell {
+    double x, y, z, f;
+};
+__device__ inline Cell load_cell(const double *__restrict__ cen, int i) {
+    const double2 *p = reinterpret_cast<const double2 *>(cen) + 2 * (size_t)i;
+    const double2 a = p[0], b = p[1];
+    return {a.x, a.y, b.x, b.y};
+}
+
+// Flux and circulation weights of the edge i -> j rebuilt from its two
+// scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).  Lanes without an
+// edge pass alpha = beta = 0.
+struct EdgeW {
+    double ax, ay, az, bx, by, bz;
+};
+__device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al, double be) {
+    EdgeW w;
+    w.ax = al * (cj.x - ci.x);
+    w.ay = al * (cj.y - ci.y);
+    w.az = al * (cj.z - ci.z);
+    w.bx = be * (ci.y * cj.z - ci.z * cj.y);
+    w.by = be * (ci.z * cj.x - ci.x * cj.z);
+    w.bz = be * (ci.x * cj.y - ci.y * cj.x);
+    return w;
 }
 
 // first cell of this thread's group and the stride, in cells
@@ -64,14 +103,15 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
     const int n = M.n;
     const int s = threadIdx.x & (kLanes - 1);
     for (int i = cell0(); i < n; i += cell_stride()) {
-        const int e = 6 * i + (s < 6 ? s : 0);
-        const int j = s < 6 ? M.nbr[e] : i;
-        double z = 0.0;
-        if (s < 6)
-            z = M.bx[e] * (u[i] + u[j]) + M.by[e] * (u[n + i] + u[n + j]) +
-                M.bz[e] * (u[2 * n + i] + u[2 * n + j]);
+        const bool edge = s < 6;
+        const int e = 6 * i + (edge ? s : 0);
+        const int j = edge ? M.nbr[e] : i;
+        const Cell ci = load_cell(M.cen, i), cj = load_cell(M.cen, j);
+        const EdgeW w = edge_weights(ci, cj, 0.0, edge ? M.beta[e] : 0.0);
+        double z = w.bx * (u[i] + u[j]) + w.by * (u[n + i] + u[n + j]) +
+                   w.bz * (u[2 * n + i] + u[2 * n + j]);
         z = grp_sum(z);
-        if (s == 0) eta[i] = z + M.cor[i];
+        if (s == 0) eta[i] = z + ci.f;
     }
 }
 
@@ -92,8 +132,9 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         const int j = edge ? M.nbr[e] : i;
         const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], h = u[3 * n + i];
         const double vx = u[j], vy = u[n + j], vz = u[2 * n + j], hj = u[3 * n + j];
-        const double ax = edge ? M.ax[e] : 0.0, ay = edge ? M.ay[e] : 0.0, az = edge ? M.az[e] : 0.0;
-        const double bx = edge ? M.bx[e] : 0.0, by = edge ? M.by[e] : 0.0, bz = edge ? M.bz[e] : 0.0;
+        const Cell ci = load_cell(M.cen, i), cj = load_cell(M.cen, j);
+        const EdgeW w = edge_weights(ci, cj, edge ? M.alpha[e] : 0.0, edge ? M.beta[e] : 0.0);
+        const double ax = w.ax, ay = w.ay, az = w.az, bx = w.bx, by = w.by, bz = w.bz;
         const double c = edge ? M.cl[e] : 0.0;
         const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * h;
         const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * hj;
@@ -105,10 +146,10 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         double d[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) d[b] = grp_sum(c * (lu[b * n + j] - lu[b * n + i]));
-        const double nx = M.nx[i], ny = M.ny[i], nz = M.nz[i];
+        const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;       // tangent projection of grad E
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
-        const double eta = zt + M.cor[i];
+        const double eta = zt + ci.f;
         const double px = ny * uz - nz * uy, py = nz * ux - nx * uz, pz = nx * uy - ny * ux;
         const double nu = M.nu;
         double o[4];
@@ -153,8 +194,9 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
         const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
         const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
         const double wx = u[j], wy = u[n + j], wz = u[2 * n + j], wh = u[3 * n + j];
-        const double ax = edge ? M.ax[e] : 0.0, ay = edge ? M.ay[e] : 0.0, az = edge ? M.az[e] : 0.0;
-        const double bx = edge ? M.bx[e] : 0.0, by = edge ? M.by[e] : 0.0, bz = edge ? M.bz[e] : 0.0;
+        const Cell ci = load_cell(M.cen, i), cj = load_cell(M.cen, j);
+        const EdgeW w = edge_weights(ci, cj, edge ? M.alpha[e] : 0.0, edge ? M.beta[e] : 0.0);
+        const double ax = w.ax, ay = w.ay, az = w.az, bx = w.bx, by = w.by, bz = w.bz;
         const double c = edge ? M.cl[e] : 0.0;
         const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
         const double sj = wx * vx + wy * vy + wz * vz + g * vh;
@@ -167,7 +209,7 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
         double d[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) d[b] = grp_sum(c * (lx[b * n + j] - lx[b * n + i]));
-        const double nx = M.nx[i], ny = M.ny[i], nz = M.nz[i];
+        const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
         const double eta = etak[i];

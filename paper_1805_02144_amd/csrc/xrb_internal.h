@@ -16,18 +16,19 @@ constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix or
 
 // Geometry of the finite-volume operators, cell-major ([cell][slot], 6
 // slots): the eight lanes that share a cell in the edge-parallel kernels read
-// one contiguous 48-byte record per array.
-//   a_s = l_e n_{e,i} / (2 A_i)   divergence and gradient weights (3 comps)
-//   b_s = l_e t_{e,i} / (2 A_i)   vorticity (circulation) weights (3 comps)
-//   c_s = l_e / (d_e A_i)         Laplacian weights
+// one contiguous 48-byte record per array.  For the edge from cell i to
+// neighbour j (unit centres x_i, x_j), x_j - x_i is exactly tangent at the
+// edge midpoint direction, so the flux and circulation weights are
+//   a = l n_e / (2 A_i)  = alpha (x_j - x_i),  alpha = l / (2 A_i |x_j - x_i|)
+//   b = l t_e / (2 A_i)  = beta  (x_i x x_j),  beta  = 2 alpha / |x_i + x_j|
+// and the Laplacian weight is c = l / (d A_i).
 struct DevMesh {
     int n = 0;
     const int32_t *nbr = nullptr;                  // [n][6]
-    const double *ax = nullptr, *ay = nullptr, *az = nullptr;   // [n][6] each
-    const double *bx = nullptr, *by = nullptr, *bz = nullptr;
+    const double *alpha = nullptr;                 // [n][6]
+    const double *beta = nullptr;                  // [n][6]
     const double *cl = nullptr;                    // [n][6]
-    const double *nx = nullptr, *ny = nullptr, *nz = nullptr;   // [n] cell normals
-    const double *cor = nullptr;                   // [n] Coriolis 2 Omega sin(lat)
+    const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, Coriolis 2 Omega sin(lat)
     double nu = 0.0, g = 0.0;
 };
 
@@ -242,8 +243,8 @@ void launch_phi_init(PhiCtl *ctl, int m0, const int32_t *m0k, double tau0, doubl
 struct HostGeometry {
     int n = 0;
     std::vector<int32_t> nbr;                              // [n][6]
-    std::vector<double> ax, ay, az, bx, by, bz, cl;        // [n][6]
-    std::vector<double> nx, ny, nz, cor;                   // [n]
+    std::vector<double> alpha, beta, cl;                   // [n][6]
+    std::vector<double> cen;                               // [n][4] x, y, z, Coriolis
     double nu = 0.0;
 };
 int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,

@@ -49,7 +49,7 @@ class Schedule(C.Structure):
 class PhiOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("m_init", C.c_int), ("m_max", C.c_int),
                 ("delta", C.c_double), ("gamma", C.c_double), ("max_attempts", C.c_int),
-                ("mode", C.c_int), ("sched", C.POINTER(Schedule))]
+                ("mode", C.c_int), ("sched", C.POINTER(Schedule)), ("tape", C.c_void_p)]
 
 
 class PhiStats(C.Structure):
@@ -86,8 +86,14 @@ def lib():
         L.orc_swe_free.argtypes = [C.POINTER(Swe)]
         for f in ("orc_rhs",):
             getattr(L, f).argtypes = [C.POINTER(Swe), _dp, _dp]
-        for f in ("orc_jv", "orc_jtv"):
+        for f in ("orc_jv", "orc_jtv", "orc_ktv"):
             getattr(L, f).argtypes = [C.POINTER(Swe), _dp, _dp, _dp]
+        L.orc_phi_vjp_dense.argtypes = [C.c_int, _dp, C.c_int, C.POINTER(_dp), C.c_int, _dp,
+                                        C.POINTER(_dp), C.POINTER(_dp), C.POINTER(_dp), _dp,
+                                        C.POINTER(PhiOpts), C.POINTER(PhiStats),
+                                        C.POINTER(PhiStats)]
+        L.orc_step_vjp.argtypes = [C.POINTER(Swe), C.c_int, _dp, C.c_double, _dp, _dp,
+                                   C.POINTER(PhiOpts), C.POINTER(PhiStats)]
         L.orc_div.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
         L.orc_grad.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
         L.orc_curl.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
@@ -187,6 +193,30 @@ def phi_combo_dense(A, vs, rho, o=None, m_warm=0):
     return outs, st.asdict(), mw.value
 
 
+def phi_vjp_dense(A, vs, rho, wbars, o=None):
+    """Forward W_i and the adjoint of one phi-combination with a dense A:
+    returns (W list, vbar list (p+1), Abar (n x n), forward stats, adjoint stats)."""
+    A = _f64(A)
+    n = A.shape[0]
+    p = len(vs) - 1
+    va, keep = _vec_array(vs, n)
+    rho = _f64(rho)
+    outs = [np.zeros(n) for _ in rho]
+    oa = (_dp * len(outs))(*[_ptr(w) for w in outs])
+    wb = [_f64(w) for w in wbars]
+    wba = (_dp * len(wb))(*[_ptr(w) for w in wb])
+    vb = [np.zeros(n) for _ in range(p + 1)]
+    vba = (_dp * len(vb))(*[_ptr(w) for w in vb])
+    Abar = np.zeros((n, n))
+    fs, ast = PhiStats(), PhiStats()
+    o = o if o is not None else opts()
+    rc = lib().orc_phi_vjp_dense(n, _ptr(A), p, va, len(rho), _ptr(rho), wba, oa, vba,
+                                 _ptr(Abar), C.byref(o), C.byref(fs), C.byref(ast))
+    if rc:
+        raise RuntimeError("orc_phi_vjp_dense failed: %d" % rc)
+    return outs, vb, Abar, fs.asdict(), ast.asdict()
+
+
 class SWE:
     """The oracle's shallow-water model on one mesh."""
 
@@ -271,6 +301,27 @@ class SWE:
         lib().orc_jtv(C.byref(self.s), _ptr(u), _ptr(w), _ptr(o))
         return o
 
+    def ktv(self, a, b):
+        """K(a, b) = grad_u <a, J(u) b>."""
+        a, b = _f64(a), _f64(b)
+        o = np.empty(self.N)
+        lib().orc_ktv(C.byref(self.s), _ptr(a), _ptr(b), _ptr(o))
+        return o
+
+    def step_vjp(self, method, u, dt, ubar, o=None):
+        """(d u_{n+1} / d u_n)^T ubar for one step from u (exprb42); pass
+        replay opts to follow a recorded forward.  Returns (ubar_n, stats of
+        the two adjoint calls)."""
+        u, ubar = _f64(u), _f64(ubar)
+        out = np.empty(self.N)
+        st = (PhiStats * 2)()
+        o = o if o is not None else opts()
+        rc = lib().orc_step_vjp(C.byref(self.s), METHODS[method], _ptr(u), dt, _ptr(ubar),
+                                _ptr(out), C.byref(o), st)
+        if rc:
+            raise RuntimeError("orc_step_vjp failed: %d" % rc)
+        return out, [st[0].asdict(), st[1].asdict()]
+
     def dense_jacobian(self, u):
         J = np.empty((self.N, self.N))
         e = np.zeros(self.N)
@@ -304,6 +355,41 @@ class SWE:
         if rc:
             raise RuntimeError("orc_phi_combo failed: %d" % rc)
         return outs, st.asdict(), mw.value
+
+
+def exprb42_loss_grad(swe, u0, dt, steps, obs_step, obs_cell, obs_val, tol=1e-10, m_max=40):
+    """Loss L = 1/2 sum_k (h[obs_cell_k] after step obs_step_k - obs_val_k)^2
+    over an exprb42 trajectory of `steps` steps from u0, and dL/du0 by
+    per-step vector-Jacobian products on the recorded schedule.
+    Returns (L, grad, schedules)."""
+    obs_step = np.asarray(obs_step, dtype=np.int64)
+    obs_cell = np.asarray(obs_cell, dtype=np.int64)
+    obs_val = np.asarray(obs_val, dtype=np.float64)
+    n = swe.n
+    us = [np.array(u0, dtype=np.float64)]
+    scheds = []
+    st = swe_stepper(swe, "exprb42")
+    for k in range(steps):
+        sch = new_schedule()
+        us.append(st.step(us[-1], dt, opts(tol=tol, m_max=m_max, mode=RECORD, sched=sch)))
+        scheds.append(sch.as_array())
+    loss = 0.0
+    res = []
+    for k in range(steps + 1):
+        sel = obs_step == k
+        r = us[k][3 * n + obs_cell[sel]] - obs_val[sel]
+        res.append((obs_cell[sel], r))
+        loss += 0.5 * float(r @ r)
+    g = np.zeros(swe.N)
+    for k in range(steps, 0, -1):
+        c, r = res[k]
+        np.add.at(g, 3 * n + c, r)
+        g, _ = swe.step_vjp("exprb42", us[k - 1], dt, g,
+                            opts(tol=tol, m_max=m_max, mode=REPLAY,
+                                 sched=schedule_from_array(scheds[k - 1])))
+    c, r = res[0]
+    np.add.at(g, 3 * n + c, r)
+    return loss, g, scheds
 
 
 class Stepper:

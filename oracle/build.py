@@ -5,7 +5,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_swe.c", "orc_linalg.c", "orc_phi.c", "orc_schemes.c"]
+SOURCES = ["orc_swe.c", "orc_linalg.c", "orc_phi.c", "orc_schemes.c", "orc_adjoint.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

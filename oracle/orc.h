@@ -20,6 +20,10 @@
  *     controller of the shape the paper cites (constants stated in orc_phi.c)
  *   - exprb42, pexprb43, exprb53 (eqs. 3.11-3.13), epi3 (eq. epi3) with an
  *     EPI2 starting step (eq. 3.5), through the call mapping of Sec. 4.4.
+ *   - the adjoint (not in the paper): K(a, b) = grad_u <a, J(u) b>, the
+ *     continuous adjoint of one phi-combination on the substeps of its
+ *     forward solve (orc_adjoint.c states the construction), and the
+ *     vector-Jacobian product of one exprb42 step.
  *
  * Parity status: the controller of Alg. 1 (steps 4-5) is only cited by the
  * paper; its constants are a reading ("parity unpinned" for the controller's
@@ -66,6 +70,8 @@ void orc_lap(const orc_swe *m, const double *psi, double *out);
 void orc_rhs(const orc_swe *m, const double *u, double *f);
 void orc_jv(const orc_swe *m, const double *u, const double *v, double *out);
 void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out);
+/* K(a, b) = grad_u <a, J(u) b>, independent of u because F is quadratic */
+void orc_ktv(const orc_swe *m, const double *a, const double *b, double *out);
 
 /* ---------------- small dense linear algebra ---------------- */
 /* X = exp(A), A and X row-major KxK.  Returns the number of squarings. */
@@ -87,6 +93,27 @@ typedef struct {
     int len, cap, pos;
 } orc_schedule;
 
+/* What the solution of one accepted substep is made of: on [t, t + tau],
+ *   y(t + s) = sum_{j<p} s^j/j! w_j + beta V_{m+1} c(s),
+ * with c(s) the first m+1 entries of column m+p of exp(s Hhat'),
+ * Hhat' = [[Hbar, e_1 e_1^T], [0, N_p]], Hbar = [[H_m, 0], [h e_m^T, 0]]. */
+typedef struct {
+    double t, tau, t_out; /* substep start, length, output time it heads for */
+    int m;                /* Krylov size of the accepted attempt (0 when w_p = 0) */
+    int out;              /* output index the substep lands on, -1 if none */
+    double beta, hsub;    /* ||w_p|| and h_{m+1,m} (0 after a breakdown) */
+    double *H;            /* m x m, row-major */
+    double *V;            /* (m+1) x n: v_1 .. v_{m+1} (one zero vector when m = 0) */
+    double *w;            /* p x n: w_0 .. w_{p-1} */
+} orc_substep;
+
+typedef struct {
+    int n, p, len, cap;
+    orc_substep *s;
+} orc_phi_tape;
+
+void orc_tape_free(orc_phi_tape *t);
+
 typedef struct {
     double tol;            /* relative: Tol_abs = tol * max_l ||v_l|| */
     int m_init, m_max;
@@ -95,6 +122,7 @@ typedef struct {
     int max_attempts;
     int mode;              /* ORC_FREE / ORC_RECORD / ORC_REPLAY */
     orc_schedule *sched;   /* used in RECORD and REPLAY */
+    orc_phi_tape *tape;    /* if set: every accepted substep is appended */
 } orc_phi_opts;
 
 typedef struct {
@@ -115,6 +143,26 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
 int orc_phi_combo_dense(int n, const double *A, int p, const double *const *v, int ns,
                         const double *rho, double *const *w_out, const orc_phi_opts *o,
                         int *m_warm, orc_phi_stats *st);
+
+/* ---------------- adjoint of a phi-combination ---------------- */
+/* acc += scale * K(a, b), K the derivative of <a, A(u) b> with respect to
+ * whatever A depends on (acc's length is the caller's business) */
+typedef void (*orc_kacc_fn)(void *ctx, const double *a, const double *b, double scale,
+                            double *acc);
+
+/* Cotangents of one phipm_simul_iom2 call from the tape of its forward
+ * solve: vbar[l] (l = 0..p, NULL entries skipped) and kacc += int K(mu, y).
+ * AT applies A^T.  p >= 1. */
+int orc_phi_adjoint(int n, orc_matvec_fn AT, void *atctx, orc_kacc_fn K, void *kctx,
+                    double *kacc, const orc_phi_tape *tape, int p, int ns, const double *rho,
+                    const double *const *wbar, double *const *vbar, const orc_phi_opts *o,
+                    orc_phi_stats *st);
+
+/* dense A: forward (w_out) and adjoint (vbar, Abar = dL/dA, n x n) */
+int orc_phi_vjp_dense(int n, const double *A, int p, const double *const *v, int ns,
+                      const double *rho, const double *const *wbar, double *const *w_out,
+                      double *const *vbar, double *Abar, const orc_phi_opts *o,
+                      orc_phi_stats *fwd, orc_phi_stats *adj);
 
 /* ---------------- exponential Rosenbrock schemes ---------------- */
 enum { ORC_EXPRB42 = 0, ORC_PEXPRB43 = 1, ORC_EXPRB53 = 2, ORC_EPI3 = 3, ORC_EPI2 = 4 };
@@ -141,6 +189,13 @@ void orc_step_state_free(orc_step_state *s);
 
 int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_state *s,
              const orc_phi_opts *o);
+
+/* Vector-Jacobian product of one step (exprb42 only): ubar_n = (du_{n+1}/du_n)^T
+ * ubar_np1, with the step recomputed under *o (replay its schedule to follow
+ * the original forward).  adj: stats of the two adjoint calls (nullable). */
+int orc_step_vjp(const orc_swe *m, int method, const double *u, double dt,
+                 const double *ubar_np1, double *ubar_n, const orc_phi_opts *o,
+                 orc_phi_stats *adj);
 
 /* SWE problem wrapper usable as orc_problem ctx */
 void orc_swe_problem(orc_swe *m, orc_problem *pb);

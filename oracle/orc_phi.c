@@ -59,6 +59,52 @@ void orc_phi_default_opts(orc_phi_opts *o)
     o->max_attempts = 10000;
     o->mode = ORC_FREE;
     o->sched = NULL;
+    o->tape = NULL;
+}
+
+void orc_tape_free(orc_phi_tape *t)
+{
+    if (!t) return;
+    for (int k = 0; k < t->len; k++) {
+        free(t->s[k].H);
+        free(t->s[k].V);
+        free(t->s[k].w);
+    }
+    free(t->s);
+    memset(t, 0, sizeof(*t));
+}
+
+/* append the accepted substep [t, t + tau] to the tape */
+static int tape_push(orc_phi_tape *tp, int n, int p, double t, double tau, double t_out, int out,
+                     int m, double beta, double hsub, const double *H, int ldh,
+                     const double *V, const double *wv)
+{
+    if (tp->len == tp->cap) {
+        int nc = tp->cap ? 2 * tp->cap : 16;
+        orc_substep *ns = realloc(tp->s, sizeof(orc_substep) * nc);
+        if (!ns) return ORC_ENOMEM;
+        tp->s = ns;
+        tp->cap = nc;
+    }
+    tp->n = n;
+    tp->p = p;
+    orc_substep *e = &tp->s[tp->len];
+    memset(e, 0, sizeof(*e));
+    e->t = t; e->tau = tau; e->t_out = t_out; e->out = out;
+    e->m = m; e->beta = beta; e->hsub = hsub;
+    e->H = calloc(m > 0 ? (size_t)m * m : 1, sizeof(double));
+    e->V = calloc((size_t)(m + 1) * n, sizeof(double));
+    e->w = calloc(p > 0 ? (size_t)p * n : 1, sizeof(double));
+    if (!e->H || !e->V || !e->w) {
+        free(e->H); free(e->V); free(e->w);
+        return ORC_ENOMEM;
+    }
+    for (int r = 0; r < m; r++)
+        for (int c = 0; c < m; c++) e->H[r * m + c] = H[r * ldh + c];
+    if (m > 0) memcpy(e->V, V, sizeof(double) * (size_t)(m + 1) * n);
+    if (p > 0) memcpy(e->w, wv, sizeof(double) * (size_t)p * n);
+    tp->len++;
+    return ORC_OK;
 }
 
 static double nrm2(int n, const double *x)
@@ -380,6 +426,14 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                 }
                 memcpy(y, yn, sizeof(double) * n);
                 free(yn);
+                if (o->tape) {
+                    int mt = beta > 0.0 ? meff : 0;
+                    double hs = 0.0;
+                    if (mt > 0) hs = (m_break && meff == m_break) ? 0.0 : H[meff * mmax + meff - 1];
+                    int r3 = tape_push(o->tape, n, p, t, tau_u, t_out, lands ? io : -1, mt, beta,
+                                       hs, H, mmax, V, wv);
+                    if (r3) { rc = r3; goto done; }
+                }
                 y_zero = 0;
                 t = lands ? t_out : t + tau_u;
                 point_ready = 0;

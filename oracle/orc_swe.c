@@ -408,6 +408,61 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out)
     }
 }
 
+/* K(a, b) = grad_u <a, J(u) b>.  F is quadratic, so J(u) is affine in u and
+ * K does not depend on u: <d, K(a, b)> = <a, (J(d) - J(0)) b>.  The terms of
+ * J(u) b that move with u are
+ *   J_v:  -(V b_vel)(n x u)            -> -(V b)_i (a_i x n_i)
+ *   J_r:  (V u)(b_vel x n)  (eta = V u + f) -> V^T c,  c_i = a_i . (b_i x n_i)
+ *   J_m:  -G(u . b_vel)                -> -(G^T a_vel)_i b_i
+ *         -D.(h b_vel + b_h u)         -> r = D^T a_h: h gets -r_i . b_i,
+ *                                         velocity gets -b_h,i r_i
+ * (the dissipation does not depend on u). */
+void orc_ktv(const orc_swe *m, const double *a, const double *b, double *out)
+{
+    int n = m->n;
+    const double *ax = a, *ay = a + n, *az = a + 2 * n, *ah = a + 3 * n;
+    const double *bx = b, *by = b + n, *bz = b + 2 * n, *bh = b + 3 * n;
+    double *zb = m->work, *c = m->work + n, *rx = m->work + 2 * n, *ry = m->work + 3 * n,
+           *rz = m->work + 4 * n, *q = m->work + 5 * n, *dx = m->work + 6 * n,
+           *dy = m->work + 7 * n, *dz = m->work + 8 * n;
+    orc_curl(m, bx, by, bz, zb);
+    for (int i = 0; i < n; i++) {
+        const double *ni = m->xyz + 3 * i;
+        /* a x n */
+        double cx = ay[i] * ni[2] - az[i] * ni[1];
+        double cy = az[i] * ni[0] - ax[i] * ni[2];
+        double cz = ax[i] * ni[1] - ay[i] * ni[0];
+        out[i] = -zb[i] * cx;
+        out[n + i] = -zb[i] * cy;
+        out[2 * n + i] = -zb[i] * cz;
+        out[3 * n + i] = 0.0;
+        /* b x n */
+        double ex = by[i] * ni[2] - bz[i] * ni[1];
+        double ey = bz[i] * ni[0] - bx[i] * ni[2];
+        double ez = bx[i] * ni[1] - by[i] * ni[0];
+        c[i] = ax[i] * ex + ay[i] * ey + az[i] * ez;
+    }
+    curl_T(m, c, rx, ry, rz);
+    for (int i = 0; i < n; i++) {
+        out[i] += rx[i];
+        out[n + i] += ry[i];
+        out[2 * n + i] += rz[i];
+    }
+    grad_T(m, ax, ay, az, q);
+    for (int i = 0; i < n; i++) {
+        out[i] -= q[i] * bx[i];
+        out[n + i] -= q[i] * by[i];
+        out[2 * n + i] -= q[i] * bz[i];
+    }
+    div_T(m, ah, dx, dy, dz);
+    for (int i = 0; i < n; i++) {
+        out[i] -= bh[i] * dx[i];
+        out[n + i] -= bh[i] * dy[i];
+        out[2 * n + i] -= bh[i] * dz[i];
+        out[3 * n + i] -= dx[i] * bx[i] + dy[i] * by[i] + dz[i] * bz[i];
+    }
+}
+
 /* ------------------------------------------------------------------ */
 static void swe_rhs_cb(void *ctx, const double *u, double *f) { orc_rhs((const orc_swe *)ctx, u, f); }
 static void swe_jv_cb(void *ctx, const double *u, const double *v, double *o)

@@ -85,13 +85,18 @@ typedef struct {
  *   m_init, m_max                first / largest Krylov size (m_max <= XRB_MMAX_LIMIT)
  *   delta, gamma                 acceptance safety factor (Alg. 1: 1.4) and
  *                                controller safety factor (0.8)
- *   max_attempts                 cap on substep attempts per phi_combo call */
+ *   max_attempts                 cap on substep attempts per phi_combo call
+ *   lanes                        tuning: lanes per cell in the stencil kernels,
+ *                                1, 2, 4 or 8, or 0 to choose from the grid size.
+ *                                Results depend on it at the rounding level (the
+ *                                order of the edge sums), never on the batch size. */
 typedef struct {
     double radius, omega, gravity, gamma_h, dt_e;
     double tol;
     int32_t m_init, m_max;
     double delta, gamma;
     int32_t max_attempts;
+    int32_t lanes;
 } xrb_params;
 
 #define XRB_MMAX_LIMIT 44
@@ -103,7 +108,7 @@ typedef struct {
 
 /* Fill p with the defaults (a = 6.371e6 m, Omega = 7.292e-5 1/s,
  * g = 9.80616 m/s^2, gamma_h = 4e-4, dt_e = 240 s, tol = 1e-10, m_init = 1,
- * m_max = 40, delta = 1.4, gamma = 0.8, max_attempts = 10000). */
+ * m_max = 40, delta = 1.4, gamma = 0.8, max_attempts = 10000, lanes = 0). */
 xrb_status xrb_default_params(xrb_params *p);
 
 /* Create a context on the current HIP device.  `stream` is a hipStream_t (NULL

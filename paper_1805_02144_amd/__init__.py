@@ -38,7 +38,7 @@ class Params(C.Structure):
     _fields_ = [("radius", C.c_double), ("omega", C.c_double), ("gravity", C.c_double),
                 ("gamma_h", C.c_double), ("dt_e", C.c_double), ("tol", C.c_double),
                 ("m_init", C.c_int32), ("m_max", C.c_int32), ("delta", C.c_double),
-                ("gamma", C.c_double), ("max_attempts", C.c_int32)]
+                ("gamma", C.c_double), ("max_attempts", C.c_int32), ("lanes", C.c_int32)]
 
 
 class PhiStats(C.Structure):

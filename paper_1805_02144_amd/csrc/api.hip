@@ -759,6 +759,7 @@ xrb_status xrb_default_params(xrb_params *p) {
     p->delta = 1.4;
     p->gamma = 0.8;
     p->max_attempts = 10000;
+    p->lanes = 0;
     return XRB_OK;
 }
 
@@ -767,7 +768,9 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     if (!mesh || !params || !out) return XRB_EINVAL;
     *out = nullptr;
     if (params->m_max < 1 || params->m_max > kMmax || params->m_init < 1 || !(params->tol > 0.0) ||
-        params->max_attempts < 1 || !(params->radius > 0.0) || !(params->dt_e > 0.0))
+        params->max_attempts < 1 || !(params->radius > 0.0) || !(params->dt_e > 0.0) ||
+        !(params->lanes == 0 || params->lanes == 1 || params->lanes == 2 || params->lanes == 4 ||
+          params->lanes == 8))
         return XRB_EINVAL;
     xrb_ctx *ctx = new (std::nothrow) xrb_ctx();
     if (!ctx) return XRB_ENOMEM;
@@ -826,6 +829,7 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     M.beta = dst[1];
     M.cl = dst[2];
     M.cen = cen;
+    M.lanes = params->lanes ? params->lanes : stencil_lanes(n);
     M.nu = geo.nu;
     M.g = params->gravity;
     *out = ctx;

@@ -3,27 +3,36 @@
 //   J(u) x  eqs. dynjs-dynjc, fused with the IOM2 dot products or the w_j
 //           recurrence axpys of Alg. 1
 //
-// Edge-parallel mapping: eight consecutive lanes serve one cell, lane s < 6
-// handling the edge to neighbour slot s (lanes 6 and 7 carry zero weights).
-// Each lane gathers its neighbour, forms its edge terms, and a fixed DPP
-// butterfly over the eight lanes sums them (bitwise identical in all eight).
-// This gives eight times the memory-level parallelism of one thread per
-// cell, which the small grids need.  The two-ring dissipation stencil
-// L(L x) takes L x from a preceding one-ring pass (launch_lap4).
+// Edge-parallel mapping: L consecutive lanes serve one cell (L = 8 on small
+// grids, where the extra memory-level parallelism pays; fewer on large
+// ones, where the per-cell work repeated in every lane of the group would
+// cost more than it hides).  Each lane gathers its neighbours, forms their
+// edge terms, and a fixed DPP butterfly over the L lanes sums them (bitwise
+// identical in all L).  The two-ring dissipation stencil L(L x) takes L x
+// from a preceding one-ring pass (launch_lap4).
 #include "reduce.h"
 #include "xrb_internal.h"
 
 namespace xrb {
 
+int stencil_lanes(int n) { return n > 100000 ? 2 : 8; }
+
 namespace {
 
-constexpr int kLanes = 8;
+constexpr int kXcd = 8;   // accelerator dies, each with its own L2
 
-inline int cells_grid(int n, int block) {
-    const int cpb = block / kLanes;
+// one block per block/L cells, rounded up to a whole number of blocks per XCD
+inline int cells_grid(int n, int block, int L) {
+    const int cpb = block / L;
     int g = (n + cpb - 1) / cpb;
-    return g < 1 ? 1 : g;
+    if (g < 1) g = 1;
+    return (g + kXcd - 1) / kXcd * kXcd;
 }
+
+// Block size of a reducing stencil launch: the partial count is fixed by
+// red_parts(n), so large grids get wider blocks (more waves per CU) rather
+// than more partials; small ones keep 256 threads and a few iterations.
+inline int red_block(int n) { return n > 65536 ? 1024 : 256; }
 
 // Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).
 template <int CTRL>
@@ -33,14 +42,15 @@ __device__ inline double dpp_f64(double v) {
     return __hiloint2double(hi, lo);
 }
 
-// Sum over the eight lanes of a cell: half-row mirror (lane i with 7-i),
-// then xor 1 and xor 2 inside each quad.  Every lane ends with the same
-// operands added in the same pairs (only commuted), so the eight results
-// are bitwise identical.
+// Sum over the L lanes of a cell: for eight, half-row mirror (lane i with
+// 7-i) first; then xor 1 and xor 2 inside each quad.  Every lane ends with
+// the same operands added in the same pairs (only commuted), so the L
+// results are bitwise identical.
+template <int L>
 __device__ inline double grp_sum(double v) {
-    v += dpp_f64<0x141>(v);   // row_half_mirror
-    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    if (L >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+    if (L >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (L >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
     return v;
 }
 
@@ -55,8 +65,7 @@ __device__ inline Cell load_cell(const double *__restrict__ cen, int i) {
 }
 
 // Flux and circulation weights of the edge i -> j rebuilt from its two
-// scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).  Lanes without an
-// edge pass alpha = beta = 0.
+// scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).
 struct EdgeW {
     double ax, ay, az, bx, by, bz;
 };
@@ -71,10 +80,31 @@ __device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al, 
     return w;
 }
 
-// first cell of this thread's group and the stride, in cells
-__device__ inline int cell0() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) / kLanes); }
-__device__ inline int cell_stride() { return (int)((gridDim.x * blockDim.x) / kLanes); }
+// Cells of this block: one contiguous chunk, walked block/L cells at a
+// time.  Workgroups are dispatched round-robin over the XCDs (block b on
+// XCD b mod 8); numbering the chunks XCD-major gives every XCD one
+// contiguous eighth of the grid, swept in order, so the neighbour lines a
+// block gathers were mostly brought into the same L2 by the blocks beside it.
+struct CellRange {
+    int i, end, step;
+};
+template <int L>
+__device__ inline CellRange block_cells(int n) {
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int chunk = (G % kXcd) ? b : (b % kXcd) * (G / kXcd) + b / kXcd;
+    const int per = (n + G - 1) / G;
+    const int i0 = chunk * per;
+    const int i1 = i0 + per < n ? i0 + per : n;
+    return {i0 + (int)threadIdx.x / L, i1, (int)blockDim.x / L};
+}
 
+// Every stencil serves a cell with L consecutive lanes (L = 1, 2, 4, 8):
+// lane q takes the neighbour slots q, q + L, ... < 6 and the lanes' edge
+// sums are combined by grp_sum<L>; outputs b = q, q + L, ... < 4 are
+// written by lane q.  Pentagon slot 5 points at the cell itself with zero
+// weights.
+
+template <int L>
 __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restrict__ psi,
                                               double *__restrict__ out, Batch bt) {
     const int mk = blockIdx.y;
@@ -82,18 +112,26 @@ __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restric
     psi = member_ptr(psi, bt.ws, mk);
     out = member_ptr(out, bt.ws, mk);
     const int n = M.n;
-    const int s = threadIdx.x & (kLanes - 1);
-    for (int i = cell0(); i < n; i += cell_stride()) {
-        const int e = 6 * i + (s < 6 ? s : 0);
-        const int j = s < 6 ? M.nbr[e] : i;
-        const double c = s < 6 ? M.cl[e] : 0.0;
-        double a[4];
+    const int q = threadIdx.x & (L - 1);
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 4; ++b) a[b] = grp_sum(c * (psi[b * n + j] - psi[b * n + i]));
-        if (s < 4) out[s * n + i] = a[s];
+        for (int s = q; s < 6; s += L) {
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const double c = M.cl[e];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) a[b] += c * (psi[b * n + j] - psi[b * n + i]);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) a[b] = grp_sum<L>(a[b]);
+#pragma unroll
+        for (int b = q; b < 4; b += L) out[b * n + i] = a[b];
     }
 }
 
+template <int L>
 __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__restrict__ u,
                                                    double *__restrict__ eta, Batch bt) {
     const int mk = blockIdx.y;
@@ -101,20 +139,26 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
     u = member_ptr(u, bt.ws, mk);
     eta = member_ptr(eta, bt.ws, mk);
     const int n = M.n;
-    const int s = threadIdx.x & (kLanes - 1);
-    for (int i = cell0(); i < n; i += cell_stride()) {
-        const bool edge = s < 6;
-        const int e = 6 * i + (edge ? s : 0);
-        const int j = edge ? M.nbr[e] : i;
-        const Cell ci = load_cell(M.cen, i), cj = load_cell(M.cen, j);
-        const EdgeW w = edge_weights(ci, cj, 0.0, edge ? M.beta[e] : 0.0);
-        double z = w.bx * (u[i] + u[j]) + w.by * (u[n + i] + u[n + j]) +
-                   w.bz * (u[2 * n + i] + u[2 * n + j]);
-        z = grp_sum(z);
-        if (s == 0) eta[i] = z + ci.f;
+    const int q = threadIdx.x & (L - 1);
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
+        const Cell ci = load_cell(M.cen, i);
+        double z = 0.0;
+#pragma unroll
+        for (int s = q; s < 6; s += L) {
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const Cell cj = load_cell(M.cen, j);
+            const EdgeW w = edge_weights(ci, cj, 0.0, M.beta[e]);
+            z += w.bx * (u[i] + u[j]) + w.by * (u[n + i] + u[n + j]) +
+                 w.bz * (u[2 * n + i] + u[2 * n + j]);
+        }
+        z = grp_sum<L>(z);
+        if (q == 0) eta[i] = z + ci.f;
     }
 }
 
+template <int L>
 __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict__ u,
                                              const double *__restrict__ lu,
                                              double *__restrict__ f, Batch bt) {
@@ -125,27 +169,39 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
     f = member_ptr(f, bt.ws, mk);
     const int n = M.n;
     const double g = M.g;
-    const int s = threadIdx.x & (kLanes - 1);
-    for (int i = cell0(); i < n; i += cell_stride()) {
-        const bool edge = s < 6;
-        const int e = 6 * i + (edge ? s : 0);
-        const int j = edge ? M.nbr[e] : i;
+    const int q = threadIdx.x & (L - 1);
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
         const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], h = u[3 * n + i];
-        const double vx = u[j], vy = u[n + j], vz = u[2 * n + j], hj = u[3 * n + j];
-        const Cell ci = load_cell(M.cen, i), cj = load_cell(M.cen, j);
-        const EdgeW w = edge_weights(ci, cj, edge ? M.alpha[e] : 0.0, edge ? M.beta[e] : 0.0);
-        const double ax = w.ax, ay = w.ay, az = w.az, bx = w.bx, by = w.by, bz = w.bz;
-        const double c = edge ? M.cl[e] : 0.0;
+        const Cell ci = load_cell(M.cen, i);
         const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * h;
-        const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * hj;
-        const double dE = Ej - Ei;
-        const double gx = grp_sum(ax * dE), gy0 = grp_sum(ay * dE), gz0 = grp_sum(az * dE);
-        const double dv = grp_sum(ax * (h * ux + hj * vx) + ay * (h * uy + hj * vy) +
-                                  az * (h * uz + hj * vz));
-        const double zt = grp_sum(bx * (ux + vx) + by * (uy + vy) + bz * (uz + vz));
-        double d[4];
+        double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 4; ++b) d[b] = grp_sum(c * (lu[b * n + j] - lu[b * n + i]));
+        for (int s = q; s < 6; s += L) {
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const double vx = u[j], vy = u[n + j], vz = u[2 * n + j], hj = u[3 * n + j];
+            const Cell cj = load_cell(M.cen, j);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+            const double c = M.cl[e];
+            const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * hj;
+            const double dE = Ej - Ei;
+            gx += w.ax * dE;
+            gy0 += w.ay * dE;
+            gz0 += w.az * dE;
+            dv += w.ax * (h * ux + hj * vx) + w.ay * (h * uy + hj * vy) + w.az * (h * uz + hj * vz);
+            zt += w.bx * (ux + vx) + w.by * (uy + vy) + w.bz * (uz + vz);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) d[b] += c * (lu[b * n + j] - lu[b * n + i]);
+        }
+        gx = grp_sum<L>(gx);
+        gy0 = grp_sum<L>(gy0);
+        gz0 = grp_sum<L>(gz0);
+        dv = grp_sum<L>(dv);
+        zt = grp_sum<L>(zt);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[b] = grp_sum<L>(d[b]);
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;       // tangent projection of grad E
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
@@ -157,21 +213,22 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         o[1] = -eta * py - Gy - nu * d[1];
         o[2] = -eta * pz - Gz - nu * d[2];
         o[3] = -dv - nu * d[3];
-        if (s < 4) f[s * n + i] = o[s];
+#pragma unroll
+        for (int b = q; b < 4; b += L) f[b * n + i] = o[b];
     }
 }
 
 // out = dt*J(u) x + sum_k c_k v_k, with an optional reduction epilogue
 // (IOM2: raw dot partials; recurrence: norm partials).
-template <int EPI>
-__global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
+template <int EPI, int L>
+__global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
     const int n = M.n;
     const double g = M.g, nu = M.nu;
     const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
-    const int s = threadIdx.x & (kLanes - 1);
+    const int q = threadIdx.x & (L - 1);
     double cax[kPmax];
     const double *axv[kPmax];
 #pragma unroll
@@ -186,29 +243,42 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
     double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
     const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
     double r0 = 0.0, r1 = 0.0;   // this lane's reduction partials
-    for (int i = cell0(); i < n; i += cell_stride()) {
-        const bool edge = s < 6;
-        const int e = 6 * i + (edge ? s : 0);
-        const int j = edge ? M.nbr[e] : i;
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
         const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], uh = u[3 * n + i];
         const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
-        const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
-        const double wx = u[j], wy = u[n + j], wz = u[2 * n + j], wh = u[3 * n + j];
-        const Cell ci = load_cell(M.cen, i), cj = load_cell(M.cen, j);
-        const EdgeW w = edge_weights(ci, cj, edge ? M.alpha[e] : 0.0, edge ? M.beta[e] : 0.0);
-        const double ax = w.ax, ay = w.ay, az = w.az, bx = w.bx, by = w.by, bz = w.bz;
-        const double c = edge ? M.cl[e] : 0.0;
+        const Cell ci = load_cell(M.cen, i);
         const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
-        const double sj = wx * vx + wy * vy + wz * vz + g * vh;
-        const double ds = sj - si;
         const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
-        const double gx = grp_sum(ax * ds), gy0 = grp_sum(ay * ds), gz0 = grp_sum(az * ds);
-        const double dv = grp_sum(ax * (fx + (wh * vx + vh * wx)) + ay * (fy + (wh * vy + vh * wy)) +
-                                  az * (fz + (wh * vz + vh * wz)));
-        const double zt = grp_sum(bx * (xx + vx) + by * (xy + vy) + bz * (xz + vz));
-        double d[4];
+        double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll(L >= 4 ? 2 : 2)
+        for (int s = q; s < 6; s += L) {
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
+            const double wx = u[j], wy = u[n + j], wz = u[2 * n + j], wh = u[3 * n + j];
+            const Cell cj = load_cell(M.cen, j);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+            const double c = M.cl[e];
+            const double sj = wx * vx + wy * vy + wz * vz + g * vh;
+            const double ds = sj - si;
+            gx += w.ax * ds;
+            gy0 += w.ay * ds;
+            gz0 += w.az * ds;
+            dv += w.ax * (fx + (wh * vx + vh * wx)) + w.ay * (fy + (wh * vy + vh * wy)) +
+                  w.az * (fz + (wh * vz + vh * wz));
+            zt += w.bx * (xx + vx) + w.by * (xy + vy) + w.bz * (xz + vz);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) d[b] = grp_sum(c * (lx[b * n + j] - lx[b * n + i]));
+            for (int b = 0; b < 4; ++b) d[b] += c * (lx[b * n + j] - lx[b * n + i]);
+        }
+        gx = grp_sum<L>(gx);
+        gy0 = grp_sum<L>(gy0);
+        gz0 = grp_sum<L>(gz0);
+        dv = grp_sum<L>(dv);
+        zt = grp_sum<L>(zt);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[b] = grp_sum<L>(d[b]);
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
@@ -222,16 +292,17 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
         o[1] = sc * (-zt * puy - eta * pxy - Gy - nu * d[1]);
         o[2] = sc * (-zt * puz - eta * pxz - Gz - nu * d[2]);
         o[3] = sc * (-dv - nu * d[3]);
-        if (s < 4) {
-            const int oi = s * n + i;
-            double ob = o[s];
+        const double xs[4] = {xx, xy, xz, xh};
+#pragma unroll
+        for (int b = q; b < 4; b += L) {
+            const int oi = b * n + i;
+            double ob = o[b];
 #pragma unroll
             for (int k = 0; k < kPmax; ++k)
                 if (k < a.naxpy) ob += cax[k] * axv[k][oi];
             outk[oi] = ob;
             if (EPI == kEpiIom2) {
-                const double xs = s == 0 ? xx : (s == 1 ? xy : (s == 2 ? xz : xh));
-                r0 += ob * xs;
+                r0 += ob * xs[b];
                 if (rjm1) r1 += ob * rjm1[oi];
             } else if (EPI == kEpiNorm) {
                 r0 += ob * ob;
@@ -249,34 +320,58 @@ __global__ void __launch_bounds__(256) k_jv(DevMesh M, JvArgs a, Batch bt) {
     }
 }
 
+template <int L>
+void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+    if (epi == kEpiNone) {
+        hipLaunchKernelGGL((k_jv<kEpiNone, L>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0,
+                           s, M, a, b);
+        return;
+    }
+    const int grid = red_parts(M.n), block = red_block(M.n);
+    if (epi == kEpiIom2)
+        hipLaunchKernelGGL((k_jv<kEpiIom2, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+    else
+        hipLaunchKernelGGL((k_jv<kEpiNorm, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+}
+
 }  // namespace
 
+#define XRB_LANES_DISPATCH(CALL)            \
+    switch (M.lanes) {                      \
+    case 1: CALL(1); break;                 \
+    case 2: CALL(2); break;                 \
+    case 4: CALL(4); break;                 \
+    default: CALL(8); break;                \
+    }
+
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_lap4, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, psi, out, b);
+#define XRB_CALL(L) \
+    hipLaunchKernelGGL(k_lap4<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
 }
 
 void launch_linearize(const DevMesh &M, const double *u, double *eta, const Batch &b,
                       hipStream_t s) {
-    hipLaunchKernelGGL(k_linearize, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, u, eta, b);
+#define XRB_CALL(L) \
+    hipLaunchKernelGGL(k_linearize<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, eta, b)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
 }
 
 void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, const Batch &b,
                 hipStream_t s) {
-    hipLaunchKernelGGL(k_rhs, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, u, lu, f, b);
+#define XRB_CALL(L) \
+    hipLaunchKernelGGL(k_rhs<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, lu, f, b)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
 }
 
 int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
-    if (epi == kEpiNone) {
-        hipLaunchKernelGGL(k_jv<kEpiNone>, dim3(cells_grid(M.n, 256), b.nm), dim3(256), 0, s, M, a,
-                           b);
-        return 0;
-    }
-    const int grid = red_parts(M.n);
-    if (epi == kEpiIom2)
-        hipLaunchKernelGGL(k_jv<kEpiIom2>, dim3(grid, b.nm), dim3(256), 0, s, M, a, b);
-    else
-        hipLaunchKernelGGL(k_jv<kEpiNorm>, dim3(grid, b.nm), dim3(256), 0, s, M, a, b);
-    return grid;
+#define XRB_CALL(L) jv_launch<L>(M, a, epi, b, s)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
+    return epi == kEpiNone ? 0 : red_parts(M.n);
 }
 
 }  // namespace xrb

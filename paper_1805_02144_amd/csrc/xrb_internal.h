@@ -30,7 +30,11 @@ struct DevMesh {
     const double *cl = nullptr;                    // [n][6]
     const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, Coriolis 2 Omega sin(lat)
     double nu = 0.0, g = 0.0;
+    int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
 };
+
+// lanes per cell of the stencil kernels on an n-cell grid
+int stencil_lanes(int n);
 
 // Decision of one substep attempt, read back by the host.
 struct Decision {

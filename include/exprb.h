@@ -135,6 +135,42 @@ xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f);
  * Device vectors of length 4N; jv must not alias u or v. */
 xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv);
 
+/* out = J(u)^T w, the Euclidean transpose of xrb_jv (the adjoint operator of
+ * the linearised model; not in the paper, which has no adjoint).  Device
+ * vectors of length 4N; out must not alias u or w.  The first call of any
+ * adjoint entry point allocates the adjoint workspace (about
+ * (2 m_max + 17) 32 N bytes). */
+xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out);
+
+/* out = K(a, b) = grad_u <a, J(u) b>: the derivative of the Jacobian product
+ * with respect to the linearisation state.  F is quadratic in u, so J is
+ * affine in u and K does not depend on u: <d, K(a, b)> = <a, (J(d) - J(0)) b>.
+ * Device vectors of length 4N; out must not alias a or b. */
+xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
+
+/* Vector-Jacobian product of one step (method XRB_EXPRB42 only):
+ * ubar_n = (d u_{n+1} / d u_n)^T ubar_np1 for u_{n+1} = step(u_n, dt).
+ * The step is recomputed on the device, following `sched` (host, sched_len
+ * entries of (tau, m, flags) as xrb_schedule_get returns them for that one
+ * step) or, with sched = NULL, the free controller from a cold start.  The
+ * reverse sweep is the continuous adjoint of each phi-combination on the
+ * recomputed substeps: a Krylov space of (dt J)^T per substep (IOM2, the
+ * forward's tau, Krylov size grown from the forward's until the correction
+ * estimate passes, at most m_max), the adjoint moments from one augmented
+ * exponential, and the A-term int K(mu, y) dt exactly through a Van Loan
+ * block exponential; then the scheme's chain rule.
+ *   u         device, the state u_n (not modified)
+ *   ubar_np1  device, the cotangent of u_{n+1}; ubar_n device output (may
+ *             alias ubar_np1, not u)
+ *   stats     optional host [2]: statistics of the two adjoint calls
+ *             (attempts = exponential tests, rejected = substeps taken at
+ *             m_max without passing the test); non-NULL forces a sync.
+ * The substeps of the recomputed forward are stored on the device (about
+ * (m_max + 5) 32 N bytes per accepted substep, kept for later calls). */
+xrb_status xrb_step_vjp(xrb_ctx *ctx, xrb_method method, const double *u, double dt,
+                        const double *sched, int sched_len, const double *ubar_np1,
+                        double *ubar_n, xrb_phi_stats *stats);
+
 /* W_i = sum_{l=0}^p rho_i^l phi_l(rho_i dt J(u)) v_l, i = 1..ns
  * (phipm_simul_iom2, Alg. 1 of Sec. 4.3; the multi-output form of
  * eq. exp_multistage with the rho^l weights that make W_i the solution of

@@ -22,7 +22,8 @@ PMAX = 4
 EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
            "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
-           "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch"]
+           "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
+           "xrb_ktv", "xrb_step_vjp"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
@@ -72,6 +73,10 @@ def lib():
         L.xrb_n_cells.restype = C.c_int64
         L.xrb_rhs.argtypes = [vp, vp, vp]
         L.xrb_jv.argtypes = [vp, vp, vp, vp]
+        L.xrb_jtv.argtypes = [vp, vp, vp, vp]
+        L.xrb_ktv.argtypes = [vp, vp, vp, vp]
+        L.xrb_step_vjp.argtypes = [vp, C.c_int, vp, C.c_double, _dp, C.c_int, vp, vp,
+                                   C.POINTER(PhiStats)]
         L.xrb_phi_combo.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(vp), C.c_int, _dp,
                                     C.POINTER(vp), C.POINTER(PhiStats)]
         L.xrb_step.argtypes = [vp, C.c_int, vp, C.c_double]
@@ -183,6 +188,42 @@ class Context:
         u, v = self._vec(u), self._vec(v)
         out = self.empty()
         self._check(lib().xrb_jv(self.h, _ptr(u), _ptr(v), _ptr(out)))
+        return out
+
+    def jtv(self, u, w):
+        """J(u)^T w."""
+        self._stream()
+        u, w = self._vec(u), self._vec(w)
+        out = self.empty()
+        self._check(lib().xrb_jtv(self.h, _ptr(u), _ptr(w), _ptr(out)))
+        return out
+
+    def ktv(self, a, b):
+        """K(a, b) = grad_u <a, J(u) b>."""
+        self._stream()
+        a, b = self._vec(a), self._vec(b)
+        out = self.empty()
+        self._check(lib().xrb_ktv(self.h, _ptr(a), _ptr(b), _ptr(out)))
+        return out
+
+    def step_vjp(self, method, u, dt, ubar, sched=None, return_stats=False):
+        """(d u_{n+1}/d u_n)^T ubar for one step from u; sched: that step's
+        recorded (tau, m, flags) rows (None: recompute with the free
+        controller from a cold start)."""
+        self._stream()
+        u, ubar = self._vec(u), self._vec(ubar)
+        out = self.empty()
+        mid = METHODS[method] if isinstance(method, str) else int(method)
+        if sched is not None and len(sched):
+            a = np.ascontiguousarray(np.asarray(sched, dtype=np.float64).reshape(-1, 3))
+            sp, sl = a.ctypes.data_as(_dp), len(a)
+        else:
+            a, sp, sl = None, None, 0
+        st = (PhiStats * 2)()
+        self._check(lib().xrb_step_vjp(self.h, mid, _ptr(u), float(dt), sp, sl, _ptr(ubar),
+                                       _ptr(out), st if return_stats else None))
+        if return_stats:
+            return out, [st[0].asdict(), st[1].asdict()]
         return out
 
     def phi_combo(self, u, dt, vs, rho, return_stats=False):

@@ -1,0 +1,655 @@
+// Kernels of the adjoint (vector-Jacobian product) path.  The paper has no
+// adjoint; this is the continuous adjoint of the phi-combination ODE (eq.
+// 3.15) on the substeps of its forward solve:
+//   mu' = -A^T mu backwards from the output cotangents, vbar_j the moments
+//   int mu t^(j-1)/(j-1)! dt, and the A-term int K(mu, y) dt, where
+//   K(a, b) = grad_u <a, J(u) b>.
+//
+//   k_lapT    L^T psi on four fields (prepass of the two-ring (L^T)^2)
+//   k_jtv     dt J(u)^T x (+ axpys) with the IOM2 / norm epilogues of k_jv,
+//             so the IOM2 driver builds a Krylov space of A^T unchanged
+//   k_kpairs  acc += sum_r c_r K(a_r, b_r)
+//   k_lincomb_multi  several combinations of one contiguous basis at once
+//   k_zgemm   Z_r = sum_c z_rc What_c (the forward substep's solution basis)
+//   k_adj_gexp    finishes the last IOM2 column, exp(tau G) of the adjoint
+//                 augmented matrix, the error ratio and the combination
+//                 coefficients of mu_k and the moments
+//   k_adj_vanloan exp of the Van Loan block matrix and the Z coefficients
+//
+// Transposes in gather form: with rho_ij = A_i / A_j and the weights of the
+// forward stencils (a = alpha (x_j - x_i), b = beta (x_i x x_j), c = l/(dA)),
+//   (V^T s)_i = A_i sum b_ij (s_i/A_i - s_j/A_j)
+//   (G^T w)_i = -A_i sum a_ij . (P_i w_i/A_i + P_j w_j/A_j)
+//   (D^T p)_i = A_i sum a_ij (p_i/A_i - p_j/A_j)
+//   (L^T p)_i = A_i sum c_ij (p_j/A_j - p_i/A_i)
+// (a_ji = -a_ij A_i/A_j and b_ji = -b_ij A_i/A_j, c_ji = c_ij A_i/A_j.)
+#include "column.h"
+#include "reduce.h"
+#include "stencil_common.h"
+#include "xrb_internal.h"
+
+namespace xrb {
+namespace {
+
+using namespace stc;
+
+template <int L>
+__global__ void __launch_bounds__(256) k_lapT(DevMesh M, const double *__restrict__ psi,
+                                              double *__restrict__ out, Batch bt) {
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    psi = member_ptr(psi, bt.ws, mk);
+    out = member_ptr(out, bt.ws, mk);
+    const int n = M.n;
+    const int q = threadIdx.x & (L - 1);
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
+        const Cell ci = load_cell(M.cen, i);
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = q; s < 6; s += L) {
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const double c = M.cl[e];
+            const double raj = M.cen[4 * (size_t)j + 3];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) a[b] += c * (psi[b * n + j] * raj - psi[b * n + i] * ci.ra);
+        }
+        const double Ai = 1.0 / ci.ra;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) a[b] = grp_sum<L>(a[b]);
+#pragma unroll
+        for (int b = q; b < 4; b += L) out[b * n + i] = Ai * a[b];
+    }
+}
+
+// out = dt J(u)^T x + sum_k c_k v_k.  J^T x (the transpose of k_jv's
+// product):
+//   velocity: -V^T(x . (n x u)) + eta (n x x) - (G^T x_vel) u - h D^T x_h
+//             - nu (L^T)^2 x_vel
+//   depth:    -g G^T x_vel - (D^T x_h) . u - nu (L^T)^2 x_h
+template <int EPI, int L>
+__global__ void __launch_bounds__(1024) k_jtv(DevMesh M, JvArgs a, Batch bt) {
+    __shared__ double lds[64];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const int n = M.n;
+    const double g = M.g, nu = M.nu;
+    const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
+    const int q = threadIdx.x & (L - 1);
+    double cax[kPmax];
+    const double *axv[kPmax];
+#pragma unroll
+    for (int k = 0; k < kPmax; ++k) {
+        cax[k] = (k < a.naxpy) ? *ctl_field(a.axc[k], mk) : 0.0;
+        axv[k] = (k < a.naxpy) ? member_ptr(a.axv[k], bt.ws, mk) : nullptr;
+    }
+    const double *__restrict__ u = member_ptr(a.u, bt.ws, mk);
+    const double *__restrict__ x = member_ptr(a.x, bt.ws, mk);
+    const double *__restrict__ lx = member_ptr(a.lx, bt.ws, mk);
+    const double *__restrict__ etak = member_ptr(a.eta, bt.ws, mk);
+    double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
+    const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
+    double r0 = 0.0, r1 = 0.0;
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
+        const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], uh = u[3 * n + i];
+        const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
+        const Cell ci = load_cell(M.cen, i);
+        const double nx = ci.x, ny = ci.y, nz = ci.z, rai = ci.ra;
+        // s_i = x_i . (n_i x u_i), P_i x_i
+        const double si = xx * (ny * uz - nz * uy) + xy * (nz * ux - nx * uz) + xz * (nx * uy - ny * ux);
+        const double xn = nx * xx + ny * xy + nz * xz;
+        const double tx = xx - xn * nx, ty = xy - xn * ny, tz = xz - xn * nz;
+        double vsx = 0.0, vsy = 0.0, vsz = 0.0, gq = 0.0, drx = 0.0, dry = 0.0, drz = 0.0;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll(2)
+        for (int s = q; s < 6; s += L) {
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
+            const double wx = u[j], wy = u[n + j], wz = u[2 * n + j];
+            const Cell cj = load_cell(M.cen, j);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+            const double c = M.cl[e];
+            const double raj = cj.ra;
+            const double sj = vx * (cj.y * wz - cj.z * wy) + vy * (cj.z * wx - cj.x * wz) +
+                              vz * (cj.x * wy - cj.y * wx);
+            const double vn = cj.x * vx + cj.y * vy + cj.z * vz;
+            const double px = vx - vn * cj.x, py = vy - vn * cj.y, pz = vz - vn * cj.z;
+            const double ds = si * rai - sj * raj;
+            vsx += w.bx * ds;
+            vsy += w.by * ds;
+            vsz += w.bz * ds;
+            gq += w.ax * (tx * rai + px * raj) + w.ay * (ty * rai + py * raj) + w.az * (tz * rai + pz * raj);
+            const double dh = xh * rai - vh * raj;
+            drx += w.ax * dh;
+            dry += w.ay * dh;
+            drz += w.az * dh;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) d[b] += c * (lx[b * n + j] * raj - lx[b * n + i] * rai);
+        }
+        vsx = grp_sum<L>(vsx);
+        vsy = grp_sum<L>(vsy);
+        vsz = grp_sum<L>(vsz);
+        gq = grp_sum<L>(gq);
+        drx = grp_sum<L>(drx);
+        dry = grp_sum<L>(dry);
+        drz = grp_sum<L>(drz);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) d[b] = grp_sum<L>(d[b]);
+        const double Ai = 1.0 / rai;
+        const double qq = -Ai * gq;                              // (G^T x_vel)_i
+        const double rx = Ai * drx, ry = Ai * dry, rz = Ai * drz;  // (D^T x_h)_i
+        const double eta = etak[i];
+        double o[4];
+        o[0] = sc * (-Ai * vsx + eta * (ny * xz - nz * xy) - qq * ux - uh * rx - nu * Ai * d[0]);
+        o[1] = sc * (-Ai * vsy + eta * (nz * xx - nx * xz) - qq * uy - uh * ry - nu * Ai * d[1]);
+        o[2] = sc * (-Ai * vsz + eta * (nx * xy - ny * xx) - qq * uz - uh * rz - nu * Ai * d[2]);
+        o[3] = sc * (-g * qq - (rx * ux + ry * uy + rz * uz) - nu * Ai * d[3]);
+        const double xs[4] = {xx, xy, xz, xh};
+#pragma unroll
+        for (int b = q; b < 4; b += L) {
+            const int oi = b * n + i;
+            double ob = o[b];
+#pragma unroll
+            for (int k = 0; k < kPmax; ++k)
+                if (k < a.naxpy) ob += cax[k] * axv[k][oi];
+            outk[oi] = ob;
+            if (EPI == kEpiIom2) {
+                r0 += ob * xs[b];
+                if (rjm1) r1 += ob * rjm1[oi];
+            } else if (EPI == kEpiNorm) {
+                r0 += ob * ob;
+            }
+        }
+    }
+    if (EPI == kEpiIom2) {
+        double v[2] = {r0, r1};
+        block_sum_all<2>(v, lds);
+        put_partials<2>(v, a.dot_out + (size_t)mk * kPartStride);
+    } else if (EPI == kEpiNorm) {
+        double v[1] = {r0};
+        block_sum_all<1>(v, lds);
+        put_partials<1>(v, a.nrm_out + (size_t)mk * kPartStride);
+    }
+}
+
+// out (= or +=) scale * sum_{r < R} coef_r K(a_r, b_r), a_r = a0 + r sa,
+// b_r = b0 + r sb.  K(a, b) = grad_u <a, J(u) b>:
+//   velocity: -(V b)_i (a_i x n_i) + V^T(a . (b x n)) - (G^T a_vel)_i b_i
+//             - b_h,i (D^T a_h)_i
+//   depth:    -(D^T a_h)_i . b_i
+template <int L>
+__global__ void __launch_bounds__(256) k_kpairs(DevMesh M, KPairArgs k, Batch bt) {
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const int n = M.n;
+    const int q = threadIdx.x & (L - 1);
+    double *__restrict__ out = member_ptr(k.out, bt.ws, mk);
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
+        const Cell ci = load_cell(M.cen, i);
+        const double nx = ci.x, ny = ci.y, nz = ci.z, rai = ci.ra;
+        const double Ai = 1.0 / rai;
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int pr = 0; pr < k.R; ++pr) {
+            const double cr = k.scale * (k.coef ? k.coef[pr] : 1.0);
+            if (cr == 0.0) continue;
+            const double *__restrict__ av = member_ptr(k.a0, bt.ws, mk) + (size_t)pr * k.sa;
+            const double *__restrict__ bv = member_ptr(k.b0, bt.ws, mk) + (size_t)pr * k.sb;
+            const double ax = av[i], ay = av[n + i], az = av[2 * n + i], ah = av[3 * n + i];
+            const double bx = bv[i], by = bv[n + i], bz = bv[2 * n + i], bh = bv[3 * n + i];
+            // c_i = a_i . (b_i x n_i), P_i a_i
+            const double cc = ax * (by * nz - bz * ny) + ay * (bz * nx - bx * nz) + az * (bx * ny - by * nx);
+            const double an = nx * ax + ny * ay + nz * az;
+            const double tx = ax - an * nx, ty = ay - an * ny, tz = az - an * nz;
+            double zb = 0.0, vcx = 0.0, vcy = 0.0, vcz = 0.0, gq = 0.0, drx = 0.0, dry = 0.0, drz = 0.0;
+#pragma unroll
+            for (int s = q; s < 6; s += L) {
+                const int e = 6 * i + s;
+                const int j = M.nbr[e];
+                const Cell cj = load_cell(M.cen, j);
+                const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+                const double ajx = av[j], ajy = av[n + j], ajz = av[2 * n + j], ajh = av[3 * n + j];
+                const double bjx = bv[j], bjy = bv[n + j], bjz = bv[2 * n + j];
+                const double raj = cj.ra;
+                zb += w.bx * (bx + bjx) + w.by * (by + bjy) + w.bz * (bz + bjz);
+                const double cj_ = ajx * (bjy * cj.z - bjz * cj.y) + ajy * (bjz * cj.x - bjx * cj.z) +
+                                   ajz * (bjx * cj.y - bjy * cj.x);
+                const double dc = cc * rai - cj_ * raj;
+                vcx += w.bx * dc;
+                vcy += w.by * dc;
+                vcz += w.bz * dc;
+                const double ajn = cj.x * ajx + cj.y * ajy + cj.z * ajz;
+                const double px = ajx - ajn * cj.x, py = ajy - ajn * cj.y, pz = ajz - ajn * cj.z;
+                gq += w.ax * (tx * rai + px * raj) + w.ay * (ty * rai + py * raj) +
+                      w.az * (tz * rai + pz * raj);
+                const double dh = ah * rai - ajh * raj;
+                drx += w.ax * dh;
+                dry += w.ay * dh;
+                drz += w.az * dh;
+            }
+            zb = grp_sum<L>(zb);
+            vcx = grp_sum<L>(vcx);
+            vcy = grp_sum<L>(vcy);
+            vcz = grp_sum<L>(vcz);
+            gq = grp_sum<L>(gq);
+            drx = grp_sum<L>(drx);
+            dry = grp_sum<L>(dry);
+            drz = grp_sum<L>(drz);
+            const double qq = -Ai * gq;
+            const double rx = Ai * drx, ry = Ai * dry, rz = Ai * drz;
+            // a x n
+            const double anx = ay * nz - az * ny, any = az * nx - ax * nz, anz = ax * ny - ay * nx;
+            o[0] += cr * (-zb * anx + Ai * vcx - qq * bx - bh * rx);
+            o[1] += cr * (-zb * any + Ai * vcy - qq * by - bh * ry);
+            o[2] += cr * (-zb * anz + Ai * vcz - qq * bz - bh * rz);
+            o[3] += cr * (-(rx * bx + ry * by + rz * bz));
+        }
+#pragma unroll
+        for (int b = q; b < 4; b += L) {
+            const int oi = b * n + i;
+            out[oi] = k.accumulate ? out[oi] + o[b] : o[b];
+        }
+    }
+}
+
+// outs[k] (= or +=, bit k of accmask) sum_{r < nv} C[k * ldc + r] v_r,
+// v_r = vbase + r * vstride; k < nout <= kMultiOut
+__global__ void __launch_bounds__(kBlock) k_lincomb_multi(int n4, MultiArgs a, Batch bt) {
+    __shared__ double cf[kMultiOut * kCoefLd];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    for (int e = threadIdx.x; e < a.nout * kCoefLd; e += blockDim.x) cf[e] = a.C[e];
+    __syncthreads();
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += gridDim.x * blockDim.x) {
+        double acc[kMultiOut];
+#pragma unroll
+        for (int k = 0; k < kMultiOut; ++k)
+            acc[k] = (k < a.nout && a.out[k] && ((a.accmask >> k) & 1)) ? a.out[k][e] : 0.0;
+        for (int r = 0; r < a.nv; ++r) {
+            const double v = a.vbase[(size_t)r * a.vstride + e];
+#pragma unroll
+            for (int k = 0; k < kMultiOut; ++k)
+                if (k < a.nout) acc[k] += cf[k * kCoefLd + r] * v;
+        }
+#pragma unroll
+        for (int k = 0; k < kMultiOut; ++k)
+            if (k < a.nout && a.out[k]) a.out[k][e] = acc[k];
+    }
+}
+
+// Z_r = sum_{c < nb} z[r * kZLd + c] What_c for r < na (What_c == nullptr: zero)
+__global__ void __launch_bounds__(kBlock) k_zgemm(int n4, ZArgs a) {
+    __shared__ double cf[kZRows * kZLd];
+    for (int e = threadIdx.x; e < a.na * kZLd; e += blockDim.x) cf[e] = a.z[e];
+    __syncthreads();
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += gridDim.x * blockDim.x) {
+        double x[kZLd];
+#pragma unroll
+        for (int c = 0; c < kZLd; ++c) x[c] = (c < a.nb && a.w[c]) ? a.w[c][e] : 0.0;
+        for (int r = 0; r < a.na; ++r) {
+            double z = 0.0;
+#pragma unroll
+            for (int c = 0; c < kZLd; ++c) z += cf[r * kZLd + c] * x[c];
+            a.Z[(size_t)r * a.zstride + e] = z;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// Dense exponential of a K x K matrix (K <= kBigMax) by one block: the
+// degree-13 Pade approximant with scaling and squaring (the method whose
+// flop count the cost model eq. cost prices), products staged through LDS,
+// the solve (V - U) X = (V + U) by LU with partial pivoting in LDS.
+// ---------------------------------------------------------------------
+struct BigLds {
+    double a[kBigMax * kBigLd];
+    double b[kBigMax * kBigLd];
+    double red[64];
+    int ired[64];
+};
+
+// C = A B (global, row-major, ld K); C may alias A or B
+__device__ void big_matmul(int K, const double *A, const double *B, double *C, BigLds &L) {
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+        const int r = e / K, c = e % K;
+        L.a[r * kBigLd + c] = A[e];
+        L.b[r * kBigLd + c] = B[e];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+        const int r = e / K, c = e % K;
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) acc += L.a[r * kBigLd + k] * L.b[k * kBigLd + c];
+        C[e] = acc;
+    }
+    __syncthreads();
+}
+
+// X = exp(A); work holds 6 K^2 doubles.  Returns the number of squarings.
+__device__ int big_expm(int K, const double *A, double *X, double *work, BigLds &L) {
+    const int tid = threadIdx.x;
+    const int KK = K * K;
+    double *B = work, *B2 = work + KK, *B4 = work + 2 * KK, *B6 = work + 3 * KK;
+    double *U = work + 4 * KK, *T = work + 5 * KK;
+    // 1-norm and the scaling exponent (K <= kBigMax < blockDim: a column per thread)
+    double cs = 0.0;
+    if (tid < K)
+        for (int r = 0; r < K; ++r) cs += fabs(A[r * K + tid]);
+    const double nrm = block_max(cs, L.red);
+    if (!(nrm <= 1e30)) {   // NaN, inf or absurd: no finite exponential to compute
+        for (int e = tid; e < KK; e += blockDim.x) X[e] = __builtin_nan("");
+        __syncthreads();
+        return -1;
+    }
+    int s = 0;
+    double scale = 1.0;
+    while (nrm * scale > 5.371920351148152) {
+        ++s;
+        scale /= 2.0;
+    }
+    double bc[14];
+    bc[0] = 1.0;
+    for (int j = 0; j < 13; ++j) bc[j + 1] = bc[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
+    for (int e = tid; e < KK; e += blockDim.x) B[e] = A[e] * scale;
+    __syncthreads();
+    big_matmul(K, B, B, B2, L);
+    big_matmul(K, B2, B2, B4, L);
+    big_matmul(K, B4, B2, B6, L);
+    // U = B (B6 (b13 B6 + b11 B4 + b9 B2) + b7 B6 + b5 B4 + b3 B2 + b1 I)
+    for (int e = tid; e < KK; e += blockDim.x) T[e] = bc[13] * B6[e] + bc[11] * B4[e] + bc[9] * B2[e];
+    __syncthreads();
+    big_matmul(K, B6, T, U, L);
+    for (int e = tid; e < KK; e += blockDim.x) {
+        double v = U[e] + bc[7] * B6[e] + bc[5] * B4[e] + bc[3] * B2[e];
+        if (e / K == e % K) v += bc[1];
+        U[e] = v;
+    }
+    __syncthreads();
+    big_matmul(K, B, U, U, L);
+    // V = B6 (b12 B6 + b10 B4 + b8 B2) + b6 B6 + b4 B4 + b2 B2 + b0 I  (into X)
+    for (int e = tid; e < KK; e += blockDim.x) T[e] = bc[12] * B6[e] + bc[10] * B4[e] + bc[8] * B2[e];
+    __syncthreads();
+    big_matmul(K, B6, T, X, L);
+    for (int e = tid; e < KK; e += blockDim.x) {
+        double v = X[e] + bc[6] * B6[e] + bc[4] * B4[e] + bc[2] * B2[e];
+        if (e / K == e % K) v += bc[0];
+        X[e] = v;
+    }
+    __syncthreads();
+    // (V - U) X = (V + U) in LDS
+    for (int e = tid; e < KK; e += blockDim.x) {
+        const int r = e / K, c = e % K;
+        L.a[r * kBigLd + c] = X[e] - U[e];
+        L.b[r * kBigLd + c] = X[e] + U[e];
+    }
+    __syncthreads();
+    for (int c = 0; c < K; ++c) {
+        // pivot: first row of largest magnitude at or below the diagonal
+        if (tid < 64) {
+            double best = -1.0;
+            int bi = K;
+            for (int r = c + tid; r < K; r += 64) {
+                const double v = fabs(L.a[r * kBigLd + c]);
+                if (v > best) {
+                    best = v;
+                    bi = r;
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_down(best, off, 64);
+                const int oi = __shfl_down(bi, off, 64);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (tid == 0) L.ired[0] = bi;
+        }
+        __syncthreads();
+        const int piv = L.ired[0];
+        if (piv != c) {
+            for (int k = tid; k < 2 * K; k += blockDim.x) {
+                double *m = k < K ? L.a : L.b;
+                const int kk = k < K ? k : k - K;
+                const double t = m[c * kBigLd + kk];
+                m[c * kBigLd + kk] = m[piv * kBigLd + kk];
+                m[piv * kBigLd + kk] = t;
+            }
+            __syncthreads();
+        }
+        const double dinv = L.a[c * kBigLd + c];
+        for (int r = c + 1 + tid; r < K; r += blockDim.x) L.a[r * kBigLd + c] /= dinv;
+        __syncthreads();
+        const int rows = K - c - 1, cols = (K - c - 1) + K;
+        for (int e = tid; e < rows * cols; e += blockDim.x) {
+            const int r = c + 1 + e / cols, k = e % cols;
+            const double l = L.a[r * kBigLd + c];
+            if (k < K - c - 1) {
+                const int kk = c + 1 + k;
+                L.a[r * kBigLd + kk] -= l * L.a[c * kBigLd + kk];
+            } else {
+                const int kk = k - (K - c - 1);
+                L.b[r * kBigLd + kk] -= l * L.b[c * kBigLd + kk];
+            }
+        }
+        __syncthreads();
+    }
+    // back substitution, one right-hand side per thread
+    for (int r = K - 1; r >= 0; --r) {
+        for (int k = tid; k < K; k += blockDim.x) {
+            double acc = L.b[r * kBigLd + k];
+            for (int c = r + 1; c < K; ++c) acc -= L.a[r * kBigLd + c] * L.b[c * kBigLd + k];
+            L.b[r * kBigLd + k] = acc / L.a[r * kBigLd + r];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < KK; e += blockDim.x) X[e] = L.b[(e / K) * kBigLd + e % K];
+    __syncthreads();
+    for (int q = 0; q < s; ++q) big_matmul(K, X, X, X, L);
+    return s;
+}
+
+// Finish the last adjoint IOM2 column, exponentiate tau G (G the corrected
+// augmented matrix of the adjoint Krylov space), the error ratio and the
+// coefficients of mu_k (row 0) and of the moment increments vbar_j (rows j).
+__global__ void __launch_bounds__(1024) k_adj_gexp(PhiCtl *c, AdjGArgs a, double *mat, double *work,
+                                                   double *C, AdjOut *out) {
+    __shared__ BigLds L;
+    const int tid = threadIdx.x;
+    if (a.built >= 1 && c->brk == 0 && !c->beta_zero) {
+        double tot[1];
+        sum_partials<1>(tot, a.nrm_in, a.np, L.red);
+        finalize_column(c, a.built, tot[0], tid == 0, L.red);
+        __syncthreads();
+    }
+    const int m = a.m, p = a.p;
+    const int brk = c->brk;
+    const int bz = c->beta_zero;
+    if (bz) {   // mu_{k+1} = 0: nothing to propagate
+        for (int e = tid; e < (kPmax + 1) * kCoefLd; e += blockDim.x) C[e] = 0.0;
+        if (tid == 0) {
+            out->omega = 0.0;
+            out->me = 0;
+            out->brk = brk;
+            out->beta_zero = 1;
+            out->status = 0;
+        }
+        return;
+    }
+    const int me = (brk > 0 && brk < m) ? brk : m;
+    const double h = (brk > 0 && me == brk) ? 0.0 : c->H[me * kMmax + me - 1];
+    const int na = me + 1;
+    const int K = na + p;
+    const double tau = a.tau;
+    for (int e = tid; e < K * K; e += blockDim.x) {
+        const int r = e / K, q = e % K;
+        double v = 0.0;
+        if (r < me && q < me) v = tau * c->H[r * kMmax + q];
+        else if (r == me && q == me - 1) v = tau * h;
+        else if (r == 0 && q == na) v = tau;
+        else if (r >= na && r + 1 < K && q == r + 1) v = tau;
+        mat[e] = v;
+    }
+    __syncthreads();
+    big_expm(K, mat, mat, work, L);
+    const double beta = c->beta;
+    // t_k^i / i! for the moment weights
+    for (int e = tid; e < (kPmax + 1) * kCoefLd; e += blockDim.x) {
+        const int row = e / kCoefLd, r = e % kCoefLd;
+        double v = 0.0;
+        if (!bz && r < na && row <= p) {
+            const double sr = c->sigma[r];
+            if (row == 0) {
+                v = beta * sr * mat[r * K + 0];
+            } else {
+                // vbar_j += sum_{l < j} t^(j-1-l)/(j-1-l)! I_l
+                const int j = row;
+                for (int l = 0; l < j; ++l) {
+                    double f = 1.0;
+                    for (int i2 = 1; i2 <= j - 1 - l; ++i2) f = f * a.t / i2;
+                    v += f * (beta * sr * mat[r * K + na + l]);
+                }
+            }
+        }
+        C[e] = v;
+    }
+    if (tid == 0) {
+        const double eps = bz ? 0.0 : beta * fabs(mat[me * K + 0]);
+        out->omega = bz ? 0.0 : a.t_out * eps / (tau * a.tol_abs);
+        out->me = bz ? 0 : me;
+        out->brk = brk;
+        out->beta_zero = bz;
+        out->status = (beta != beta || out->omega != out->omega) ? XRB_ENAN : 0;
+    }
+}
+
+// Van Loan: M = int_0^tau a(tau - s) b(s)^T ds is the top-right block of
+// exp(tau [[Hbar_mu, e_1 e_last^T], [0, Hhat_y^T]]); the Z coefficients
+// fold in beta_mu sigma_r (adjoint raw basis) and beta_y sigma_c (forward
+// raw basis) or 1 (the polynomial vectors w_{p-1} .. w_0).
+__global__ void __launch_bounds__(1024) k_adj_vanloan(const PhiCtl *c, const PhiCtl *cy,
+                                                      AdjVArgs a, double *mat, double *work,
+                                                      double *z) {
+    __shared__ BigLds L;
+    const int tid = threadIdx.x;
+    const int me = a.me, my = a.my, p = a.p;
+    const int na = me + 1, nb = my + 1 + p, K = na + nb;
+    const double tau = a.tau;
+    const int brk = c->brk;
+    const double h = (brk > 0 && me == brk) ? 0.0 : c->H[me * kMmax + me - 1];
+    const int brky = cy->brk;
+    const double hy = (my == 0) ? 0.0 : ((brky > 0 && my == brky) ? 0.0 : cy->H[my * kMmax + my - 1]);
+    for (int e = tid; e < K * K; e += blockDim.x) {
+        const int r = e / K, q = e % K;
+        double v = 0.0;
+        if (r < na && q < na) {
+            if (r < me && q < me) v = tau * c->H[r * kMmax + q];
+            else if (r == me && q == me - 1) v = tau * h;
+        } else if (r < na) {
+            if (r == 0 && q == K - 1) v = tau;
+        } else if (q >= na) {
+            // (Hhat_y^T)[rr][qq] = Hhat_y[qq][rr]
+            const int rr = r - na, qq = q - na;
+            double hv = 0.0;
+            if (qq < my && rr < my) hv = cy->H[qq * kMmax + rr];
+            else if (qq == my && rr == my - 1) hv = hy;
+            else if (qq == 0 && rr == my + 1) hv = 1.0;
+            else if (qq >= my + 1 && qq + 1 < nb && rr == qq + 1) hv = 1.0;
+            v = tau * hv;
+        }
+        mat[e] = v;
+    }
+    __syncthreads();
+    big_expm(K, mat, mat, work, L);
+    const double bmu = c->beta;
+    const double by = cy->beta;
+    for (int e = tid; e < kZRows * kZLd; e += blockDim.x) {
+        const int r = e / kZLd, q = e % kZLd;
+        double v = 0.0;
+        if (!c->beta_zero && r < na && q < nb) {
+            double f;
+            if (q <= my) {
+                f = (my == 0) ? 0.0 : by * cy->sigma[q];
+            } else {
+                const int jw = p - (q - my);
+                f = ((a.wzero >> jw) & 1) ? 0.0 : 1.0;
+            }
+            v = bmu * c->sigma[r] * mat[r * K + na + q] * f;
+        }
+        z[e] = v;
+    }
+}
+
+template <int L>
+void lapT_launch(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_lapT<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b);
+}
+
+template <int L>
+void jtv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+    if (epi == kEpiNone) {
+        hipLaunchKernelGGL((k_jtv<kEpiNone, L>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0,
+                           s, M, a, b);
+        return;
+    }
+    const int grid = red_parts(M.n), block = red_block(M.n);
+    if (epi == kEpiIom2)
+        hipLaunchKernelGGL((k_jtv<kEpiIom2, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+    else
+        hipLaunchKernelGGL((k_jtv<kEpiNorm, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+}
+
+template <int L>
+void kpairs_launch(const DevMesh &M, const KPairArgs &k, const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_kpairs<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, k, b);
+}
+
+inline int elem_grid(int n4) {
+    int g = (n4 + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    return g < 1 ? 1 : g;
+}
+
+}  // namespace
+
+void launch_lapT(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
+#define XRB_CALL(L) lapT_launch<L>(M, psi, out, b, s)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
+}
+
+int launch_jtv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+#define XRB_CALL(L) jtv_launch<L>(M, a, epi, b, s)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
+    return epi == kEpiNone ? 0 : red_parts(M.n);
+}
+
+void launch_kpairs(const DevMesh &M, const KPairArgs &k, const Batch &b, hipStream_t s) {
+#define XRB_CALL(L) kpairs_launch<L>(M, k, b, s)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
+}
+
+void launch_lincomb_multi(int n4, const MultiArgs &a, const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb_multi, dim3(elem_grid(n4), b.nm), dim3(kBlock), 0, s, n4, a, b);
+}
+
+void launch_zgemm(int n4, const ZArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(k_zgemm, dim3(elem_grid(n4)), dim3(kBlock), 0, s, n4, a);
+}
+
+void launch_adj_gexp(PhiCtl *c, const AdjGArgs &a, double *mat, double *work, double *C,
+                     AdjOut *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_gexp, dim3(1), dim3(1024), 0, s, c, a, mat, work, C, out);
+}
+
+void launch_adj_vanloan(const PhiCtl *c, const PhiCtl *cy, const AdjVArgs &a, double *mat,
+                        double *work, double *z, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_vanloan, dim3(1), dim3(1024), 0, s, c, cy, a, mat, work, z);
+}
+
+}  // namespace xrb

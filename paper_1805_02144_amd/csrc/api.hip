@@ -11,6 +11,7 @@
 // the same code, so batched and single results come from the same kernels
 // and the same reduction trees.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -31,6 +32,21 @@ struct SchedEntry {
 // stage slots of the scheme drivers
 enum { S_FN, S_V, S_W1, S_W2, S_X1, S_X2, S_U2, S_U3, S_D2, S_D3, S_A3, S_A4, S_T1, S_T2,
        S_UPREV, S_FPREV, S_STATE, S_COUNT };
+
+// What the solution of one accepted forward substep is made of (kept for
+// the adjoint): y(t + s) = sum_{j<p} s^j/j! w_j + beta V_{m+1} c(s), with the
+// raw basis R_0..R_m, its scales and the Hessenberg matrix in a PhiCtl copy.
+struct TapeSub {
+    double t = 0.0, tau = 0.0, t_out = 0.0;
+    int my = 0;        // Krylov size of the accepted attempt, 0 when w_p = 0
+    int out = -1;      // output index the substep lands on, -1 if none
+    int wzero = 0;     // bit j: w_j is zero
+    double *chunk = nullptr;   // device: [PhiCtl][R_0..R_mmax][w_0..w_{kPmax-1}]
+};
+struct PhiTape {
+    int p = 0;
+    std::vector<TapeSub> subs;
+};
 
 // Device workspace of nm members: member k's vectors sit at member 0's
 // address plus k * ws doubles.
@@ -66,6 +82,24 @@ struct Work {
 
 }  // namespace
 
+namespace {
+// Device workspace of the adjoint path (single state).
+struct AdjWork {
+    double *base = nullptr;
+    double *Vmu = nullptr, *Z = nullptr;   // (m_max + 1) vectors each
+    double *mu = nullptr, *mu2 = nullptr, *lapT = nullptr, *e = nullptr, *Dbar = nullptr;
+    double *Ubar2 = nullptr, *Fbar = nullptr, *kacc = nullptr, *wbar = nullptr;
+    double *vb[kPmax + 1] = {};
+    PhiCtl *actl = nullptr;
+    double *small = nullptr;   // partials, coefficients, dense matrices
+    double *dot_parts = nullptr, *nrm_parts = nullptr, *v_parts = nullptr, *vnorm2 = nullptr;
+    double *C = nullptr, *zc = nullptr, *mat = nullptr, *work = nullptr;
+    AdjOut *out = nullptr;
+    AdjOut *h_out = nullptr;   // pinned
+    double *h_vn = nullptr;    // pinned
+};
+}  // namespace
+
 struct xrb_ctx {
     xrb_params prm{};
     int n = 0, n4 = 0;
@@ -89,6 +123,10 @@ struct xrb_ctx {
     std::vector<Pending> ev_pend;
     double prof_ms[XRB_K_COUNT] = {};
     int64_t prof_n[XRB_K_COUNT] = {};
+    // adjoint path: workspace and the substep store of recomputed forwards
+    AdjWork adj;
+    std::vector<double *> tape_chunks;
+    size_t tape_next = 0;
 };
 
 namespace {
@@ -207,6 +245,7 @@ struct MemberPhi {
     bool ready = false;
     bool y_zero = true;
     int io = 0, built = 0, m = 1, wp_zero = 0;
+    double t = 0.0;           // start of the current substep
     int wzero[kPmax + 1] = {};
     xrb_phi_stats st{};
 };
@@ -228,8 +267,23 @@ int upload_plan(xrb_ctx *ctx, Work &W, int half) {
 // are member-0 pointers (member stride W.ws); dt of member k is W.dtk[k];
 // eta must hold V.u + f for every member.  m_warm[k*3 + site] holds the
 // warm start in and the last accepted Krylov size out (site < 0: cold start).
+size_t tape_ctl_doubles() { return (sizeof(PhiCtl) + 255) / 256 * 32; }
+
+// A free substep store chunk (allocated on first use, kept for the context).
+double *tape_chunk(xrb_ctx *ctx) {
+    if (ctx->tape_next < ctx->tape_chunks.size()) return ctx->tape_chunks[ctx->tape_next++];
+    const size_t doubles =
+        tape_ctl_doubles() + (size_t)(ctx->prm.m_max + 1 + kPmax) * (size_t)ctx->n4;
+    double *c = nullptr;
+    if (hipMalloc((void **)&c, sizeof(double) * doubles) != hipSuccess) return nullptr;
+    ctx->tape_chunks.push_back(c);
+    ctx->tape_next = ctx->tape_chunks.size();
+    return c;
+}
+
 int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const *v, int ns,
-              const double *rho, double *const *w_out, int site, xrb_phi_stats *st_out) {
+              const double *rho, double *const *w_out, int site, xrb_phi_stats *st_out,
+              PhiTape *tape = nullptr) {
     const int nm = W.nm, n = ctx->n, n4 = ctx->n4;
     const hipStream_t s = ctx->stream;
     const xrb_params &P = ctx->prm;
@@ -245,6 +299,11 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
     }
     if (ctx->mode == XRB_REPLAY && nm > 1)
         return fail(ctx, XRB_EINVAL, "phi_combo: replay is available for single states only");
+    if (tape && nm > 1) return fail(ctx, XRB_EINVAL, "phi_combo: substep store is single-state");
+    if (tape) {
+        tape->p = p;
+        tape->subs.clear();
+    }
     const int np = red_parts(n);   // partials of every reducing producer
     std::vector<MemberPhi> ms(nm);
     // input norms, warm starts, controller initialisation
@@ -487,7 +546,31 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             mm.st.max_m = std::max(mm.st.max_m, mm.m);
             if (ctx->mode == XRB_RECORD && nm == 1)
                 ctx->sched.push_back({d.tau_u, mm.m, (d.accept ? 1 : 0) | (d.lands ? 2 : 0)});
+            if (d.accept && tape) {
+                // keep this substep's solution basis before the combine overwrites y = w_0
+                TapeSub ts;
+                ts.t = mm.t;
+                ts.tau = d.tau_u;
+                ts.t_out = rho[mm.io];
+                ts.my = d.m_eff;
+                ts.out = d.reached ? mm.io : -1;
+                for (int j = 0; j < p; ++j) ts.wzero |= mm.wzero[j] << j;
+                ts.chunk = tape_chunk(ctx);
+                if (!ts.chunk) return fail(ctx, XRB_ENOMEM, "phi_combo: substep store");
+                double *cv = ts.chunk + tape_ctl_doubles();
+                double *cw = cv + (size_t)(P.m_max + 1) * n4;
+                HIPCHK(hipMemcpyAsync(ts.chunk, &W.ctl[0], sizeof(PhiCtl), hipMemcpyDeviceToDevice, s));
+                if (ts.my > 0)
+                    HIPCHK(hipMemcpyAsync(cv, W.V, sizeof(double) * (size_t)(ts.my + 1) * n4,
+                                          hipMemcpyDeviceToDevice, s));
+                for (int j = 0; j < p; ++j)
+                    if (!mm.wzero[j])
+                        HIPCHK(hipMemcpyAsync(cw + (size_t)j * n4, wptr[j], sizeof(double) * n4,
+                                              hipMemcpyDeviceToDevice, s));
+                tape->subs.push_back(ts);
+            }
             if (d.accept) {
+                mm.t = d.lands ? rho[mm.io] : mm.t + d.tau_u;
                 int zm = 0;
                 for (int j = 0; j < p; ++j) zm |= mm.wzero[j] << j;
                 W.h_plan[kPlanW * k + PF_COMB] = 1 | (zm << 1);
@@ -742,6 +825,373 @@ int set_dt(xrb_ctx *ctx, Work &W, const double *dt) {
     return XRB_OK;
 }
 
+// ------------------------------------------------------------------------
+// Adjoint path (single state)
+// ------------------------------------------------------------------------
+void adj_free(AdjWork &A) {
+    if (A.base) (void)hipFree(A.base);
+    if (A.small) (void)hipFree(A.small);
+    if (A.actl) (void)hipFree(A.actl);
+    if (A.h_out) (void)hipHostFree(A.h_out);
+    if (A.h_vn) (void)hipHostFree(A.h_vn);
+    A = AdjWork{};
+}
+
+int adj_alloc(xrb_ctx *ctx) {
+    AdjWork &A = ctx->adj;
+    if (A.base) return XRB_OK;
+    const size_t n4 = (size_t)ctx->n4;
+    const int mm = ctx->prm.m_max + 1;
+    const size_t nvec = 2 * (size_t)mm + 10 + (kPmax + 1);
+    const size_t small = (size_t)kPartStride * 2 + kVPartStride + (kPmax + 1) +
+                         (size_t)kMultiOut * kCoefLd + (size_t)kZRows * kZLd +
+                         (size_t)kBigMax * kBigMax * 7 + 64;
+    int rc = XRB_OK;
+    auto ck = [&](hipError_t e) {
+        if (e != hipSuccess && rc == XRB_OK) {
+            ctx->err = std::string("adjoint workspace: ") + hipGetErrorString(e);
+            rc = XRB_ENOMEM;
+        }
+    };
+    ck(hipMalloc((void **)&A.base, sizeof(double) * nvec * n4));
+    ck(hipMalloc((void **)&A.small, sizeof(double) * small));
+    ck(hipMalloc((void **)&A.actl, sizeof(PhiCtl)));
+    ck(hipHostMalloc((void **)&A.h_out, sizeof(AdjOut), hipHostMallocDefault));
+    ck(hipHostMalloc((void **)&A.h_vn, sizeof(double) * (kPmax + 1), hipHostMallocDefault));
+    if (rc) {
+        adj_free(A);
+        return rc;
+    }
+    ck(hipMemset(A.base, 0, sizeof(double) * nvec * n4));
+    ck(hipMemset(A.small, 0, sizeof(double) * small));
+    ck(hipMemset(A.actl, 0, sizeof(PhiCtl)));
+    double *p = A.base;
+    A.Vmu = p; p += mm * n4;
+    A.Z = p; p += mm * n4;
+    double **vs[] = {&A.mu, &A.mu2, &A.lapT, &A.e, &A.Dbar, &A.Ubar2, &A.Fbar, &A.kacc, &A.wbar};
+    for (double **v : vs) {
+        *v = p;
+        p += n4;
+    }
+    for (int l = 0; l <= kPmax; ++l) {
+        A.vb[l] = p;
+        p += n4;
+    }
+    double *q = A.small;
+    A.dot_parts = q; q += kPartStride;
+    A.nrm_parts = q; q += kPartStride;
+    A.v_parts = q; q += kVPartStride;
+    A.vnorm2 = q; q += kPmax + 1;
+    A.C = q; q += (size_t)kMultiOut * kCoefLd;
+    A.zc = q; q += (size_t)kZRows * kZLd;
+    A.mat = q; q += (size_t)kBigMax * kBigMax;
+    A.work = q; q += (size_t)kBigMax * kBigMax * 6;
+    A.out = (AdjOut *)q;
+    if (rc) adj_free(A);
+    return rc;
+}
+
+// Adjoint of one phipm_simul_iom2 call whose forward substeps are in tape:
+// vbar[l] (l = 0..p; nullptr entries skipped) = the cotangents of v_l, and
+// kacc += dt int K(mu, y) dt (the A = dt J(u) term), for output cotangents
+// wbar[i].  eta must hold V.u + f at u (the forward's linearisation).
+int adj_phi(xrb_ctx *ctx, const PhiTape &tape, const double *u, const double *eta, double dt,
+            int p, int ns, const double *rho, const double *const *wbar, double *const *vbar,
+            double *kacc, xrb_phi_stats *st) {
+    AdjWork &A = ctx->adj;
+    const int n = ctx->n, n4 = ctx->n4;
+    const hipStream_t s = ctx->stream;
+    const xrb_params &P = ctx->prm;
+    *st = xrb_phi_stats{};
+    if (p < 1 || p > kPmax || ns < 1 || ns > kPmax) return fail(ctx, XRB_EINVAL, "adjoint: bad p or ns");
+    if (!tape.subs.empty() && tape.p != p) return fail(ctx, XRB_EINVAL, "adjoint: tape of another call");
+    Batch b1;
+    b1.nm = 1;
+    const int np = red_parts(n);
+    auto nrm_buf = [&](int col) { return A.nrm_parts + (size_t)(col & 1) * kRedBlocks; };
+    const double *none[1] = {nullptr};
+    const double zc0[1] = {0.0};
+    for (int l = 0; l <= p; ++l)
+        if (vbar[l]) launch_lincomb(n4, vbar[l], 0, none, zc0, 0, b1, s);
+    // Tol = tol * max_i ||wbar_i|| (also initialises actl, rec_coef[0] = 1)
+    launch_norms(n, ns, wbar, A.v_parts, b1, s);
+    launch_phi_init(A.actl, 1, nullptr, 1.0, P.tol, A.v_parts, np, ns, A.vnorm2, b1, s);
+    HIPCHK(hipMemcpyAsync(A.h_vn, A.vnorm2, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    prof_drain(ctx);
+    double smax = 0.0;
+    for (int i = 0; i < ns; ++i) {
+        if (A.h_vn[i] != A.h_vn[i]) return fail(ctx, XRB_ENAN, "adjoint: NaN cotangent");
+        smax = std::max(smax, std::sqrt(A.h_vn[i]));
+    }
+    if (smax == 0.0) return XRB_OK;
+    const double tol_abs = P.tol * smax;
+    // substeps: the forward's, or one per output interval when it had none
+    std::vector<TapeSub> subs = tape.subs;
+    const bool have_y = !subs.empty();
+    if (!have_y)
+        for (int i = 0; i < ns; ++i) {
+            TapeSub ts;
+            ts.t = i ? rho[i - 1] : 0.0;
+            ts.tau = rho[i] - ts.t;
+            ts.t_out = rho[i];
+            ts.out = i;
+            subs.push_back(ts);
+        }
+    double *mu = A.mu, *mu2 = A.mu2;
+    launch_lincomb(n4, mu, 0, none, zc0, 0, b1, s);
+    const double *one_dev = &A.actl->rec_coef[0];
+    for (int k = (int)subs.size() - 1; k >= 0; --k) {
+        const TapeSub &sb = subs[k];
+        if (sb.out >= 0) {
+            const double *vv[2] = {mu, wbar[sb.out]};
+            const double cc[2] = {1.0, 1.0};
+            launch_lincomb(n4, mu, 2, vv, cc, 0, b1, s);
+        }
+        // Krylov space of A^T = dt J^T from mu_{k+1}
+        {
+            const double *vv[1] = {mu};
+            const double *cf[1] = {one_dev};
+            launch_lincomb_dev(n, A.Vmu, 1, vv, cf, A.actl, nrm_buf(0), b1, s);
+        }
+        int m = std::min(std::max(sb.my > 0 ? sb.my : P.m_init, 1), P.m_max);
+        int built = 0;
+        AdjOut o{};
+        for (;;) {
+            for (int j = built; j < m; ++j) {
+                double *rj = A.Vmu + (size_t)j * n4;
+                double *rn = A.Vmu + (size_t)(j + 1) * n4;
+                const double *rm = j > 0 ? A.Vmu + (size_t)(j - 1) * n4 : nullptr;
+                timed(ctx, XRB_K_LAP, [&] { launch_lapT(ctx->M, rj, A.lapT, b1, s); });
+                JvArgs a;
+                a.u = u;
+                a.eta = eta;
+                a.x = rj;
+                a.lx = A.lapT;
+                a.dt = dt;
+                a.out = rn;
+                a.j = j;
+                a.rjm1 = rm;
+                a.ctl = A.actl;
+                a.dot_out = A.dot_parts;
+                timed(ctx, XRB_K_JV_IOM2, [&] { launch_jtv(ctx->M, a, kEpiIom2, b1, s); });
+                timed(ctx, XRB_K_IOM2_UPD, [&] {
+                    launch_iom2_update(n, j, rn, rj, rm, A.actl, nrm_buf(j), np, A.dot_parts, np,
+                                       nrm_buf(j + 1), b1, s);
+                });
+                st->matvecs++;
+            }
+            built = m;
+            AdjGArgs g;
+            g.m = m;
+            g.built = built;
+            g.p = p;
+            g.tau = sb.tau;
+            g.t = sb.t;
+            g.t_out = sb.t_out;
+            g.tol_abs = tol_abs;
+            g.nrm_in = nrm_buf(built);
+            g.np = np;
+            timed(ctx, XRB_K_CTL, [&] { launch_adj_gexp(A.actl, g, A.mat, A.work, A.C, A.out, s); });
+            HIPCHK(hipMemcpyAsync(A.h_out, A.out, sizeof(AdjOut), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            prof_drain(ctx);
+            o = *A.h_out;
+            st->attempts++;
+            st->expms++;
+            if (o.status) return fail(ctx, o.status, "adjoint: NaN in the Krylov process");
+            if (o.beta_zero || o.omega <= P.delta || o.brk || m == P.m_max) {
+                if (!o.beta_zero && o.omega > P.delta && !o.brk) st->rejected++;   // taken at m_max
+                break;
+            }
+            m = std::min(P.m_max, std::max(m + 1, (4 * m) / 3 + 1));
+        }
+        if (o.beta_zero) continue;   // mu_{k+1} = 0 stays 0
+        const int me = o.me;
+        st->accepted++;
+        st->sum_m += me;
+        st->max_m = std::max(st->max_m, me);
+        st->last_m = me;
+        // mu_k and the moment increments in one pass over the basis
+        MultiArgs ma;
+        ma.nout = p + 1;
+        ma.out[0] = mu2;
+        for (int j = 1; j <= p; ++j) {
+            ma.out[j] = vbar[j];
+            ma.accmask |= 1u << j;
+        }
+        ma.nv = me + 1;
+        ma.vbase = A.Vmu;
+        ma.vstride = n4;
+        ma.C = A.C;
+        timed(ctx, XRB_K_COMBINE, [&] { launch_lincomb_multi(n4, ma, b1, s); });
+        // the A-term int K(mu, y) over this substep
+        if (kacc && have_y) {
+            AdjVArgs va;
+            va.me = me;
+            va.my = sb.my;
+            va.p = p;
+            va.tau = sb.tau;
+            va.wzero = sb.wzero;
+            const PhiCtl *cy = (const PhiCtl *)sb.chunk;
+            timed(ctx, XRB_K_CTL, [&] { launch_adj_vanloan(A.actl, cy, va, A.mat, A.work, A.zc, s); });
+            st->expms++;
+            const double *cv = sb.chunk + tape_ctl_doubles();
+            const double *cw = cv + (size_t)(P.m_max + 1) * n4;
+            ZArgs za;
+            za.na = me + 1;
+            za.nb = sb.my + 1 + p;
+            for (int c = 0; c < za.nb; ++c) {
+                if (c <= sb.my) {
+                    za.w[c] = sb.my > 0 ? cv + (size_t)c * n4 : nullptr;
+                } else {
+                    const int jw = p - (c - sb.my);
+                    za.w[c] = ((sb.wzero >> jw) & 1) ? nullptr : cw + (size_t)jw * n4;
+                }
+            }
+            za.z = A.zc;
+            za.Z = A.Z;
+            za.zstride = n4;
+            timed(ctx, XRB_K_VEC, [&] { launch_zgemm(n4, za, s); });
+            KPairArgs kp;
+            kp.a0 = A.Vmu;
+            kp.sa = n4;
+            kp.b0 = A.Z;
+            kp.sb = n4;
+            kp.R = me + 1;
+            kp.scale = dt;
+            kp.out = kacc;
+            kp.accumulate = 1;
+            timed(ctx, XRB_K_JV_OTHER, [&] { launch_kpairs(ctx->M, kp, b1, s); });
+        }
+        std::swap(mu, mu2);
+    }
+    if (vbar[0]) {
+        const double *vv[1] = {mu};
+        const double cc[1] = {1.0};
+        launch_lincomb(n4, vbar[0], 1, vv, cc, 0, b1, s);
+    }
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+// out = J(u)^T w (eta must hold V.u + f at u)
+void jtv_plain(xrb_ctx *ctx, const double *u, const double *eta, const double *w, double *out,
+               int naxpy, const double *const *axv, const double *const *axc) {
+    Batch b1;
+    b1.nm = 1;
+    timed(ctx, XRB_K_LAP, [&] { launch_lapT(ctx->M, w, ctx->adj.lapT, b1, ctx->stream); });
+    JvArgs a;
+    a.u = u;
+    a.eta = eta;
+    a.x = w;
+    a.lx = ctx->adj.lapT;
+    a.dt = 1.0;
+    a.out = out;
+    a.naxpy = naxpy;
+    for (int k = 0; k < naxpy; ++k) {
+        a.axv[k] = axv[k];
+        a.axc[k] = axc[k];
+    }
+    timed(ctx, XRB_K_JV_OTHER, [&] { launch_jtv(ctx->M, a, kEpiNone, b1, ctx->stream); });
+}
+
+// Vector-Jacobian product of one exprb42 step (A = dt J_n, v = dt F_n):
+//   forward  W1 = 3/4 phi_1(3/4 A) v, U2 = u + W1, D2 = F(U2) - F_n - J_n W1,
+//            W2 = phi_1(A) v + phi_3(A) 32/9 dt D2, u_{n+1} = u + W2
+//   reverse  (vbar1_2, vbar3_2) = adjoint of call 2 at Wbar = ubar_{n+1}
+//            Dbar = 32/9 dt vbar3_2,  Ubar2 = (J(U2) - J_n)^T Dbar = K(Dbar, e), e = U2 - u
+//            vbar1_1 = adjoint of call 1 at Wbar = Ubar2
+//            ubar_n = ubar_{n+1} + J_n^T dt (vbar1_1 + vbar1_2) + A-terms of both calls
+// (the direct terms J_n^T Dbar - K(Dbar, e) of D2 and -J_n^T Dbar of F_n
+// cancel against Ubar2 entering through U2 = u + W1; F is quadratic, so
+// J(U2) - J_n = J'[e] exactly.)
+int vjp_exprb42(xrb_ctx *ctx, const double *u, double dt, const double *ubar_np1,
+                double *ubar_n, xrb_phi_stats *st2) {
+    Work &W = ctx->one;
+    AdjWork &A = ctx->adj;
+    const hipStream_t s = ctx->stream;
+    const int n4 = ctx->n4;
+    Batch b1;
+    b1.nm = 1;
+    int rc = set_dt(ctx, W, &dt);
+    if (rc) return rc;
+    ctx->tape_next = 0;
+    PhiTape t1, t2;
+    double *Fn = stage_vec(ctx, W, S_FN), *v = stage_vec(ctx, W, S_V), *W1 = stage_vec(ctx, W, S_W1);
+    double *W2 = stage_vec(ctx, W, S_W2), *U2 = stage_vec(ctx, W, S_U2), *D2 = stage_vec(ctx, W, S_D2);
+    double *a3 = stage_vec(ctx, W, S_A3), *t2v = stage_vec(ctx, W, S_T2);
+    double *ev = stage_vec(ctx, W, S_T1);
+    // keep the cotangent: ubar_n may alias ubar_np1
+    {
+        const double *vv[1] = {ubar_np1};
+        const double cc[1] = {1.0};
+        launch_lincomb(n4, A.wbar, 1, vv, cc, 0, b1, s);
+    }
+    // forward, keeping both calls' substeps
+    rhs_plain(ctx, W, u, Fn);
+    lincomb(ctx, W, v, {Fn}, {1.0}, 1u);
+    launch_linearize(ctx->M, u, W.eta, batch_of(W), s);
+    {
+        const double r1[1] = {0.75};
+        const double *vi[2] = {nullptr, v};
+        double *o1[1] = {W1};
+        rc = phi_batch(ctx, W, u, 1, vi, 1, r1, o1, -1, nullptr, &t1);
+        if (rc) return rc;
+    }
+    lincomb(ctx, W, U2, {u, W1}, {1.0, 1.0});
+    lincomb(ctx, W, ev, {U2, u}, {1.0, -1.0});   // e = U2 - u_n, as the forward step forms it
+    jv_plain(ctx, W, u, ev, t2v, false);
+    rhs_plain(ctx, W, U2, D2);
+    lincomb(ctx, W, D2, {D2, Fn, t2v}, {1.0, -1.0, -1.0});
+    lincomb(ctx, W, a3, {D2}, {32.0 / 9.0}, 1u);
+    {
+        const double r2[1] = {1.0};
+        const double *vii[4] = {nullptr, v, nullptr, a3};
+        double *o2[1] = {W2};
+        rc = phi_batch(ctx, W, u, 3, vii, 1, r2, o2, -1, nullptr, &t2);
+        if (rc) return rc;
+    }
+    // reverse
+    launch_lincomb(n4, A.kacc, 0, nullptr, nullptr, 0, b1, s);
+    {
+        const double r2[1] = {1.0};
+        const double *wb[1] = {A.wbar};
+        double *vb[4] = {nullptr, A.vb[1], nullptr, A.vb[3]};
+        rc = adj_phi(ctx, t2, u, W.eta, dt, 3, 1, r2, wb, vb, A.kacc, &st2[1]);
+        if (rc) return rc;
+    }
+    {
+        const double *vv[1] = {A.vb[3]};
+        const double cc[1] = {32.0 / 9.0 * dt};
+        launch_lincomb(n4, A.Dbar, 1, vv, cc, 0, b1, s);
+    }
+    KPairArgs kp;
+    kp.a0 = A.Dbar;
+    kp.b0 = ev;
+    kp.R = 1;
+    kp.out = A.Ubar2;
+    timed(ctx, XRB_K_JV_OTHER, [&] { launch_kpairs(ctx->M, kp, b1, s); });
+    {
+        const double r1[1] = {0.75};
+        const double *wb[1] = {A.Ubar2};
+        double *vb[2] = {nullptr, A.vb[2]};
+        rc = adj_phi(ctx, t1, u, W.eta, dt, 1, 1, r1, wb, vb, A.kacc, &st2[0]);
+        if (rc) return rc;
+    }
+    {
+        const double *vv[2] = {A.vb[1], A.vb[2]};
+        const double cc[2] = {dt, dt};
+        launch_lincomb(n4, A.Fbar, 2, vv, cc, 0, b1, s);
+    }
+    const double *axv[2] = {A.wbar, A.kacc};
+    const double *one_dev = &A.actl->rec_coef[0];
+    const double *axc[2] = {one_dev, one_dev};
+    jtv_plain(ctx, u, W.eta, A.Fbar, ubar_n, 2, axv, axc);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -831,6 +1281,7 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     M.cen = cen;
     M.lanes = params->lanes ? params->lanes : stencil_lanes(n);
     M.nu = geo.nu;
+    M.two_omega = 2.0 * params->omega;
     M.g = params->gravity;
     *out = ctx;
     return XRB_OK;
@@ -843,6 +1294,8 @@ xrb_status xrb_destroy(xrb_ctx *ctx) {
     for (hipEvent_t ev : ctx->ev_free) (void)hipEventDestroy(ev);
     int rc = free_work(ctx->one);
     rc |= free_work(ctx->ens);
+    adj_free(ctx->adj);
+    for (double *c : ctx->tape_chunks) (void)hipFree(c);
     if (ctx->geo_mem && hipFree(ctx->geo_mem) != hipSuccess) rc = XRB_EDEVICE;
     delete ctx;
     return (e != hipSuccess || rc) ? XRB_EDEVICE : XRB_OK;
@@ -877,6 +1330,70 @@ xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
     launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
     jv_plain(ctx, ctx->one, u, v, jv, false);
     HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out) {
+    if (!ctx || !u || !w || !out || out == u || out == w)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "jtv: bad pointers");
+    int rc = adj_alloc(ctx);
+    if (rc) return (xrb_status)rc;
+    launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    jtv_plain(ctx, u, ctx->one.eta, w, out, 0, nullptr, nullptr);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out) {
+    if (!ctx || !a || !b || !out || out == a || out == b)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "ktv: bad pointers");
+    Batch b1;
+    b1.nm = 1;
+    KPairArgs kp;
+    kp.a0 = a;
+    kp.b0 = b;
+    kp.R = 1;
+    kp.out = out;
+    launch_kpairs(ctx->M, kp, b1, ctx->stream);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+xrb_status xrb_step_vjp(xrb_ctx *ctx, xrb_method method, const double *u, double dt,
+                        const double *sched, int sched_len, const double *ubar_np1,
+                        double *ubar_n, xrb_phi_stats *stats) {
+    if (!ctx || !u || !ubar_np1 || !ubar_n || ubar_n == u || !(dt > 0.0) || sched_len < 0 ||
+        (sched_len > 0 && !sched))
+        return (xrb_status)fail(ctx, XRB_EINVAL, "step_vjp: bad argument");
+    if (method != XRB_EXPRB42) return (xrb_status)fail(ctx, XRB_EINVAL, "step_vjp: exprb42 only");
+    int rc = adj_alloc(ctx);
+    if (rc) return (xrb_status)rc;
+    // the recomputed forward follows `sched` (replay) or, without one, the
+    // free controller from a cold start
+    const int mode0 = ctx->mode;
+    std::vector<SchedEntry> sched0;
+    sched0.swap(ctx->sched);
+    const size_t pos0 = ctx->sched_pos;
+    if (sched && sched_len > 0) {
+        ctx->sched.resize(sched_len);
+        for (int i = 0; i < sched_len; ++i)
+            ctx->sched[i] = {sched[3 * i], (int32_t)sched[3 * i + 1], (int32_t)sched[3 * i + 2]};
+        ctx->mode = XRB_REPLAY;
+    } else {
+        ctx->mode = XRB_FREE;
+    }
+    ctx->sched_pos = 0;
+    xrb_phi_stats st2[2] = {};
+    rc = vjp_exprb42(ctx, u, dt, ubar_np1, ubar_n, st2);
+    ctx->mode = mode0;
+    ctx->sched.swap(sched0);
+    ctx->sched_pos = pos0;
+    if (rc) return (xrb_status)rc;
+    if (stats) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        stats[0] = st2[0];
+        stats[1] = st2[1];
+    }
     return XRB_OK;
 }
 

@@ -103,7 +103,7 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
         }
         double *ce = &geo.cen[4 * (size_t)i];
         ce[0] = xi.x; ce[1] = xi.y; ce[2] = xi.z;
-        ce[3] = 2.0 * prm.omega * xi.z;
+        ce[3] = 1.0 / area;
     }
     const double dxbar = std::sqrt(4.0 * M_PI * R * R / (double)n);
     geo.nu = prm.gamma_h * dxbar * dxbar * dxbar * dxbar / prm.dt_e;

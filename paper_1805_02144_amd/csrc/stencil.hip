@@ -11,6 +11,7 @@
 // identical in all L).  The two-ring dissipation stencil L(L x) takes L x
 // from a preceding one-ring pass (launch_lap4).
 #include "reduce.h"
+#include "stencil_common.h"
 #include "xrb_internal.h"
 
 namespace xrb {
@@ -19,84 +20,7 @@ int stencil_lanes(int n) { return n > 100000 ? 2 : 8; }
 
 namespace {
 
-constexpr int kXcd = 8;   // accelerator dies, each with its own L2
-
-// one block per block/L cells, rounded up to a whole number of blocks per XCD
-inline int cells_grid(int n, int block, int L) {
-    const int cpb = block / L;
-    int g = (n + cpb - 1) / cpb;
-    if (g < 1) g = 1;
-    return (g + kXcd - 1) / kXcd * kXcd;
-}
-
-// Block size of a reducing stencil launch: the partial count is fixed by
-// red_parts(n), so large grids get wider blocks (more waves per CU) rather
-// than more partials; small ones keep 256 threads and a few iterations.
-inline int red_block(int n) { return n > 65536 ? 1024 : 256; }
-
-// Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).
-template <int CTRL>
-__device__ inline double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the L lanes of a cell: for eight, half-row mirror (lane i with
-// 7-i) first; then xor 1 and xor 2 inside each quad.  Every lane ends with
-// the same operands added in the same pairs (only commuted), so the L
-// results are bitwise identical.
-template <int L>
-__device__ inline double grp_sum(double v) {
-    if (L >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
-    if (L >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-    if (L >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
-    return v;
-}
-
-// Cell record: unit centre and Coriolis parameter, two 16-byte loads.
-struct Cell {
-    double x, y, z, f;
-};
-__device__ inline Cell load_cell(const double *__restrict__ cen, int i) {
-    const double2 *p = reinterpret_cast<const double2 *>(cen) + 2 * (size_t)i;
-    const double2 a = p[0], b = p[1];
-    return {a.x, a.y, b.x, b.y};
-}
-
-// Flux and circulation weights of the edge i -> j rebuilt from its two
-// scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).
-struct EdgeW {
-    double ax, ay, az, bx, by, bz;
-};
-__device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al, double be) {
-    EdgeW w;
-    w.ax = al * (cj.x - ci.x);
-    w.ay = al * (cj.y - ci.y);
-    w.az = al * (cj.z - ci.z);
-    w.bx = be * (ci.y * cj.z - ci.z * cj.y);
-    w.by = be * (ci.z * cj.x - ci.x * cj.z);
-    w.bz = be * (ci.x * cj.y - ci.y * cj.x);
-    return w;
-}
-
-// Cells of this block: one contiguous chunk, walked block/L cells at a
-// time.  Workgroups are dispatched round-robin over the XCDs (block b on
-// XCD b mod 8); numbering the chunks XCD-major gives every XCD one
-// contiguous eighth of the grid, swept in order, so the neighbour lines a
-// block gathers were mostly brought into the same L2 by the blocks beside it.
-struct CellRange {
-    int i, end, step;
-};
-template <int L>
-__device__ inline CellRange block_cells(int n) {
-    const int G = (int)gridDim.x, b = (int)blockIdx.x;
-    const int chunk = (G % kXcd) ? b : (b % kXcd) * (G / kXcd) + b / kXcd;
-    const int per = (n + G - 1) / G;
-    const int i0 = chunk * per;
-    const int i1 = i0 + per < n ? i0 + per : n;
-    return {i0 + (int)threadIdx.x / L, i1, (int)blockDim.x / L};
-}
+using namespace stc;
 
 // Every stencil serves a cell with L consecutive lanes (L = 1, 2, 4, 8):
 // lane q takes the neighbour slots q, q + L, ... < 6 and the lanes' edge
@@ -154,7 +78,7 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
                  w.bz * (u[2 * n + i] + u[2 * n + j]);
         }
         z = grp_sum<L>(z);
-        if (q == 0) eta[i] = z + ci.f;
+        if (q == 0) eta[i] = z + M.two_omega * ci.z;
     }
 }
 
@@ -205,7 +129,7 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;       // tangent projection of grad E
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
-        const double eta = zt + ci.f;
+        const double eta = zt + M.two_omega * ci.z;
         const double px = ny * uz - nz * uy, py = nz * ux - nx * uz, pz = nx * uy - ny * ux;
         const double nu = M.nu;
         double o[4];
@@ -335,14 +259,6 @@ void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipSt
 }
 
 }  // namespace
-
-#define XRB_LANES_DISPATCH(CALL)            \
-    switch (M.lanes) {                      \
-    case 1: CALL(1); break;                 \
-    case 2: CALL(2); break;                 \
-    case 4: CALL(4); break;                 \
-    default: CALL(8); break;                \
-    }
 
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
 #define XRB_CALL(L) \

@@ -1,0 +1,102 @@
+// Device helpers shared by the forward and transposed stencil kernels:
+// lane groups, DPP group sums, cell records, edge weights, XCD-aware cell
+// ranges and the lanes-per-cell dispatch.
+#pragma once
+#include "xrb_internal.h"
+
+namespace xrb {
+namespace stc {
+
+
+constexpr int kXcd = 8;   // accelerator dies, each with its own L2
+
+// one block per block/L cells, rounded up to a whole number of blocks per XCD
+inline int cells_grid(int n, int block, int L) {
+    const int cpb = block / L;
+    int g = (n + cpb - 1) / cpb;
+    if (g < 1) g = 1;
+    return (g + kXcd - 1) / kXcd * kXcd;
+}
+
+// Block size of a reducing stencil launch: the partial count is fixed by
+// red_parts(n), so large grids get wider blocks (more waves per CU) rather
+// than more partials; small ones keep 256 threads and a few iterations.
+inline int red_block(int n) { return n > 65536 ? 1024 : 256; }
+
+// Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the L lanes of a cell: for eight, half-row mirror (lane i with
+// 7-i) first; then xor 1 and xor 2 inside each quad.  Every lane ends with
+// the same operands added in the same pairs (only commuted), so the L
+// results are bitwise identical.
+template <int L>
+__device__ inline double grp_sum(double v) {
+    if (L >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+    if (L >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (L >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    return v;
+}
+
+// Cell record: unit centre and reciprocal area, two 16-byte loads.  The
+// Coriolis parameter is rebuilt as (2 Omega) z, the same product the host
+// geometry forms.
+struct Cell {
+    double x, y, z, ra;
+};
+__device__ inline Cell load_cell(const double *__restrict__ cen, int i) {
+    const double2 *p = reinterpret_cast<const double2 *>(cen) + 2 * (size_t)i;
+    const double2 a = p[0], b = p[1];
+    return {a.x, a.y, b.x, b.y};
+}
+
+// Flux and circulation weights of the edge i -> j rebuilt from its two
+// scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).
+struct EdgeW {
+    double ax, ay, az, bx, by, bz;
+};
+__device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al, double be) {
+    EdgeW w;
+    w.ax = al * (cj.x - ci.x);
+    w.ay = al * (cj.y - ci.y);
+    w.az = al * (cj.z - ci.z);
+    w.bx = be * (ci.y * cj.z - ci.z * cj.y);
+    w.by = be * (ci.z * cj.x - ci.x * cj.z);
+    w.bz = be * (ci.x * cj.y - ci.y * cj.x);
+    return w;
+}
+
+// Cells of this block: one contiguous chunk, walked block/L cells at a
+// time.  Workgroups are dispatched round-robin over the XCDs (block b on
+// XCD b mod 8); numbering the chunks XCD-major gives every XCD one
+// contiguous eighth of the grid, swept in order, so the neighbour lines a
+// block gathers were mostly brought into the same L2 by the blocks beside it.
+struct CellRange {
+    int i, end, step;
+};
+template <int L>
+__device__ inline CellRange block_cells(int n) {
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int chunk = (G % kXcd) ? b : (b % kXcd) * (G / kXcd) + b / kXcd;
+    const int per = (n + G - 1) / G;
+    const int i0 = chunk * per;
+    const int i1 = i0 + per < n ? i0 + per : n;
+    return {i0 + (int)threadIdx.x / L, i1, (int)blockDim.x / L};
+}
+
+}  // namespace stc
+
+#define XRB_LANES_DISPATCH(CALL)            \
+    switch (M.lanes) {                      \
+    case 1: CALL(1); break;                 \
+    case 2: CALL(2); break;                 \
+    case 4: CALL(4); break;                 \
+    default: CALL(8); break;                \
+    }
+
+}  // namespace xrb

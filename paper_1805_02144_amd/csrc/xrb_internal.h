@@ -28,8 +28,9 @@ struct DevMesh {
     const double *alpha = nullptr;                 // [n][6]
     const double *beta = nullptr;                  // [n][6]
     const double *cl = nullptr;                    // [n][6]
-    const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, Coriolis 2 Omega sin(lat)
+    const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, 1 / cell area
     double nu = 0.0, g = 0.0;
+    double two_omega = 0.0;                        // Coriolis f_i = two_omega * z_i
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
 };
 
@@ -243,12 +244,72 @@ void launch_phi_init(PhiCtl *ctl, int m0, const int32_t *m0k, double tau0, doubl
                      const double *parts, int np, int nv, double *vnorm2, const Batch &b,
                      hipStream_t s);
 
+// ---------------- adjoint (vector-Jacobian product) path ----------------
+// acc (= or +=) scale * sum_{r < R} coef_r K(a0 + r sa, b0 + r sb)
+struct KPairArgs {
+    const double *a0 = nullptr;
+    int64_t sa = 0;
+    const double *b0 = nullptr;
+    int64_t sb = 0;
+    int R = 0;
+    const double *coef = nullptr;   // device [R], nullptr = all 1
+    double scale = 1.0;
+    double *out = nullptr;
+    int accumulate = 0;
+};
+constexpr int kMultiOut = kPmax + 1;       // mu_k and vbar_1..vbar_p
+constexpr int kCoefLd = kMmax + 2;         // coefficients per output row
+struct MultiArgs {
+    int nout = 0;
+    double *out[kMultiOut] = {};
+    unsigned accmask = 0;
+    int nv = 0;
+    const double *vbase = nullptr;
+    int64_t vstride = 0;
+    const double *C = nullptr;              // device [nout][kCoefLd]
+};
+constexpr int kZRows = kMmax + 1;          // adjoint basis vectors
+constexpr int kZLd = kMmax + 1 + kPmax;    // forward substep solution basis
+struct ZArgs {
+    int na = 0, nb = 0;
+    const double *w[kZLd] = {};
+    const double *z = nullptr;              // device [kZRows][kZLd]
+    double *Z = nullptr;
+    int64_t zstride = 0;
+};
+constexpr int kBigMax = 96;                 // >= kZRows + kZLd: the Van Loan block size
+constexpr int kBigLd = kBigMax + 1;
+struct AdjGArgs {
+    int m = 0, built = 0, p = 0;
+    double tau = 0.0, t = 0.0, t_out = 0.0, tol_abs = 0.0;
+    const double *nrm_in = nullptr;
+    int np = 0;
+};
+struct AdjOut {
+    double omega;
+    int32_t me, brk, beta_zero, status;
+};
+struct AdjVArgs {
+    int me = 0, my = 0, p = 0;
+    double tau = 0.0;
+    int wzero = 0;                          // bit j: w_j of the forward substep is zero
+};
+void launch_lapT(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s);
+int launch_jtv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s);
+void launch_kpairs(const DevMesh &M, const KPairArgs &k, const Batch &b, hipStream_t s);
+void launch_lincomb_multi(int n4, const MultiArgs &a, const Batch &b, hipStream_t s);
+void launch_zgemm(int n4, const ZArgs &a, hipStream_t s);
+void launch_adj_gexp(PhiCtl *c, const AdjGArgs &a, double *mat, double *work, double *C,
+                     AdjOut *out, hipStream_t s);
+void launch_adj_vanloan(const PhiCtl *c, const PhiCtl *cy, const AdjVArgs &a, double *mat,
+                        double *work, double *z, hipStream_t s);
+
 // ---------------- host geometry ----------------
 struct HostGeometry {
     int n = 0;
     std::vector<int32_t> nbr;                              // [n][6]
     std::vector<double> alpha, beta, cl;                   // [n][6]
-    std::vector<double> cen;                               // [n][4] x, y, z, Coriolis
+    std::vector<double> cen;                               // [n][4] x, y, z, 1 / area
     double nu = 0.0;
 };
 int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,

@@ -138,6 +138,123 @@ def jet_leg(X, torch, event_every):
     return out
 
 
+ADJ_STEPS, ADJ_DT, ADJ_OBS = 12, 1800.0, 5000
+
+
+def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
+    """Level-7 twin experiment (N = 163842, n = 655368): the gradient of
+    L = 1/2 sum (h - y)^2 over 5000 observations of a 12-step exprb42
+    trajectory (1800 s steps) with respect to the whole initial state, by
+    per-step vector-Jacobian products on the schedules recorded by the
+    forward.  Reported: forward time (recording), reverse-sweep time (with
+    its forward recomputation), their ratio, and central differences of the
+    replayed forward along seeded directions."""
+    import numpy as np
+    import oracle as O
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    level = 7
+    mesh = get_mesh(level)
+    n = len(mesh["xyz"])
+    u0h, uth, ost, oce, oer = F.adjoint_twin(level, F.config_seed(4), ADJ_STEPS, ADJ_OBS)
+    dev = "cuda:0"
+    ctx = X.Context(mesh, dev, gamma_h=4e-4, tol=1e-10, m_max=40)
+    cells = [torch.tensor(3 * n + oce[ost == k], device=dev) for k in range(ADJ_STEPS + 1)]
+    errs = [torch.tensor(oer[ost == k], dtype=torch.float64, device=dev)
+            for k in range(ADJ_STEPS + 1)]
+    empty = np.zeros((0, 3))
+
+    def run(u_init, record=False, scheds=None):
+        u = u_init.clone()
+        us, rec = [u.clone()], []
+        ctx.reset_history()
+        for k in range(ADJ_STEPS):
+            if record or scheds is not None:
+                ctx.schedule_set(empty if record else scheds[k])
+                ctx.schedule_mode(X.RECORD if record else X.REPLAY)
+            ctx.step("exprb42", u, ADJ_DT)
+            if record or scheds is not None:
+                ctx.schedule_mode(X.FREE)
+            if record:
+                rec.append(ctx.schedule_get())
+            us.append(u.clone())
+        return us, rec
+
+    # truth and observations
+    tru, _ = run(torch.tensor(uth, dtype=torch.float64, device=dev))
+    ys = [tru[k][cells[k]] + errs[k] for k in range(ADJ_STEPS + 1)]
+
+    def loss(us):
+        return sum(0.5 * float(((us[k][cells[k]] - ys[k]) ** 2).sum())
+                   for k in range(1, ADJ_STEPS + 1))
+
+    u0 = torch.tensor(u0h, dtype=torch.float64, device=dev)
+
+    def gradient(us, scheds, stats=None):
+        g = torch.zeros(4 * n, dtype=torch.float64, device=dev)
+        for k in range(ADJ_STEPS, 0, -1):
+            g.index_add_(0, cells[k], us[k][cells[k]] - ys[k])
+            if stats is None:
+                g = ctx.step_vjp("exprb42", us[k - 1], ADJ_DT, g, sched=scheds[k - 1])
+            else:
+                g, st = ctx.step_vjp("exprb42", us[k - 1], ADJ_DT, g, sched=scheds[k - 1],
+                                     return_stats=True)
+                stats.append(st)
+        return g
+
+    us, scheds = run(u0, record=True)            # warm-up: workspaces, substep store
+    gradient(us, scheds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    us, scheds = run(u0, record=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = gradient(us, scheds)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = []
+    gradient(us, scheds, st)
+    L0 = loss(us)
+    fwd, bwd = t1 - t0, t2 - t1
+    # central differences of the replayed forward
+    # central differences of the replayed forward.  eps = 1e-5 (times the
+    # block RMS): at this size the replayed discrete map is not smooth below
+    # ~1e-9 relative (IOM2 near-breakdowns; the oracle shows the same), so
+    # smaller steps measure that roughness rather than the gradient.
+    rng = np.random.default_rng(F.config_seed(4))
+    scal = np.repeat([np.sqrt(np.mean(u0h[b * n:(b + 1) * n] ** 2)) for b in range(4)], n)
+    fd = []
+    eps = 1e-5
+    for _ in range(fd_dirs):
+        d = torch.tensor(rng.standard_normal(4 * n) * scal, device=dev)
+        lp = loss(run(u0 + eps * d, scheds=scheds)[0])
+        lm = loss(run(u0 - eps * d, scheds=scheds)[0])
+        f = (lp - lm) / (2 * eps)
+        a = float(g @ d)
+        fd.append(abs(f - a) / abs(a))
+    agg = {}
+    for s2 in st:
+        for c in s2:
+            for k2 in ("attempts", "rejected", "accepted", "matvecs", "expms", "sum_m"):
+                agg[k2] = agg.get(k2, 0) + c[k2]
+    out = {"workload": "exprb42, 12 steps of 1800 s, level-7 grid (N=163842, n=655368), "
+                       "5000 depth observations (twin experiment), FP64, tol 1e-10, m_max 40",
+           "loss": L0, "forward_ms": 1e3 * fwd, "reverse_ms": 1e3 * bwd,
+           "adjoint_over_forward": bwd / fwd, "fd_rel_err_max": max(fd) if fd else None,
+           "fd_directions": fd_dirs, "fd_eps": eps, "adjoint_krylov": agg}
+    if cpu:
+        s = O.SWE(mesh, gamma_h=4e-4)
+        gh = np.zeros(4 * n)
+        gh[3 * n + oce[ost == ADJ_STEPS]] = 1.0
+        tc = time.perf_counter()
+        s.step_vjp("exprb42", u0h, ADJ_DT, gh, O.opts())
+        out["cpu_oracle_step_vjp_s"] = time.perf_counter() - tc
+        out["cpu_oracle_note"] = "one step vector-Jacobian product (forward recomputation " \
+                                 "included), serial C oracle, free controller"
+    ctx.close()
+    return out
+
+
 def cpu_baseline(mesh, u0_host, steps):
     import oracle as O
     s = O.SWE(mesh)
@@ -177,6 +294,9 @@ def main():
     ap.add_argument("--no-jet", action="store_true")
     ap.add_argument("--jet-only", action="store_true",
                     help="run only the level-8 leg (for profiling it alone)")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the level-7 adjoint leg")
     ap.add_argument("--event-every", type=int, default=16,
                     help="time every N-th launch of each kernel with HIP events")
     args = ap.parse_args()
@@ -194,6 +314,9 @@ def main():
 
     if args.jet_only:
         print(json.dumps({"level8_jet": jet_leg(X, torch, args.event_every)}))
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(X, torch, cpu=not args.no_cpu)}))
         return
 
     level = 6
@@ -248,6 +371,7 @@ def main():
 
     ens = None if args.no_ensemble else ensemble_leg(X, torch, mesh)
     jet = None if args.no_jet else jet_leg(X, torch, args.event_every)
+    adj = None if args.no_adjoint else adjoint_leg(X, torch, cpu=not args.no_cpu)
 
     cpu = None
     if not args.no_cpu:
@@ -276,6 +400,7 @@ def main():
         "krylov_per_step": per_pass,
         "ensemble": ens,
         "level8_jet": jet,
+        "adjoint": adj,
         "device_time_fraction": (tot_ms * 1e-3) / elapsed,
     }
     print(json.dumps(out))

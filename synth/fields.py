@@ -220,6 +220,36 @@ def ensemble_states(level, seed, members=64):
     return U, dts
 
 
+def adjoint_twin(level, seed, steps=12, n_obs=5000, truth_amp=20.0, noise=5.0):
+    """Inputs of the twin experiment of the adjoint workload: the initial
+    state (as sh_balanced_state), the truth's initial state (that state plus
+    an independent SH(truth_amp) depth perturbation with its balanced
+    velocity), n_obs distinct (step, cell) pairs with step in 1..steps, drawn
+    uniformly without replacement, and N(0, noise^2) observation errors.
+    The observations are y = h_truth(step, cell) + error, with h_truth from
+    the caller's own integration of the truth."""
+    xyz = get_mesh(level)["xyz"]
+    n = len(xyz)
+    u0 = sh_balanced_state(level, seed)
+    hp, fun = sh_perturbation(Stream(seed, 7), xyz, truth_amp)
+    ut = u0 + pack(balanced_velocity(fun, xyz), hp)
+    st = Stream(seed, 8)
+    total = steps * n
+    if n_obs > total:
+        raise ValueError("more observations than (step, cell) pairs")
+    chosen, seen = [], set()
+    while len(chosen) < n_obs:
+        for k in st.integers(2 * (n_obs - len(chosen)), total):
+            k = int(k)
+            if k not in seen:
+                seen.add(k)
+                chosen.append(k)
+                if len(chosen) == n_obs:
+                    break
+    idx = np.array(chosen, dtype=np.int64)
+    return u0, ut, 1 + idx // n, idx % n, noise * st.normal(n_obs)
+
+
 def config_seed(index):
     return BASE_SEED + index
 

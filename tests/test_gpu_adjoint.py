@@ -191,3 +191,28 @@ def test_step_vjp_central_difference_on_gpu(X):
         fd = ubar @ (psi(u0 + eps * d) - psi(u0 - eps * d)) / (2 * eps)
         say("  fd", fd, "adjoint", g @ d)
         assert abs(fd - g @ d) <= 1e-8 * abs(g @ d)
+
+
+def test_level7_step_vjp_parity(X):
+    """The adjoint workload's shape: level 7, an observation-like cotangent
+    (depth at a seeded subset of cells), one exprb42 step of 1800 s, the
+    forward replayed from the oracle's schedule."""
+    mesh = get_mesh(7)
+    s = O.SWE(mesh)
+    n = s.n
+    u0, _, ost, oce, oer = F.adjoint_twin(7, F.config_seed(4), 12, 5000)
+    _, arr = _record_step(s, u0, 1800.0)
+    ubar = np.zeros(4 * n)
+    sel = oce[ost == 1]
+    ubar[3 * n + sel] = oer[ost == 1]
+    say("level 7 step_vjp, attempts", len(arr))
+    ref, ast = s.step_vjp("exprb42", u0, 1800.0, ubar,
+                          O.opts(mode=O.REPLAY, sched=O.schedule_from_array(arr)))
+    ctx = X.Context(mesh, "cuda:0")
+    got, gst = ctx.step_vjp("exprb42", u0, 1800.0, ubar, sched=arr, return_stats=True)
+    got = to_np(got)
+    for a, g in zip(ast, gst):
+        assert (a["accepted"], a["sum_m"], a["attempts"]) == (g["accepted"], g["sum_m"], g["attempts"])
+    say("  rel", blocks_rel(got, ref, n))
+    assert blocks_rel(got, ref, n) < TOL
+    ctx.close()

@@ -38,6 +38,39 @@ DT = 3600.0
 EVALS_PER_STEP = {"pexprb43": 2, "exprb53": 3}
 
 
+# Kernel sources of the roofline kernel: a PMC traffic figure in profiles/ is
+# used only while these hash to the value it was taken on.
+TRAFFIC_SOURCES = ["paper_1805_02144_amd/csrc/stencil.hip", "paper_1805_02144_amd/csrc/stencil_common.h",
+                   "paper_1805_02144_amd/csrc/reduce.h", "paper_1805_02144_amd/csrc/xrb_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_l6_jv_iom2_traffic.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the roofline kernel from the committed PMC
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain
+    device copy of known size gives), or None if the kernel changed since."""
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                kv[k.strip()] = v.strip().strip("`")
+        if kv.get("source_sha") != kernel_source_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -295,6 +328,9 @@ def main():
     ap.add_argument("--jet-only", action="store_true",
                     help="run only the level-8 leg (for profiling it alone)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three 64 MiB device-to-device copies (the reference "
+                         "kernel for scaling PMC byte counters)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the level-7 adjoint leg")
     ap.add_argument("--event-every", type=int, default=16,
@@ -351,9 +387,13 @@ def main():
     ms, timed_n, all_n = prof["jv_iom2"]
     avg_s = ms * 1e-3 / max(timed_n, 1)
     achieved = JV_IOM2_BYTES_PER_CELL * n / avg_s / 1e9 if timed_n else 0.0
+    traffic = measured_traffic()
     roofline = {"bound": "hbm", "kernel": "k_jv<kEpiIom2>", "achieved": achieved,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": None, "avg_us": avg_s * 1e6, "launches": all_n,
+                "traffic": traffic,
+                "traffic_over_algorithmic": (traffic / (JV_IOM2_BYTES_PER_CELL * n)
+                                             if traffic else None),
+                "avg_us": avg_s * 1e6, "launches": all_n,
                 "timed_launches": timed_n, "bytes_per_cell": JV_IOM2_BYTES_PER_CELL, "cells": n}
     avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     counts = {k: v[2] for k, v in prof.items()}
@@ -405,6 +445,12 @@ def main():
     }
     print(json.dumps(out))
     ctx.close()
+    if args.copy_calibration:
+        a = torch.ones(1 << 23, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

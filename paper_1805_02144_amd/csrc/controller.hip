@@ -168,13 +168,12 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
             Bm[e] = v;
         }
         __syncthreads();
+        // 1-norm of tau Hhat: a column per thread
+        double csum = 0.0;
+        if (tid < K)
+            for (int r = 0; r < K; ++r) csum += fabs(Bm[r * kLd + tid]);
+        const double nrm = block_max(csum, red);
         if (tid == 0) {
-            double nrm = 0.0;
-            for (int q = 0; q < K; ++q) {
-                double cs = 0.0;
-                for (int r = 0; r < K; ++r) cs += fabs(Bm[r * kLd + q]);
-                nrm = cs > nrm ? cs : nrm;
-            }
             int s = 0;
             double sc = 1.0;
             if (!(nrm < 1e300)) {

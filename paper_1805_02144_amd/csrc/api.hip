@@ -438,7 +438,7 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             ca.wp_zero = mm.wp_zero;
             ca.built = mm.built;
             ca.nrm_buf = mm.built & 1;
-            ca.n_nrm_in = np;
+            ca.n_nrm_in = upd_parts(n);   // the last column's norm comes from an IOM2 update
             ca.t_out = rho[mm.io];
             ca.n4 = (double)n4;
             ca.delta = P.delta;
@@ -513,7 +513,8 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             a.dot_out = W.dot_parts;
             timed(ctx, XRB_K_JV_IOM2, [&] { launch_jv(ctx->M, a, kEpiIom2, bj, s); });
             timed(ctx, XRB_K_IOM2_UPD, [&] {
-                launch_iom2_update(n, j, rn, rj, rm, W.ctl, nrm_buf(j), np, W.dot_parts, np,
+                launch_iom2_update(n, j, rn, rj, rm, W.ctl, nrm_buf(j), j == 0 ? np : upd_parts(n),
+                                   W.dot_parts, np,
                                    nrm_buf(j + 1), bj, s);
             });
         }
@@ -976,7 +977,8 @@ int adj_phi(xrb_ctx *ctx, const PhiTape &tape, const double *u, const double *et
                 a.dot_out = A.dot_parts;
                 timed(ctx, XRB_K_JV_IOM2, [&] { launch_jtv(ctx->M, a, kEpiIom2, b1, s); });
                 timed(ctx, XRB_K_IOM2_UPD, [&] {
-                    launch_iom2_update(n, j, rn, rj, rm, A.actl, nrm_buf(j), np, A.dot_parts, np,
+                    launch_iom2_update(n, j, rn, rj, rm, A.actl, nrm_buf(j),
+                                       j == 0 ? np : upd_parts(n), A.dot_parts, np,
                                        nrm_buf(j + 1), b1, s);
                 });
                 st->matvecs++;
@@ -991,7 +993,7 @@ int adj_phi(xrb_ctx *ctx, const PhiTape &tape, const double *u, const double *et
             g.t_out = sb.t_out;
             g.tol_abs = tol_abs;
             g.nrm_in = nrm_buf(built);
-            g.np = np;
+            g.np = upd_parts(n);
             timed(ctx, XRB_K_CTL, [&] { launch_adj_gexp(A.actl, g, A.mat, A.work, A.C, A.out, s); });
             HIPCHK(hipMemcpyAsync(A.h_out, A.out, sizeof(AdjOut), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));

@@ -291,7 +291,7 @@ int launch_iom2_update(int n, int j, double *rjp1, const double *rj, const doubl
                        PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
                        int np_dot, double *nrm_out, const Batch &b, hipStream_t s) {
     const int n4 = 4 * n;
-    const int grid = red_parts(n);
+    const int grid = upd_parts(n);
     hipLaunchKernelGGL(k_iom2_update, dim3(grid, b.nm), dim3(kRedBlock), 0, s, n4, j, rjp1, rj,
                        rjm1, ctl, nrm_in, np_nrm, dot_in, np_dot, nrm_out, b);
     return grid;

@@ -106,6 +106,15 @@ inline int red_grid(int items, int block) {
 // every producer of a partial family writes the same number of partials).
 inline int red_parts(int n) { return red_grid(8 * n, 256); }
 
+// Blocks of the IOM2 update (a streaming kernel over 4n values whose
+// prologue sums the previous kernels' partials): about 4096 values per
+// block, between 64 and kRedBlocks blocks.  Its norm partials form a family
+// of this size, which the kernels that finish a column are told explicitly.
+inline int upd_parts(int n) {
+    const long g = (4L * n + 4095) / 4096;
+    return (int)(g < 64 ? 64 : (g > kRedBlocks ? kRedBlocks : g));
+}
+
 template <class T>
 __host__ __device__ inline T *member_ptr(T *p, int64_t stride, int k) {
     return p ? p + stride * k : p;

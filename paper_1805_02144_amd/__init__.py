@@ -306,3 +306,61 @@ class Context:
         a = np.zeros((max(1, n.value), 3))
         self._check(lib().xrb_schedule_get(self.h, a.ctypes.data_as(_dp), n.value, C.byref(n)))
         return a[:n.value]
+
+
+def _trajectory_function():
+    torch = _torch()
+
+    class _Trajectory(torch.autograd.Function):
+        """States u_0..u_K of K steps of a scheme, differentiable in u_0.
+        Forward: each step runs in RECORD mode and its schedule is kept with a
+        checkpoint of its input state.  Backward: for k = K..1,
+        g <- vjp(u_{k-1}, g) + dL/du_{k-1}, each VJP replaying step k's
+        schedule (xrb_step_vjp recomputes the step on the device)."""
+
+        @staticmethod
+        def forward(fctx, u0, ctx, dts, method):
+            states = [u0.detach().clone()]
+            scheds = []
+            u = u0.detach().clone()
+            ctx.reset_history()
+            for dt in dts:
+                ctx.schedule_set(np.zeros((0, 3)))
+                ctx.schedule_mode(RECORD)
+                try:
+                    ctx.step(method, u, float(dt))
+                finally:
+                    ctx.schedule_mode(FREE)
+                scheds.append(ctx.schedule_get())
+                states.append(u.clone())
+            fctx.ctx, fctx.dts, fctx.method, fctx.scheds = ctx, list(dts), method, scheds
+            fctx.save_for_backward(*states[:-1])
+            return torch.stack(states)
+
+        @staticmethod
+        def backward(fctx, grad):
+            states = fctx.saved_tensors
+            g = grad[-1].contiguous()
+            for k in range(len(fctx.dts), 0, -1):
+                g = fctx.ctx.step_vjp(fctx.method, states[k - 1], fctx.dts[k - 1], g,
+                                      sched=fctx.scheds[k - 1])
+                g = g + grad[k - 1]
+            return g, None, None, None
+
+    return _Trajectory
+
+
+_TRAJ = None
+
+
+def trajectory(ctx, u0, dts, method="exprb42"):
+    """Run len(dts) steps from u0 (float64 device tensor of length 4N) and
+    return the states [K+1, 4N]; with u0.requires_grad the result is
+    differentiable in u0 (backward by per-step vector-Jacobian products on the
+    recorded schedules; exprb42 only)."""
+    global _TRAJ
+    if method != "exprb42":
+        raise ValueError("trajectory gradients are available for exprb42")
+    if _TRAJ is None:
+        _TRAJ = _trajectory_function()
+    return _TRAJ.apply(u0, ctx, list(dts), method)

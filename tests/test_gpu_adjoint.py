@@ -216,3 +216,35 @@ def test_level7_step_vjp_parity(X):
     say("  rel", blocks_rel(got, ref, n))
     assert blocks_rel(got, ref, n) < TOL
     ctx.close()
+
+
+def test_autograd_trajectory(X):
+    """X.trajectory as a torch.autograd.Function: the gradient of a loss on
+    the states (observations of the depth) against the oracle's trajectory
+    gradient, and the states themselves against plain steps."""
+    import torch
+    ctx, s = setup(X, 3)
+    n = s.n
+    u0h = F.initial_state("c1_exprb42_l4", level=3)
+    dt, steps = 1800.0, 3
+    rng = np.random.default_rng(45)
+    obs_step = rng.integers(1, steps + 1, 50)
+    obs_cell = rng.choice(n, 50, replace=False)
+    obs_val = u0h[3 * n + obs_cell] + rng.normal(0.0, 5.0, 50)
+    L_ref, g_ref, _ = O.exprb42_loss_grad(s, u0h, dt, steps, obs_step, obs_cell, obs_val)
+    u0 = torch.tensor(u0h, device="cuda:0", requires_grad=True)
+    states = X.trajectory(ctx, u0, [dt] * steps)
+    y = torch.tensor(obs_val, device="cuda:0")
+    r = states[torch.tensor(obs_step, device="cuda:0"), torch.tensor(3 * n + obs_cell, device="cuda:0")] - y
+    loss = 0.5 * (r * r).sum()
+    loss.backward()
+    lv = float(loss.detach())
+    say("autograd loss", lv, "oracle", L_ref)
+    assert abs(lv - L_ref) <= 1e-9 * L_ref
+    assert blocks_rel(u0.grad.detach().cpu().numpy(), g_ref, n) < TOL
+    # the states equal plain steps
+    u = torch.tensor(u0h, device="cuda:0")
+    ctx.reset_history()
+    for k in range(steps):
+        ctx.step("exprb42", u, dt)
+    assert np.array_equal(to_np(u), states[-1].detach().cpu().numpy())

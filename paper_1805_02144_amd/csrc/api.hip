@@ -206,7 +206,8 @@ void jv_plain(xrb_ctx *ctx, const Work &W, const double *u, const double *x, dou
               bool scale_dt) {
     Batch b = batch_of(W);
     if (!scale_dt) b.dtk = nullptr;
-    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, x, W.lap, b, ctx->stream); });
+    if (!jv_fuses_lap(ctx->M, b.nm))
+        timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, x, W.lap, b, ctx->stream); });
     JvArgs a;
     a.u = u;
     a.eta = W.eta;
@@ -467,7 +468,8 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
                 double *dst = (double *)wptr[j];
                 if (any_prod) {
                     const Batch bp = batch_of(W, W.plan, PF_REC_PROD, j);
-                    timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, wptr[j - 1], W.lap, bp, s); });
+                    if (!jv_fuses_lap(ctx->M, bp.nm))
+                        timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, wptr[j - 1], W.lap, bp, s); });
                     a.u = u;
                     a.eta = W.eta;
                     a.x = wptr[j - 1];
@@ -500,7 +502,8 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             double *rj = W.V + (size_t)j * n4;
             double *rn = W.V + (size_t)(j + 1) * n4;
             const double *rm = j > 0 ? W.V + (size_t)(j - 1) * n4 : nullptr;
-            timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, W.lap, bj, s); });
+            if (!jv_fuses_lap(ctx->M, bj.nm))
+                timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, W.lap, bj, s); });
             JvArgs a;
             a.u = u;
             a.eta = W.eta;

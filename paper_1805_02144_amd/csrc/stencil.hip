@@ -9,7 +9,8 @@
 // cost more than it hides).  Each lane gathers its neighbours, forms their
 // edge terms, and a fixed DPP butterfly over the L lanes sums them (bitwise
 // identical in all L).  The two-ring dissipation stencil L(L x) takes L x
-// from a preceding one-ring pass (launch_lap4).
+// from a preceding one-ring pass (launch_lap4), or, in small eight-lane
+// launches, forms it in the product kernel with the same rounding.
 #include "reduce.h"
 #include "stencil_common.h"
 #include "xrb_internal.h"
@@ -17,6 +18,12 @@
 namespace xrb {
 
 int stencil_lanes(int n) { return n > 100000 ? 2 : 8; }
+
+// The product forms L x itself (eight lanes per cell) for launches over few
+// cells in all, where the saved launch and round trip pay; large grids and
+// ensembles keep the separate k_lap4 pass (the extra gathers cost more
+// there).  Both forms give the same bits.
+bool jv_fuses_lap(const DevMesh &M, int nm) { return M.lanes == 8 && (long)nm * M.n <= 200000L; }
 
 namespace {
 
@@ -144,7 +151,15 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 
 // out = dt*J(u) x + sum_k c_k v_k, with an optional reduction epilogue
 // (IOM2: raw dot partials; recurrence: norm partials).
-template <int EPI, int L>
+// FL (eight lanes per cell only): the two-ring dissipation term takes L x
+// from inside the kernel instead of from a preceding k_lap4 pass -- one
+// launch and one vector round trip less per product, for more gathers per
+// lane.  Each lane forms L x at its neighbour j over j's ring with the sum
+// tree the eight-lane group sum of k_lap4 applies, (t0 + t1) + ((t2 + t5) +
+// (t3 + t4)), products rounded on their own; L x at i is the group sum of
+// the lanes' own-edge terms.  The result is therefore bit-identical to the
+// two-pass form, and the launcher may choose either per call.
+template <int EPI, int L, bool FL>
 __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
     const int mk = blockIdx.y;
@@ -176,6 +191,10 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
         const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
         double d[4] = {0.0, 0.0, 0.0, 0.0};
+        double lxi[4] = {0.0, 0.0, 0.0, 0.0};   // FL: this lane's edge term of L x at i
+        double lxj[4] = {0.0, 0.0, 0.0, 0.0};   // FL: L x at this lane's neighbour
+        double cl_s = 0.0;                      // FL: this lane's c (0 without an edge)
+        const double xs_i[4] = {xx, xy, xz, xh};
 #pragma unroll(L >= 4 ? 2 : 2)
         for (int s = q; s < 6; s += L) {
             const int e = 6 * i + s;
@@ -193,16 +212,50 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
             dv += w.ax * (fx + (wh * vx + vh * wx)) + w.ay * (fy + (wh * vy + vh * wy)) +
                   w.az * (fz + (wh * vz + vh * wz));
             zt += w.bx * (xx + vx) + w.by * (xy + vy) + w.bz * (xz + vz);
+            if (FL) {
+                // no contraction: every product is rounded on its own, as the
+                // single-term lane sums of the two-pass form are
+#pragma clang fp contract(off)
+                const double xs_j[4] = {vx, vy, vz, vh};
+                double t[6][4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) d[b] += c * (lx[b * n + j] - lx[b * n + i]);
+                for (int tt = 0; tt < 6; ++tt) {
+                    const int ej = 6 * j + tt;
+                    const int k = M.nbr[ej];
+                    const double cj = M.cl[ej];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) t[tt][b] = cj * (x[b * n + k] - xs_j[b]);
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    lxj[b] = (t[0][b] + t[1][b]) + ((t[2][b] + t[5][b]) + (t[3][b] + t[4][b]));
+                    lxi[b] = c * (xs_j[b] - xs_i[b]);
+                }
+                cl_s = c;
+            } else {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) d[b] += c * (lx[b * n + j] - lx[b * n + i]);
+            }
+        }
+        if (FL) {
+            // the two-pass form's d = group sum of c_s (L x_j - L x_i)
+#pragma clang fp contract(off)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const double li = grp_sum<L>(lxi[b]);
+                const double ts = cl_s * (lxj[b] - li);
+                d[b] = grp_sum<L>(ts);
+            }
         }
         gx = grp_sum<L>(gx);
         gy0 = grp_sum<L>(gy0);
         gz0 = grp_sum<L>(gz0);
         dv = grp_sum<L>(dv);
         zt = grp_sum<L>(zt);
+        if (!FL) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) d[b] = grp_sum<L>(d[b]);
+            for (int b = 0; b < 4; ++b) d[b] = grp_sum<L>(d[b]);
+        }
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
@@ -244,18 +297,29 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
     }
 }
 
-template <int L>
-void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+template <int L, bool FL>
+void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
     if (epi == kEpiNone) {
-        hipLaunchKernelGGL((k_jv<kEpiNone, L>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0,
-                           s, M, a, b);
+        hipLaunchKernelGGL((k_jv<kEpiNone, L, FL>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256),
+                           0, s, M, a, b);
         return;
     }
     const int grid = red_parts(M.n), block = red_block(M.n);
     if (epi == kEpiIom2)
-        hipLaunchKernelGGL((k_jv<kEpiIom2, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+        hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
     else
-        hipLaunchKernelGGL((k_jv<kEpiNorm, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+        hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+}
+
+template <int L>
+void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+    if constexpr (L == 8) {
+        if (jv_fuses_lap(M, b.nm)) {
+            jv_launch_t<8, true>(M, a, epi, b, s);
+            return;
+        }
+    }
+    jv_launch_t<L, false>(M, a, epi, b, s);
 }
 
 }  // namespace

@@ -195,6 +195,10 @@ struct JvArgs {
     double *dot_out = nullptr;
     double *nrm_out = nullptr;
 };
+// When jv_fuses_lap(M, b.nm) holds the product forms L x itself and ignores
+// a.lx, so callers skip the launch_lap4 pass that would feed it; the two
+// forms give the same bits.
+bool jv_fuses_lap(const DevMesh &M, int nm);
 int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s);
 
 // out = sum_k coef[k] * vec[k] (coefficients inside PhiCtl, offset per member);

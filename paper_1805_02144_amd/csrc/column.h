@@ -33,8 +33,23 @@ __device__ inline double block_max(double v, double *lds) {
     return r;
 }
 
-__device__ inline ColumnScale finalize_column(PhiCtl *c, int j, double ss, bool write,
-                                              double *lds) {
+// |column q| of the leading j x j block of H for q = threadIdx.x (0 for
+// threads past it); its block maximum is the ||H||_1 of the breakdown test.
+__device__ inline double column_abs_sum(const PhiCtl *c, int j) {
+    const int q = threadIdx.x;
+    double cs = 0.0;
+    if (q < j) {
+        if (q > 0) cs = fabs(c->H[(q - 1) * kMmax + q]);
+        cs += fabs(c->H[q * kMmax + q]);
+        if (q + 1 < j) cs += fabs(c->H[(q + 1) * kMmax + q]);
+    }
+    return cs;
+}
+
+// Column finalisation given ss = ||R_j||^2 and, for j >= 1, bn = ||H||_1 of
+// the leading j x j block.
+__device__ inline ColumnScale finalize_column_bn(PhiCtl *c, int j, double ss, double bn,
+                                                 bool write) {
     const double h = sqrt(ss);
     if (j == 0) {
         if (write) {
@@ -46,14 +61,6 @@ __device__ inline ColumnScale finalize_column(PhiCtl *c, int j, double ss, bool 
         }
         return {h > 0.0 ? 1.0 / h : 0.0, !(h > 0.0)};
     }
-    const int q = threadIdx.x;
-    double cs = 0.0;
-    if (q < j) {
-        if (q > 0) cs = fabs(c->H[(q - 1) * kMmax + q]);
-        cs += fabs(c->H[q * kMmax + q]);
-        if (q + 1 < j) cs += fabs(c->H[(q + 1) * kMmax + q]);
-    }
-    const double bn = block_max(cs, lds);
     if (!(h > 1e-14 * bn)) {
         if (write) {
             if (h != h) c->dec.status = XRB_ENAN;
@@ -68,6 +75,12 @@ __device__ inline ColumnScale finalize_column(PhiCtl *c, int j, double ss, bool 
         c->sigma[j] = 1.0 / h;
     }
     return {1.0 / h, 0};
+}
+
+__device__ inline ColumnScale finalize_column(PhiCtl *c, int j, double ss, bool write,
+                                              double *lds) {
+    const double bn = j > 0 ? block_max(column_abs_sum(c, j), lds) : 0.0;
+    return finalize_column_bn(c, j, ss, bn, write);
 }
 
 }  // namespace xrb

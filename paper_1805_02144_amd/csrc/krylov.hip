@@ -88,31 +88,83 @@ __global__ void __launch_bounds__(kRedBlock) k_lincomb_dev(int n4, double *__res
 }
 
 // IOM2 update of column j (classical two-term Gram-Schmidt) and its norm.
+// Latency shape: the thread's first kUpdPre elements of w, R_j and R_{j-1}
+// are requested before the prologue (the column scale needs the previous
+// kernels' partials and H), and the prologue issues all its loads at once
+// and reduces the three sums and the column maximum behind one barrier --
+// in the same order as separate block reductions would.
+constexpr int kUpdPre = 8;
+
 __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double *__restrict__ w,
                                                            const double *__restrict__ rj,
                                                            const double *__restrict__ rjm1,
                                                            PhiCtl *ctl0, const double *nrm_in,
                                                            int np_nrm, const double *dot_in,
                                                            int np_dot, double *nrm_out, Batch bt) {
-    __shared__ double lds[64];
+    __shared__ double pro[16 * 4];
+    __shared__ double lds[16];
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
-    PhiCtl *ctl = ctl_member(ctl0, mk);
-    // a new basis (j = 0) starts fresh; later columns stop after a breakdown
-    if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
     w = member_ptr(w, bt.ws, mk);
     rj = member_ptr(rj, bt.ws, mk);
     rjm1 = member_ptr(rjm1, bt.ws, mk);
-    double nn[1], dd[2];
-    sum_partials<1>(nn, nrm_in + (size_t)mk * kPartStride, np_nrm, lds);
-    sum_partials<2>(dd, dot_in + (size_t)mk * kPartStride, np_dot, lds);
+    const int stride = gridDim.x * blockDim.x;
+    const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    double pw[kUpdPre], pr[kUpdPre], pm[kUpdPre];
+#pragma unroll
+    for (int u = 0; u < kUpdPre; ++u) {
+        const int i = i0 + u * stride;
+        const bool in = i < n4;
+        pw[u] = in ? w[i] : 0.0;
+        pr[u] = in ? rj[i] : 0.0;
+        pm[u] = (in && j > 0) ? rjm1[i] : 0.0;
+    }
+    PhiCtl *ctl = ctl_member(ctl0, mk);
+    // a new basis (j = 0) starts fresh; later columns stop after a breakdown
+    if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
+    // prologue: ||R_j||^2, <w, R_j>, <w, R_{j-1}> and max column sum of H
+    double v[3] = {0.0, 0.0, 0.0};
+    const double *nk = nrm_in + (size_t)mk * kPartStride;
+    const double *dk = dot_in + (size_t)mk * kPartStride;
+    for (int b = threadIdx.x; b < np_nrm; b += blockDim.x) v[0] += nk[b];
+    for (int b = threadIdx.x; b < np_dot; b += blockDim.x) {
+        v[1] += dk[2 * b];
+        v[2] += dk[2 * b + 1];
+    }
+    double cm_ = j > 0 ? column_abs_sum(ctl, j) : 0.0;
+    {
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        const int nw = blockDim.x >> 6;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_down(cm_, off, 64);
+            cm_ = o > cm_ ? o : cm_;
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) pro[wid * 4 + k] = v[k];
+            pro[wid * 4 + 3] = cm_;
+        }
+        __syncthreads();
+        double t[3] = {0.0, 0.0, 0.0}, bn = 0.0;
+        for (int q = 0; q < nw; ++q) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t[k] += pro[q * 4 + k];
+            bn = pro[q * 4 + 3] > bn ? pro[q * 4 + 3] : bn;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = t[k];
+        cm_ = bn;
+    }
     const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
-    const ColumnScale cs = finalize_column(ctl, j, nn[0], writer, lds);
+    const ColumnScale cs = finalize_column_bn(ctl, j, v[0], cm_, writer);
     if (cs.stop) return;
     const double sj = cs.sigma;
     const double sm = j > 0 ? ctl->sigma[j - 1] : 0.0;
-    const double hjj = sj * sj * dd[0];
-    const double hmj = j > 0 ? sj * sm * dd[1] : 0.0;
+    const double hjj = sj * sj * v[1];
+    const double hmj = j > 0 ? sj * sm * v[2] : 0.0;
     if (writer) {
         ctl->H[j * kMmax + j] = hjj;
         if (j > 0) ctl->H[(j - 1) * kMmax + j] = hmj;
@@ -120,15 +172,25 @@ __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double
     const double cj = hjj * sj;
     const double cm = hmj * sm;
     double r = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kUpdPre; ++u) {
+        const int i = i0 + u * stride;
+        if (i < n4) {
+            double x = sj * pw[u] - cj * pr[u];
+            if (j > 0) x -= cm * pm[u];
+            w[i] = x;
+            r += x * x;
+        }
+    }
+    for (int i = i0 + kUpdPre * stride; i < n4; i += stride) {
         double x = sj * w[i] - cj * rj[i];
         if (j > 0) x -= cm * rjm1[i];
         w[i] = x;
         r += x * x;
     }
-    double v[1] = {r};
-    block_sum_all<1>(v, lds);
-    put_partials<1>(v, nrm_out + (size_t)mk * kPartStride);
+    double vv[1] = {r};
+    block_sum_all<1>(vv, lds);
+    put_partials<1>(vv, nrm_out + (size_t)mk * kPartStride);
 }
 
 struct CombArgs {

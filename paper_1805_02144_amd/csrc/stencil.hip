@@ -162,11 +162,16 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 template <int EPI, int L, bool FL>
 __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
+    __shared__ double cterm[2 * kCellRedMax];   // per-cell reduction terms
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
     const int n = M.n;
     const double g = M.g, nu = M.nu;
     const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
+    // small grids reduce per-cell terms (fixed order, any block size);
+    // large ones accumulate per lane (block size fixed by n)
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const bool cellred = EPI != kEpiNone && per <= kCellRedMax;
     const int q = threadIdx.x & (L - 1);
     double cax[kPmax];
     const double *axv[kPmax];
@@ -182,7 +187,8 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
     double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
     const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
     double r0 = 0.0, r1 = 0.0;   // this lane's reduction partials
-    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+    const CellRange r_init = block_cells<L>(n);
+    for (CellRange r = r_init; r.i < r.end; r.i += r.step) {
         const int i = r.i;
         const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], uh = u[3 * n + i];
         const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
@@ -270,6 +276,7 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
         o[2] = sc * (-zt * puz - eta * pxz - Gz - nu * d[2]);
         o[3] = sc * (-dv - nu * d[3]);
         const double xs[4] = {xx, xy, xz, xh};
+        double c0 = 0.0, c1 = 0.0;   // this lane's terms of the cell
 #pragma unroll
         for (int b = q; b < 4; b += L) {
             const int oi = b * n + i;
@@ -279,22 +286,52 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
                 if (k < a.naxpy) ob += cax[k] * axv[k][oi];
             outk[oi] = ob;
             if (EPI == kEpiIom2) {
-                r0 += ob * xs[b];
-                if (rjm1) r1 += ob * rjm1[oi];
+                c0 += ob * xs[b];
+                if (rjm1) c1 += ob * rjm1[oi];
             } else if (EPI == kEpiNorm) {
-                r0 += ob * ob;
+                c0 += ob * ob;
+            }
+        }
+        if (EPI != kEpiNone) {
+            if (cellred) {
+                c0 = grp_sum<L>(c0);
+                if (EPI == kEpiIom2) c1 = grp_sum<L>(c1);
+                if (q == 0) {
+                    cterm[2 * (i - r.first)] = c0;
+                    cterm[2 * (i - r.first) + 1] = c1;
+                }
+            } else {
+                r0 += c0;
+                r1 += c1;
             }
         }
     }
-    if (EPI == kEpiIom2) {
-        double v[2] = {r0, r1};
-        block_sum_all<2>(v, lds);
-        put_partials<2>(v, a.dot_out + (size_t)mk * kPartStride);
-    } else if (EPI == kEpiNorm) {
-        double v[1] = {r0};
-        block_sum_all<1>(v, lds);
-        put_partials<1>(v, a.nrm_out + (size_t)mk * kPartStride);
+    if (EPI == kEpiNone) return;
+    double *parts = (EPI == kEpiIom2 ? a.dot_out : a.nrm_out) + (size_t)mk * kPartStride;
+    constexpr int NV = EPI == kEpiIom2 ? 2 : 1;
+    if (cellred) {
+        // cell terms summed by the first wave in cell order
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int cnt = r_init.end - r_init.first;
+            double v[2] = {0.0, 0.0};
+            for (int c = (int)threadIdx.x; c < cnt; c += 64) {
+                v[0] += cterm[2 * c];
+                v[1] += cterm[2 * c + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+            if (threadIdx.x == 0)
+#pragma unroll
+                for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
+        }
+        return;
     }
+    double v[2] = {r0, r1};
+    block_sum_all<2>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
 }
 
 template <int L, bool FL>
@@ -304,7 +341,7 @@ void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hip
                            0, s, M, a, b);
         return;
     }
-    const int grid = red_parts(M.n), block = red_block(M.n);
+    const int grid = red_parts(M.n), block = red_block(M.n, b.nm);
     if (epi == kEpiIom2)
         hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
     else

@@ -19,9 +19,27 @@ inline int cells_grid(int n, int block, int L) {
 }
 
 // Block size of a reducing stencil launch: the partial count is fixed by
-// red_parts(n), so large grids get wider blocks (more waves per CU) rather
+// red_parts(n), so larger grids get wider blocks (more waves per CU) rather
 // than more partials; small ones keep 256 threads and a few iterations.
 inline int red_block(int n) { return n > 65536 ? 1024 : 256; }
+
+// Cells per block of a reducing stencil launch (red_parts(n) blocks): at
+// most kCellRedMax for n <= 65536, where the kernels reduce per-cell terms
+// in a fixed order that does not depend on the block size.
+constexpr int kCellRedMax = 128;
+inline int red_cells(int n) {
+    const int g = red_parts(n);
+    return (n + g - 1) / g;
+}
+
+// Block size of a reducing product launch over nm members: with per-cell
+// reduction the block size is free, so a launch over few cells in all takes
+// 512 threads (about one pass over its chunk, for latency) and a large
+// batch keeps 256 (fewer idle lanes in the last pass, for throughput).
+inline int red_block(int n, int nm) {
+    if (red_cells(n) > kCellRedMax) return red_block(n);
+    return ((long)nm * n <= 200000L && n > 16384) ? 512 : 256;
+}
 
 // Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).
 template <int CTRL>
@@ -78,6 +96,7 @@ __device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al, 
 // block gathers were mostly brought into the same L2 by the blocks beside it.
 struct CellRange {
     int i, end, step;
+    int first;   // first cell of the block's chunk
 };
 template <int L>
 __device__ inline CellRange block_cells(int n) {
@@ -86,7 +105,7 @@ __device__ inline CellRange block_cells(int n) {
     const int per = (n + G - 1) / G;
     const int i0 = chunk * per;
     const int i1 = i0 + per < n ? i0 + per : n;
-    return {i0 + (int)threadIdx.x / L, i1, (int)blockDim.x / L};
+    return {i0 + (int)threadIdx.x / L, i1, (int)blockDim.x / L, i0};
 }
 
 }  // namespace stc

@@ -46,20 +46,24 @@ __global__ void __launch_bounds__(256) k_lapT(DevMesh M, const double *__restric
         const int i = r.i;
         const Cell ci = load_cell(M.cen, i);
         double a[4] = {0.0, 0.0, 0.0, 0.0};
+        double pi[4];
+        load4(psi, i, pi);
 #pragma unroll
         for (int s = q; s < 6; s += L) {
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             const double c = M.cl[e];
             const double raj = M.cen[4 * (size_t)j + 3];
+            double pj[4];
+            load4(psi, j, pj);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) a[b] += c * (psi[b * n + j] * raj - psi[b * n + i] * ci.ra);
+            for (int b = 0; b < 4; ++b) a[b] += c * (pj[b] * raj - pi[b] * ci.ra);
         }
         const double Ai = 1.0 / ci.ra;
 #pragma unroll
         for (int b = 0; b < 4; ++b) a[b] = grp_sum<L>(a[b]);
 #pragma unroll
-        for (int b = q; b < 4; b += L) out[b * n + i] = Ai * a[b];
+        for (int b = q; b < 4; b += L) out[4 * i + b] = Ai * a[b];
     }
 }
 
@@ -93,8 +97,12 @@ __global__ void __launch_bounds__(1024) k_jtv(DevMesh M, JvArgs a, Batch bt) {
     double r0 = 0.0, r1 = 0.0;
     for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
         const int i = r.i;
-        const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], uh = u[3 * n + i];
-        const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
+        double ui[4], xi[4], lxi[4];
+        load4(u, i, ui);
+        load4(x, i, xi);
+        load4(lx, i, lxi);
+        const double ux = ui[0], uy = ui[1], uz = ui[2], uh = ui[3];
+        const double xx = xi[0], xy = xi[1], xz = xi[2], xh = xi[3];
         const Cell ci = load_cell(M.cen, i);
         const double nx = ci.x, ny = ci.y, nz = ci.z, rai = ci.ra;
         // s_i = x_i . (n_i x u_i), P_i x_i
@@ -107,8 +115,12 @@ __global__ void __launch_bounds__(1024) k_jtv(DevMesh M, JvArgs a, Batch bt) {
         for (int s = q; s < 6; s += L) {
             const int e = 6 * i + s;
             const int j = M.nbr[e];
-            const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
-            const double wx = u[j], wy = u[n + j], wz = u[2 * n + j];
+            double xj[4], uj[4], lxj[4];
+            load4(x, j, xj);
+            load4(u, j, uj);
+            load4(lx, j, lxj);
+            const double vx = xj[0], vy = xj[1], vz = xj[2], vh = xj[3];
+            const double wx = uj[0], wy = uj[1], wz = uj[2];
             const Cell cj = load_cell(M.cen, j);
             const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
             const double c = M.cl[e];
@@ -127,7 +139,7 @@ __global__ void __launch_bounds__(1024) k_jtv(DevMesh M, JvArgs a, Batch bt) {
             dry += w.ay * dh;
             drz += w.az * dh;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) d[b] += c * (lx[b * n + j] * raj - lx[b * n + i] * rai);
+            for (int b = 0; b < 4; ++b) d[b] += c * (lxj[b] * raj - lxi[b] * rai);
         }
         vsx = grp_sum<L>(vsx);
         vsy = grp_sum<L>(vsy);
@@ -150,7 +162,7 @@ __global__ void __launch_bounds__(1024) k_jtv(DevMesh M, JvArgs a, Batch bt) {
         const double xs[4] = {xx, xy, xz, xh};
 #pragma unroll
         for (int b = q; b < 4; b += L) {
-            const int oi = b * n + i;
+            const int oi = 4 * i + b;
             double ob = o[b];
 #pragma unroll
             for (int k = 0; k < kPmax; ++k)
@@ -198,8 +210,11 @@ __global__ void __launch_bounds__(256) k_kpairs(DevMesh M, KPairArgs k, Batch bt
             if (cr == 0.0) continue;
             const double *__restrict__ av = member_ptr(k.a0, bt.ws, mk) + (size_t)pr * k.sa;
             const double *__restrict__ bv = member_ptr(k.b0, bt.ws, mk) + (size_t)pr * k.sb;
-            const double ax = av[i], ay = av[n + i], az = av[2 * n + i], ah = av[3 * n + i];
-            const double bx = bv[i], by = bv[n + i], bz = bv[2 * n + i], bh = bv[3 * n + i];
+            double ai_[4], bi_[4];
+            load4(av, i, ai_);
+            load4(bv, i, bi_);
+            const double ax = ai_[0], ay = ai_[1], az = ai_[2], ah = ai_[3];
+            const double bx = bi_[0], by = bi_[1], bz = bi_[2], bh = bi_[3];
             // c_i = a_i . (b_i x n_i), P_i a_i
             const double cc = ax * (by * nz - bz * ny) + ay * (bz * nx - bx * nz) + az * (bx * ny - by * nx);
             const double an = nx * ax + ny * ay + nz * az;
@@ -211,8 +226,11 @@ __global__ void __launch_bounds__(256) k_kpairs(DevMesh M, KPairArgs k, Batch bt
                 const int j = M.nbr[e];
                 const Cell cj = load_cell(M.cen, j);
                 const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
-                const double ajx = av[j], ajy = av[n + j], ajz = av[2 * n + j], ajh = av[3 * n + j];
-                const double bjx = bv[j], bjy = bv[n + j], bjz = bv[2 * n + j];
+                double aj_[4], bj_[4];
+                load4(av, j, aj_);
+                load4(bv, j, bj_);
+                const double ajx = aj_[0], ajy = aj_[1], ajz = aj_[2], ajh = aj_[3];
+                const double bjx = bj_[0], bjy = bj_[1], bjz = bj_[2];
                 const double raj = cj.ra;
                 zb += w.bx * (bx + bjx) + w.by * (by + bjy) + w.bz * (bz + bjz);
                 const double cj_ = ajx * (bjy * cj.z - bjz * cj.y) + ajy * (bjz * cj.x - bjx * cj.z) +
@@ -249,7 +267,7 @@ __global__ void __launch_bounds__(256) k_kpairs(DevMesh M, KPairArgs k, Batch bt
         }
 #pragma unroll
         for (int b = q; b < 4; b += L) {
-            const int oi = b * n + i;
+            const int oi = 4 * i + b;
             out[oi] = k.accumulate ? out[oi] + o[b] : o[b];
         }
     }

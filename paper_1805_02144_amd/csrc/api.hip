@@ -127,9 +127,17 @@ struct xrb_ctx {
     AdjWork adj;
     std::vector<double *> tape_chunks;
     size_t tape_next = 0;
+    // cell-major copies of the caller's vectors at the boundary (allocated on
+    // first use): slot 0 the state, 1..kPmax+1 the inputs v_l, then kIoOut
+    // outputs
+    double *io = nullptr;
 };
 
 namespace {
+
+constexpr int kIoOut = 8;                       // outputs of one phi combination
+constexpr int kIoVecs = 1 + (kPmax + 1) + kIoOut;
+constexpr int kIoOutSlot = 1 + (kPmax + 1);
 
 #define HIPCHK(call)                                                                  \
     do {                                                                              \
@@ -143,6 +151,27 @@ namespace {
 int fail(xrb_ctx *ctx, int code, const char *msg) {
     if (ctx) ctx->err = msg;
     return code;
+}
+
+// The boundary takes component-major vectors [u_x | u_y | u_z | h]; every
+// kernel works on cell-major copies.  io_in / io_out convert one vector into
+// or out of slot k of the context's boundary area.
+int io_ensure(xrb_ctx *ctx) {
+    if (ctx->io) return XRB_OK;
+    if (hipMalloc((void **)&ctx->io, sizeof(double) * kIoVecs * (size_t)ctx->n4) != hipSuccess) {
+        ctx->io = nullptr;
+        return fail(ctx, XRB_ENOMEM, "boundary buffers: out of device memory");
+    }
+    return XRB_OK;
+}
+double *io_vec(const xrb_ctx *ctx, int k) { return ctx->io + (size_t)k * ctx->n4; }
+double *io_in(xrb_ctx *ctx, int k, const double *src) {
+    double *d = io_vec(ctx, k);
+    launch_relayout(ctx->n, 1, src, 0, d, 0, true, ctx->stream);
+    return d;
+}
+void io_out(xrb_ctx *ctx, int k, double *dst) {
+    launch_relayout(ctx->n, 1, io_vec(ctx, k), 0, dst, 0, false, ctx->stream);
 }
 
 hipEvent_t ev_get(xrb_ctx *ctx) {
@@ -1301,6 +1330,7 @@ xrb_status xrb_destroy(xrb_ctx *ctx) {
     rc |= free_work(ctx->ens);
     adj_free(ctx->adj);
     for (double *c : ctx->tape_chunks) (void)hipFree(c);
+    if (ctx->io) (void)hipFree(ctx->io);
     if (ctx->geo_mem && hipFree(ctx->geo_mem) != hipSuccess) rc = XRB_EDEVICE;
     delete ctx;
     return (e != hipSuccess || rc) ? XRB_EDEVICE : XRB_OK;
@@ -1324,7 +1354,9 @@ int64_t xrb_n_cells(const xrb_ctx *ctx) { return ctx ? ctx->n : 0; }
 
 xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f) {
     if (!ctx || !u || !f || u == f) return (xrb_status)fail(ctx, XRB_EINVAL, "rhs: bad pointers");
-    rhs_plain(ctx, ctx->one, u, f);
+    if (int rc = io_ensure(ctx)) return (xrb_status)rc;
+    rhs_plain(ctx, ctx->one, io_in(ctx, 0, u), io_vec(ctx, kIoOutSlot));
+    io_out(ctx, kIoOutSlot, f);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -1332,8 +1364,11 @@ xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f) {
 xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
     if (!ctx || !u || !v || !jv || jv == u || jv == v)
         return (xrb_status)fail(ctx, XRB_EINVAL, "jv: bad pointers");
-    launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
-    jv_plain(ctx, ctx->one, u, v, jv, false);
+    if (int rc = io_ensure(ctx)) return (xrb_status)rc;
+    const double *uc = io_in(ctx, 0, u), *vc = io_in(ctx, 1, v);
+    launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    jv_plain(ctx, ctx->one, uc, vc, io_vec(ctx, kIoOutSlot), false);
+    io_out(ctx, kIoOutSlot, jv);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -1342,9 +1377,12 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out) 
     if (!ctx || !u || !w || !out || out == u || out == w)
         return (xrb_status)fail(ctx, XRB_EINVAL, "jtv: bad pointers");
     int rc = adj_alloc(ctx);
+    if (!rc) rc = io_ensure(ctx);
     if (rc) return (xrb_status)rc;
-    launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
-    jtv_plain(ctx, u, ctx->one.eta, w, out, 0, nullptr, nullptr);
+    const double *uc = io_in(ctx, 0, u), *wc = io_in(ctx, 1, w);
+    launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    jtv_plain(ctx, uc, ctx->one.eta, wc, io_vec(ctx, kIoOutSlot), 0, nullptr, nullptr);
+    io_out(ctx, kIoOutSlot, out);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -1352,14 +1390,16 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out) 
 xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out) {
     if (!ctx || !a || !b || !out || out == a || out == b)
         return (xrb_status)fail(ctx, XRB_EINVAL, "ktv: bad pointers");
+    if (int rc = io_ensure(ctx)) return (xrb_status)rc;
     Batch b1;
     b1.nm = 1;
     KPairArgs kp;
-    kp.a0 = a;
-    kp.b0 = b;
+    kp.a0 = io_in(ctx, 1, a);
+    kp.b0 = io_in(ctx, 2, b);
     kp.R = 1;
-    kp.out = out;
+    kp.out = io_vec(ctx, kIoOutSlot);
     launch_kpairs(ctx->M, kp, b1, ctx->stream);
+    io_out(ctx, kIoOutSlot, out);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -1372,6 +1412,7 @@ xrb_status xrb_step_vjp(xrb_ctx *ctx, xrb_method method, const double *u, double
         return (xrb_status)fail(ctx, XRB_EINVAL, "step_vjp: bad argument");
     if (method != XRB_EXPRB42) return (xrb_status)fail(ctx, XRB_EINVAL, "step_vjp: exprb42 only");
     int rc = adj_alloc(ctx);
+    if (!rc) rc = io_ensure(ctx);
     if (rc) return (xrb_status)rc;
     // the recomputed forward follows `sched` (replay) or, without one, the
     // free controller from a cold start
@@ -1389,11 +1430,13 @@ xrb_status xrb_step_vjp(xrb_ctx *ctx, xrb_method method, const double *u, double
     }
     ctx->sched_pos = 0;
     xrb_phi_stats st2[2] = {};
-    rc = vjp_exprb42(ctx, u, dt, ubar_np1, ubar_n, st2);
+    const double *uc = io_in(ctx, 0, u), *bc = io_in(ctx, 1, ubar_np1);
+    rc = vjp_exprb42(ctx, uc, dt, bc, io_vec(ctx, 2), st2);
     ctx->mode = mode0;
     ctx->sched.swap(sched0);
     ctx->sched_pos = pos0;
     if (rc) return (xrb_status)rc;
+    io_out(ctx, 2, ubar_n);
     if (stats) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
         stats[0] = st2[0];
@@ -1406,19 +1449,45 @@ xrb_status xrb_phi_combo(xrb_ctx *ctx, double dt, const double *u, int p, const 
                          int ns, const double *rho, double *const *w_out, xrb_phi_stats *stats) {
     if (!ctx || !u) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: null");
     if (!(dt == dt) || dt == 0.0) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: dt");
+    if (p < 0 || p > kPmax || ns < 1 || ns > kIoOut || !rho || !w_out || !v)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: bad p, ns or null array");
+    for (int i = 0; i < ns; ++i) {
+        if (!w_out[i]) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: null output");
+        if (w_out[i] == u) return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: output aliases u");
+        for (int l = 0; l <= p; ++l)
+            if (v[l] && v[l] == w_out[i])
+                return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: output aliases input");
+        for (int k = 0; k < i; ++k)
+            if (w_out[k] == w_out[i])
+                return (xrb_status)fail(ctx, XRB_EINVAL, "phi_combo: outputs alias each other");
+    }
     int rc = set_dt(ctx, ctx->one, &dt);
+    if (!rc) rc = io_ensure(ctx);
     if (rc) return (xrb_status)rc;
-    launch_linearize(ctx->M, u, ctx->one.eta, batch_of(ctx->one), ctx->stream);
-    rc = phi_batch(ctx, ctx->one, u, p, v, ns, rho, w_out, -1, stats);
-    if (rc == XRB_OK) HIPCHK(hipGetLastError());
-    return (xrb_status)rc;
+    const double *uc = io_in(ctx, 0, u);
+    const double *vc[kPmax + 1];
+    double *wc[kIoOut];
+    for (int l = 0; l <= p; ++l) vc[l] = v[l] ? io_in(ctx, 1 + l, v[l]) : nullptr;
+    for (int i = 0; i < ns; ++i) wc[i] = io_vec(ctx, kIoOutSlot + i);
+    launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    rc = phi_batch(ctx, ctx->one, uc, p, vc, ns, rho, wc, -1, stats);
+    if (rc) return (xrb_status)rc;
+    for (int i = 0; i < ns; ++i) io_out(ctx, kIoOutSlot + i, w_out[i]);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
 }
 
 xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt) {
     if (!ctx || !u || !(dt > 0.0)) return (xrb_status)fail(ctx, XRB_EINVAL, "step: bad argument");
     int rc = set_dt(ctx, ctx->one, &dt);
+    if (!rc) rc = io_ensure(ctx);
     if (rc) return (xrb_status)rc;
-    return (xrb_status)scheme_step(ctx, ctx->one, (int)method, u);
+    double *uc = io_in(ctx, 0, u);
+    rc = scheme_step(ctx, ctx->one, (int)method, uc);
+    if (rc) return (xrb_status)rc;
+    io_out(ctx, 0, u);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
 }
 
 xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, const double *dt,
@@ -1436,21 +1505,11 @@ xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, co
     if (rc) return (xrb_status)rc;
     // member states into the workspace, one step, and back
     double *ust = stage_vec(ctx, W, S_STATE);
-    const size_t row = sizeof(double) * ctx->n4;
-    if (nm == 1) {
-        HIPCHK(hipMemcpyAsync(ust, U, row, hipMemcpyDeviceToDevice, ctx->stream));
-    } else {
-        HIPCHK(hipMemcpy2DAsync(ust, sizeof(double) * W.ws, U, row, row, nm,
-                                hipMemcpyDeviceToDevice, ctx->stream));
-    }
+    launch_relayout(ctx->n, nm, U, ctx->n4, ust, W.ws, true, ctx->stream);
     rc = scheme_step(ctx, W, (int)method, ust);
     if (rc) return (xrb_status)rc;
-    if (nm == 1) {
-        HIPCHK(hipMemcpyAsync(U, ust, row, hipMemcpyDeviceToDevice, ctx->stream));
-    } else {
-        HIPCHK(hipMemcpy2DAsync(U, row, ust, sizeof(double) * W.ws, row, nm,
-                                hipMemcpyDeviceToDevice, ctx->stream));
-    }
+    launch_relayout(ctx->n, nm, ust, W.ws, U, ctx->n4, false, ctx->stream);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (stats)
         for (int k = 0; k < 3 * nm; ++k) stats[k] = W.stats[k];

@@ -47,18 +47,22 @@ __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restric
     for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
         const int i = r.i;
         double a[4] = {0.0, 0.0, 0.0, 0.0};
+        double pi[4];
+        load4(psi, i, pi);
 #pragma unroll
         for (int s = q; s < 6; s += L) {
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             const double c = M.cl[e];
+            double pj[4];
+            load4(psi, j, pj);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) a[b] += c * (psi[b * n + j] - psi[b * n + i]);
+            for (int b = 0; b < 4; ++b) a[b] += c * (pj[b] - pi[b]);
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) a[b] = grp_sum<L>(a[b]);
 #pragma unroll
-        for (int b = q; b < 4; b += L) out[b * n + i] = a[b];
+        for (int b = q; b < 4; b += L) out[4 * i + b] = a[b];
     }
 }
 
@@ -74,6 +78,8 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
     for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
         const int i = r.i;
         const Cell ci = load_cell(M.cen, i);
+        double ui[4];
+        load4(u, i, ui);
         double z = 0.0;
 #pragma unroll
         for (int s = q; s < 6; s += L) {
@@ -81,8 +87,9 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
             const int j = M.nbr[e];
             const Cell cj = load_cell(M.cen, j);
             const EdgeW w = edge_weights(ci, cj, 0.0, M.beta[e]);
-            z += w.bx * (u[i] + u[j]) + w.by * (u[n + i] + u[n + j]) +
-                 w.bz * (u[2 * n + i] + u[2 * n + j]);
+            double uj[4];
+            load4(u, j, uj);
+            z += w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]);
         }
         z = grp_sum<L>(z);
         if (q == 0) eta[i] = z + M.two_omega * ci.z;
@@ -103,7 +110,10 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
     const int q = threadIdx.x & (L - 1);
     for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
         const int i = r.i;
-        const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], h = u[3 * n + i];
+        double ui[4], lui[4];
+        load4(u, i, ui);
+        load4(lu, i, lui);
+        const double ux = ui[0], uy = ui[1], uz = ui[2], h = ui[3];
         const Cell ci = load_cell(M.cen, i);
         const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * h;
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
@@ -112,7 +122,10 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         for (int s = q; s < 6; s += L) {
             const int e = 6 * i + s;
             const int j = M.nbr[e];
-            const double vx = u[j], vy = u[n + j], vz = u[2 * n + j], hj = u[3 * n + j];
+            double uj[4], luj[4];
+            load4(u, j, uj);
+            load4(lu, j, luj);
+            const double vx = uj[0], vy = uj[1], vz = uj[2], hj = uj[3];
             const Cell cj = load_cell(M.cen, j);
             const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
             const double c = M.cl[e];
@@ -124,7 +137,7 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
             dv += w.ax * (h * ux + hj * vx) + w.ay * (h * uy + hj * vy) + w.az * (h * uz + hj * vz);
             zt += w.bx * (ux + vx) + w.by * (uy + vy) + w.bz * (uz + vz);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) d[b] += c * (lu[b * n + j] - lu[b * n + i]);
+            for (int b = 0; b < 4; ++b) d[b] += c * (luj[b] - lui[b]);
         }
         gx = grp_sum<L>(gx);
         gy0 = grp_sum<L>(gy0);
@@ -145,7 +158,7 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         o[2] = -eta * pz - Gz - nu * d[2];
         o[3] = -dv - nu * d[3];
 #pragma unroll
-        for (int b = q; b < 4; b += L) f[b * n + i] = o[b];
+        for (int b = q; b < 4; b += L) f[4 * i + b] = o[b];
     }
 }
 
@@ -190,8 +203,12 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
     const CellRange r_init = block_cells<L>(n);
     for (CellRange r = r_init; r.i < r.end; r.i += r.step) {
         const int i = r.i;
-        const double ux = u[i], uy = u[n + i], uz = u[2 * n + i], uh = u[3 * n + i];
-        const double xx = x[i], xy = x[n + i], xz = x[2 * n + i], xh = x[3 * n + i];
+        double ui[4], xi[4], lxo[4] = {0.0, 0.0, 0.0, 0.0};
+        load4(u, i, ui);
+        load4(x, i, xi);
+        if (!FL) load4(lx, i, lxo);
+        const double ux = ui[0], uy = ui[1], uz = ui[2], uh = ui[3];
+        const double xx = xi[0], xy = xi[1], xz = xi[2], xh = xi[3];
         const Cell ci = load_cell(M.cen, i);
         const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
         const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
@@ -205,8 +222,11 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
         for (int s = q; s < 6; s += L) {
             const int e = 6 * i + s;
             const int j = M.nbr[e];
-            const double vx = x[j], vy = x[n + j], vz = x[2 * n + j], vh = x[3 * n + j];
-            const double wx = u[j], wy = u[n + j], wz = u[2 * n + j], wh = u[3 * n + j];
+            double xj[4], uj[4];
+            load4(x, j, xj);
+            load4(u, j, uj);
+            const double vx = xj[0], vy = xj[1], vz = xj[2], vh = xj[3];
+            const double wx = uj[0], wy = uj[1], wz = uj[2], wh = uj[3];
             const Cell cj = load_cell(M.cen, j);
             const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
             const double c = M.cl[e];
@@ -229,8 +249,10 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
                     const int ej = 6 * j + tt;
                     const int k = M.nbr[ej];
                     const double cj = M.cl[ej];
+                    double xk[4];
+                    load4(x, k, xk);
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) t[tt][b] = cj * (x[b * n + k] - xs_j[b]);
+                    for (int b = 0; b < 4; ++b) t[tt][b] = cj * (xk[b] - xs_j[b]);
                 }
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
@@ -239,8 +261,10 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
                 }
                 cl_s = c;
             } else {
+                double lxj_[4];
+                load4(lx, j, lxj_);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) d[b] += c * (lx[b * n + j] - lx[b * n + i]);
+                for (int b = 0; b < 4; ++b) d[b] += c * (lxj_[b] - lxo[b]);
             }
         }
         if (FL) {
@@ -279,7 +303,7 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
         double c0 = 0.0, c1 = 0.0;   // this lane's terms of the cell
 #pragma unroll
         for (int b = q; b < 4; b += L) {
-            const int oi = b * n + i;
+            const int oi = 4 * i + b;
             double ob = o[b];
 #pragma unroll
             for (int k = 0; k < kPmax; ++k)

@@ -73,6 +73,18 @@ __device__ inline Cell load_cell(const double *__restrict__ cen, int i) {
     return {a.x, a.y, b.x, b.y};
 }
 
+// State and Krylov vectors are stored cell-major, [cell][4] = (u_x, u_y, u_z,
+// h): component b of cell i sits at 4 i + b, and a gathered neighbour's four
+// components come in two 16-byte loads (vectors start 16-byte aligned).
+__device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]) {
+    const double2 *p = reinterpret_cast<const double2 *>(v) + 2 * (size_t)i;
+    const double2 a = p[0], b = p[1];
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+
 // Flux and circulation weights of the edge i -> j rebuilt from its two
 // scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).
 struct EdgeW {

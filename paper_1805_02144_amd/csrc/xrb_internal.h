@@ -206,6 +206,11 @@ int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStr
 int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
                        const double *const *coef, PhiCtl *ctl0, double *nrm_out,
                        const Batch &b, hipStream_t s);
+// Caller layout [u_x | u_y | u_z | h] (component-major) to the kernels'
+// cell-major [cell][4] (to_cell) or back, for nm members at strides ss / ds
+// (doubles); src and dst must not overlap.
+void launch_relayout(int n, int nm, const double *src, int64_t ss, double *dst, int64_t ds,
+                     bool to_cell, hipStream_t s);
 // out = sum_i c[i] * vec[i] (c[i] times dt_k when bit i of dtmask is set), length n4
 void launch_lincomb(int n4, double *out, int k, const double *const *vec, const double *c,
                     unsigned dtmask, const Batch &b, hipStream_t s);

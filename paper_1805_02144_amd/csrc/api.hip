@@ -1314,6 +1314,8 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     M.cl = dst[2];
     M.cen = cen;
     M.lanes = params->lanes ? params->lanes : stencil_lanes(n);
+    // batches of small grids take two lanes per cell (same bits as eight)
+    M.lanes_batch = (!params->lanes && M.lanes == 8 && n <= 65536) ? 2 : M.lanes;
     M.nu = geo.nu;
     M.two_omega = 2.0 * params->omega;
     M.g = params->gravity;

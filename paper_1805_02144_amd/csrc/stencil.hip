@@ -25,15 +25,23 @@ int stencil_lanes(int n) { return n > 100000 ? 2 : 8; }
 // there).  Both forms give the same bits.
 bool jv_fuses_lap(const DevMesh &M, int nm) { return M.lanes == 8 && (long)nm * M.n <= 200000L; }
 
+// Lanes per cell of a forward stencil launch over nm members: few cells in
+// all take M.lanes (more memory-level parallelism per cell, for latency),
+// many take M.lanes_batch (fewer repeated per-cell instructions, for
+// throughput).  Two and eight lanes give the same bits.
+int launch_lanes(const DevMesh &M, int nm) {
+    return (long)nm * M.n > 200000L ? M.lanes_batch : M.lanes;
+}
+
 namespace {
 
 using namespace stc;
 
 // Every stencil serves a cell with L consecutive lanes (L = 1, 2, 4, 8):
-// lane q takes the neighbour slots q, q + L, ... < 6 and the lanes' edge
-// sums are combined by grp_sum<L>; outputs b = q, q + L, ... < 4 are
-// written by lane q.  Pentagon slot 5 points at the cell itself with zero
-// weights.
+// lane q takes the neighbour slots slot_of<L>(q, k) and writes the output
+// components comp_of<L>(q, k); the lanes' edge sums, accumulated with
+// acc_add, are combined by grp_sum<L>, so two and eight lanes give the same
+// bits.  Pentagon slot 5 points at the cell itself with zero weights.
 
 template <int L>
 __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restrict__ psi,
@@ -50,19 +58,24 @@ __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restric
         double pi[4];
         load4(psi, i, pi);
 #pragma unroll
-        for (int s = q; s < 6; s += L) {
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int s = slot_of<L>(q, k);
+            if (s < 0) continue;
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             const double c = M.cl[e];
             double pj[4];
             load4(psi, j, pj);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) a[b] += c * (pj[b] - pi[b]);
+            for (int b = 0; b < 4; ++b) a[b] = acc_add(a[b], c * (pj[b] - pi[b]));
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) a[b] = grp_sum<L>(a[b]);
 #pragma unroll
-        for (int b = q; b < 4; b += L) out[4 * i + b] = a[b];
+        for (int k = 0; k < kCompIter<L>; ++k) {
+            const int b = comp_of<L>(q, k);
+            if (b >= 0) out[4 * i + b] = a[b];
+        }
     }
 }
 
@@ -82,14 +95,16 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
         load4(u, i, ui);
         double z = 0.0;
 #pragma unroll
-        for (int s = q; s < 6; s += L) {
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int s = slot_of<L>(q, k);
+            if (s < 0) continue;
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             const Cell cj = load_cell(M.cen, j);
             const EdgeW w = edge_weights(ci, cj, 0.0, M.beta[e]);
             double uj[4];
             load4(u, j, uj);
-            z += w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]);
+            z = acc_add(z, w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]));
         }
         z = grp_sum<L>(z);
         if (q == 0) eta[i] = z + M.two_omega * ci.z;
@@ -119,7 +134,13 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
         double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s = q; s < 6; s += L) {
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            // edge terms without contraction: h u_i is loop-invariant, so an
+            // unrolled two-lane loop (one product, three uses) and a one-edge
+            // eight-lane body (one use) would fuse it differently
+#pragma clang fp contract(off)
+            const int s = slot_of<L>(q, k);
+            if (s < 0) continue;
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             double uj[4], luj[4];
@@ -131,13 +152,14 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
             const double c = M.cl[e];
             const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * hj;
             const double dE = Ej - Ei;
-            gx += w.ax * dE;
-            gy0 += w.ay * dE;
-            gz0 += w.az * dE;
-            dv += w.ax * (h * ux + hj * vx) + w.ay * (h * uy + hj * vy) + w.az * (h * uz + hj * vz);
-            zt += w.bx * (ux + vx) + w.by * (uy + vy) + w.bz * (uz + vz);
+            gx = acc_add(gx, w.ax * dE);
+            gy0 = acc_add(gy0, w.ay * dE);
+            gz0 = acc_add(gz0, w.az * dE);
+            dv = acc_add(dv, w.ax * (h * ux + hj * vx) + w.ay * (h * uy + hj * vy) +
+                                 w.az * (h * uz + hj * vz));
+            zt = acc_add(zt, w.bx * (ux + vx) + w.by * (uy + vy) + w.bz * (uz + vz));
 #pragma unroll
-            for (int b = 0; b < 4; ++b) d[b] += c * (luj[b] - lui[b]);
+            for (int b = 0; b < 4; ++b) d[b] = acc_add(d[b], c * (luj[b] - lui[b]));
         }
         gx = grp_sum<L>(gx);
         gy0 = grp_sum<L>(gy0);
@@ -158,7 +180,10 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         o[2] = -eta * pz - Gz - nu * d[2];
         o[3] = -dv - nu * d[3];
 #pragma unroll
-        for (int b = q; b < 4; b += L) f[4 * i + b] = o[b];
+        for (int k = 0; k < kCompIter<L>; ++k) {
+            const int b = comp_of<L>(q, k);
+            if (b >= 0) f[4 * i + b] = o[b];
+        }
     }
 }
 
@@ -168,9 +193,8 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 // from inside the kernel instead of from a preceding k_lap4 pass -- one
 // launch and one vector round trip less per product, for more gathers per
 // lane.  Each lane forms L x at its neighbour j over j's ring with the sum
-// tree the eight-lane group sum of k_lap4 applies, (t0 + t1) + ((t2 + t5) +
-// (t3 + t4)), products rounded on their own; L x at i is the group sum of
-// the lanes' own-edge terms.  The result is therefore bit-identical to the
+// tree k_lap4 applies, ((t0 + t2) + t4) + ((t1 + t3) + t5), products rounded
+// on their own; L x at i is the group sum of the lanes' own-edge terms.  The result is therefore bit-identical to the
 // two-pass form, and the launcher may choose either per call.
 template <int EPI, int L, bool FL>
 __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
@@ -218,8 +242,10 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
         double lxj[4] = {0.0, 0.0, 0.0, 0.0};   // FL: L x at this lane's neighbour
         double cl_s = 0.0;                      // FL: this lane's c (0 without an edge)
         const double xs_i[4] = {xx, xy, xz, xh};
-#pragma unroll(L >= 4 ? 2 : 2)
-        for (int s = q; s < 6; s += L) {
+#pragma unroll
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int s = slot_of<L>(q, k);
+            if (s < 0) continue;
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             double xj[4], uj[4];
@@ -232,12 +258,12 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
             const double c = M.cl[e];
             const double sj = wx * vx + wy * vy + wz * vz + g * vh;
             const double ds = sj - si;
-            gx += w.ax * ds;
-            gy0 += w.ay * ds;
-            gz0 += w.az * ds;
-            dv += w.ax * (fx + (wh * vx + vh * wx)) + w.ay * (fy + (wh * vy + vh * wy)) +
-                  w.az * (fz + (wh * vz + vh * wz));
-            zt += w.bx * (xx + vx) + w.by * (xy + vy) + w.bz * (xz + vz);
+            gx = acc_add(gx, w.ax * ds);
+            gy0 = acc_add(gy0, w.ay * ds);
+            gz0 = acc_add(gz0, w.az * ds);
+            dv = acc_add(dv, w.ax * (fx + (wh * vx + vh * wx)) + w.ay * (fy + (wh * vy + vh * wy)) +
+                                 w.az * (fz + (wh * vz + vh * wz)));
+            zt = acc_add(zt, w.bx * (xx + vx) + w.by * (xy + vy) + w.bz * (xz + vz));
             if (FL) {
                 // no contraction: every product is rounded on its own, as the
                 // single-term lane sums of the two-pass form are
@@ -247,16 +273,16 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
 #pragma unroll
                 for (int tt = 0; tt < 6; ++tt) {
                     const int ej = 6 * j + tt;
-                    const int k = M.nbr[ej];
+                    const int kk = M.nbr[ej];
                     const double cj = M.cl[ej];
                     double xk[4];
-                    load4(x, k, xk);
+                    load4(x, kk, xk);
 #pragma unroll
                     for (int b = 0; b < 4; ++b) t[tt][b] = cj * (xk[b] - xs_j[b]);
                 }
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    lxj[b] = (t[0][b] + t[1][b]) + ((t[2][b] + t[5][b]) + (t[3][b] + t[4][b]));
+                    lxj[b] = ((t[0][b] + t[2][b]) + t[4][b]) + ((t[1][b] + t[3][b]) + t[5][b]);
                     lxi[b] = c * (xs_j[b] - xs_i[b]);
                 }
                 cl_s = c;
@@ -264,7 +290,7 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
                 double lxj_[4];
                 load4(lx, j, lxj_);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) d[b] += c * (lxj_[b] - lxo[b]);
+                for (int b = 0; b < 4; ++b) d[b] = acc_add(d[b], c * (lxj_[b] - lxo[b]));
             }
         }
         if (FL) {
@@ -302,7 +328,9 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
         const double xs[4] = {xx, xy, xz, xh};
         double c0 = 0.0, c1 = 0.0;   // this lane's terms of the cell
 #pragma unroll
-        for (int b = q; b < 4; b += L) {
+        for (int kc = 0; kc < kCompIter<L>; ++kc) {
+            const int b = comp_of<L>(q, kc);
+            if (b < 0) continue;
             const int oi = 4 * i + b;
             double ob = o[b];
 #pragma unroll
@@ -310,10 +338,10 @@ __global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
                 if (k < a.naxpy) ob += cax[k] * axv[k][oi];
             outk[oi] = ob;
             if (EPI == kEpiIom2) {
-                c0 += ob * xs[b];
-                if (rjm1) c1 += ob * rjm1[oi];
+                c0 = acc_add(c0, ob * xs[b]);
+                if (rjm1) c1 = acc_add(c1, ob * rjm1[oi]);
             } else if (EPI == kEpiNorm) {
-                c0 += ob * ob;
+                c0 = acc_add(c0, ob * ob);
             }
         }
         if (EPI != kEpiNone) {
@@ -388,7 +416,7 @@ void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipSt
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
 #define XRB_CALL(L) \
     hipLaunchKernelGGL(k_lap4<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b)
-    XRB_LANES_DISPATCH(XRB_CALL)
+    XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
 }
 
@@ -396,7 +424,7 @@ void launch_linearize(const DevMesh &M, const double *u, double *eta, const Batc
                       hipStream_t s) {
 #define XRB_CALL(L) \
     hipLaunchKernelGGL(k_linearize<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, eta, b)
-    XRB_LANES_DISPATCH(XRB_CALL)
+    XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
 }
 
@@ -404,13 +432,13 @@ void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, 
                 hipStream_t s) {
 #define XRB_CALL(L) \
     hipLaunchKernelGGL(k_rhs<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, lu, f, b)
-    XRB_LANES_DISPATCH(XRB_CALL)
+    XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
 }
 
 int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
 #define XRB_CALL(L) jv_launch<L>(M, a, epi, b, s)
-    XRB_LANES_DISPATCH(XRB_CALL)
+    XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
     return epi == kEpiNone ? 0 : red_parts(M.n);
 }

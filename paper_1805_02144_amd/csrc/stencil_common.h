@@ -53,6 +53,45 @@ __device__ inline double dpp_f64(double v) {
 // 7-i) first; then xor 1 and xor 2 inside each quad.  Every lane ends with
 // the same operands added in the same pairs (only commuted), so the L
 // results are bitwise identical.
+//
+// Lane placement.  Lane q of L serves the edge slots slot_of<L>(q, k) and
+// writes the output components comp_of<L>(q, k), k < kSlotIter<L> /
+// kCompIter<L> (a negative value: none).  For L = 1, 2, 4 these are
+// q, q + L, ...  For L = 8 the six slots sit on lanes 0, 2, 7, 5, 1, 3 and
+// the four components on lanes 0, 2, 7, 5, so that grp_sum<8> adds them in
+// the pairs ((s0 + s2) + s4) + ((s1 + s3) + s5) and (c0 + c2) + (c1 + c3):
+// exactly what two lanes' running sums and one xor-1 exchange give.  With
+// the edge and component sums accumulated without contraction (acc_add),
+// the two- and eight-lane kernels therefore produce the same bits, and a
+// launch may take either.
+template <int L>
+constexpr int kSlotIter = (6 + L - 1) / L;
+template <int L>
+constexpr int kCompIter = (4 + L - 1) / L;
+template <int L>
+__device__ inline int slot_of(int q, int k) {
+    if (L == 8) {
+        const int v = (0x2F3F5140 >> (4 * q)) & 0xF;   // lane -> slot, F = none
+        return v == 0xF ? -1 : v;
+    }
+    const int s = q + L * k;
+    return s < 6 ? s : -1;
+}
+template <int L>
+__device__ inline int comp_of(int q, int k) {
+    if (L == 8) {
+        const int v = (0x2F3FF1F0 >> (4 * q)) & 0xF;   // lane -> component, F = none
+        return v == 0xF ? -1 : v;
+    }
+    const int b = q + L * k;
+    return b < 4 ? b : -1;
+}
+
+// a + t rounded on its own (never fused with the product that formed t)
+__device__ inline double acc_add(double a, double t) {
+#pragma clang fp contract(off)
+    return a + t;
+}
 template <int L>
 __device__ inline double grp_sum(double v) {
     if (L >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
@@ -121,6 +160,14 @@ __device__ inline CellRange block_cells(int n) {
 }
 
 }  // namespace stc
+
+#define XRB_LANES_DISPATCH_N(NL, CALL)      \
+    switch (NL) {                           \
+    case 1: CALL(1); break;                 \
+    case 2: CALL(2); break;                 \
+    case 4: CALL(4); break;                 \
+    default: CALL(8); break;                \
+    }
 
 #define XRB_LANES_DISPATCH(CALL)            \
     switch (M.lanes) {                      \

@@ -32,10 +32,13 @@ struct DevMesh {
     double nu = 0.0, g = 0.0;
     double two_omega = 0.0;                        // Coriolis f_i = two_omega * z_i
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
+    int lanes_batch = 8;                           // lanes of forward launches over many cells
 };
 
 // lanes per cell of the stencil kernels on an n-cell grid
 int stencil_lanes(int n);
+// lanes of a forward stencil launch over nm members (M.lanes or M.lanes_batch)
+int launch_lanes(const DevMesh &M, int nm);
 
 // Decision of one substep attempt, read back by the host.
 struct Decision {

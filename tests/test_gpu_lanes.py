@@ -145,3 +145,32 @@ def test_level7_automatic_lanes(X):
     assert blocks_rel(to_np(ctx.rhs(u)), s.rhs(u), s.n) < TOL
     assert blocks_rel(to_np(ctx.jv(u, v)), s.jv(u, v), s.n) < TOL
     ctx.close()
+
+
+@pytest.mark.parametrize("level", [4, 6])
+def test_two_and_eight_lanes_bitwise(X, level):
+    """Two and eight lanes per cell place the edge slots and output
+    components so that the group sums add the same pairs, and accumulate
+    without contraction: rhs, products and whole free-running steps agree
+    bit for bit (eight lanes on these grids also form L x inside the
+    product, two lanes use the separate Laplacian pass).  This is what lets
+    ensemble batches take two lanes while single states take eight."""
+    import torch
+    mesh = get_mesh(level)
+    n = len(mesh["xyz"])
+    u0 = F.initial_state("c2_l6_24x3600", level=level)
+    v = rand_dir(n, 40 + level)
+    res = {}
+    for lanes in (2, 8):
+        ctx = X.Context(mesh, "cuda:0", lanes=lanes)
+        say("lanes", lanes, "level", level, "bitwise")
+        out = [to_np(ctx.rhs(u0)), to_np(ctx.jv(u0, v))]
+        u = torch.tensor(u0, dtype=torch.float64, device="cuda:0")
+        ctx.reset_history()
+        for _ in range(2):
+            ctx.step("pexprb43", u, 3600.0)
+        out.append(to_np(u))
+        res[lanes] = out
+        ctx.close()
+    for a, b in zip(res[2], res[8]):
+        assert np.array_equal(a, b)

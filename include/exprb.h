@@ -87,9 +87,13 @@ typedef struct {
  *                                controller safety factor (0.8)
  *   max_attempts                 cap on substep attempts per phi_combo call
  *   lanes                        tuning: lanes per cell in the stencil kernels,
- *                                1, 2, 4 or 8, or 0 to choose from the grid size.
- *                                Results depend on it at the rounding level (the
- *                                order of the edge sums), never on the batch size. */
+ *                                1, 2, 4 or 8, or 0 to choose from the grid size
+ *                                (8 up to 100000 cells, else 2; with 0, batched
+ *                                steps on grids up to 65536 cells use 2).  Two
+ *                                and eight lanes give the same bits; 1 and 4
+ *                                differ from them at the rounding level (the
+ *                                order of the edge sums).  Results never depend
+ *                                on the batch size. */
 typedef struct {
     double radius, omega, gravity, gamma_h, dt_e;
     double tol;

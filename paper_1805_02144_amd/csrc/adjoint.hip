@@ -72,8 +72,13 @@ __global__ void __launch_bounds__(256) k_lapT(DevMesh M, const double *__restric
 //   velocity: -V^T(x . (n x u)) + eta (n x x) - (G^T x_vel) u - h D^T x_h
 //             - nu (L^T)^2 x_vel
 //   depth:    -g G^T x_vel - (D^T x_h) . u - nu (L^T)^2 x_h
+// Threads per block at most, as for the forward product: plain 256, norm
+// 512, IOM2 1024 (the smaller bounds leave registers enough to avoid spills).
+template <int EPI>
+constexpr int kJtvMaxBlock = EPI == kEpiNone ? 256 : (EPI == kEpiNorm ? 512 : 1024);
+
 template <int EPI, int L>
-__global__ void __launch_bounds__(1024) k_jtv(DevMesh M, JvArgs a, Batch bt) {
+__global__ void __launch_bounds__(kJtvMaxBlock<EPI>) k_jtv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
@@ -614,10 +619,12 @@ void jtv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipS
         return;
     }
     const int grid = red_parts(M.n), block = red_block(M.n);
-    if (epi == kEpiIom2)
+    if (epi == kEpiIom2) {
         hipLaunchKernelGGL((k_jtv<kEpiIom2, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
-    else
-        hipLaunchKernelGGL((k_jtv<kEpiNorm, L>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+    } else {
+        const int nb = block < kJtvMaxBlock<kEpiNorm> ? block : kJtvMaxBlock<kEpiNorm>;
+        hipLaunchKernelGGL((k_jtv<kEpiNorm, L>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
+    }
 }
 
 template <int L>

@@ -196,8 +196,14 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 // tree k_lap4 applies, ((t0 + t2) + t4) + ((t1 + t3) + t5), products rounded
 // on their own; L x at i is the group sum of the lanes' own-edge terms.  The result is therefore bit-identical to the
 // two-pass form, and the launcher may choose either per call.
+// Threads per block at most: the plain product 256 and the norm variant 512
+// (the register budgets these bounds allow keep them free of spills), the
+// IOM2 variant 1024.
+template <int EPI>
+constexpr int kJvMaxBlock = EPI == kEpiNone ? 256 : (EPI == kEpiNorm ? 512 : 1024);
+
 template <int EPI, int L, bool FL>
-__global__ void __launch_bounds__(1024) k_jv(DevMesh M, JvArgs a, Batch bt) {
+__global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
     __shared__ double cterm[2 * kCellRedMax];   // per-cell reduction terms
     const int mk = blockIdx.y;
@@ -394,10 +400,12 @@ void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hip
         return;
     }
     const int grid = red_parts(M.n), block = red_block(M.n, b.nm);
-    if (epi == kEpiIom2)
+    if (epi == kEpiIom2) {
         hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
-    else
-        hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+    } else {
+        const int nb = block < kJvMaxBlock<kEpiNorm> ? block : kJvMaxBlock<kEpiNorm>;
+        hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
+    }
 }
 
 template <int L>

@@ -9,8 +9,11 @@ with all inputs resident in device memory.
 
 Also reported: the roofline of the fused Jacobian-product/IOM2 kernel
 (algorithmic bytes per launch over its HIP-event-timed average duration),
-a per-kernel time breakdown, and the CPU oracle timed on a bounded sample of
-the same workload.
+a per-kernel time breakdown, the CPU oracle timed on a bounded sample of
+the same workload, and the other workloads' legs: one level-4 exprb42 step
+(latency), the 64-member level-6 ensemble (batched vs per-member loop), the
+level-8 jet (rooflines of the product and the update) and the level-7
+adjoint twin experiment.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -168,6 +171,56 @@ def jet_leg(X, torch, event_every):
                                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                                    "avg_us": 1e6 * avg, "launches": an,
                                    "bytes_per_cell": bpc}
+    return out
+
+
+def c1_leg(X, torch, cpu=True, reps=100):
+    """One exprb42 step of 900 s on the level-4 grid (N = 2562, n = 10248)
+    from the seeded balanced state: a latency-bound single step (vectors of
+    82 KB live in cache).  The state is reset before every step; reported
+    are the median and mean microseconds per step over `reps` steps (HIP
+    events around each step) and the phi-combination rate (two per step),
+    plus the oracle's median over 5 steps."""
+    import numpy as np
+    import oracle as O
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(4)
+    u0h = F.initial_state("c1_exprb42_l4")
+    ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
+    u0 = torch.tensor(u0h, dtype=torch.float64, device="cuda:0")
+    u = torch.empty_like(u0)
+    for _ in range(10):
+        u.copy_(u0)
+        ctx.reset_history()
+        ctx.step("exprb42", u, 900.0)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        u.copy_(u0)
+        ctx.reset_history()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        ctx.step("exprb42", u, 900.0)
+        b.record()
+        b.synchronize()
+        ts.append(1e3 * a.elapsed_time(b))
+    ctx.close()
+    med = float(np.median(ts))
+    out = {"workload": "exprb42, one step of 900 s, level-4 grid (N=2562, n=10248), FP64, "
+                       "tol 1e-10, m_max 40, state reset before each step",
+           "us_per_step_median": med, "us_per_step_mean": float(np.mean(ts)),
+           "phi_evals_per_s": 2.0 / (med * 1e-6), "steps": reps}
+    if cpu:
+        s_ = O.SWE(mesh, gamma_h=4e-4)
+        st = O.swe_stepper(s_, "exprb42")
+        tc = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            st.step(u0h, 900.0)
+            tc.append(time.perf_counter() - t0)
+        out["cpu_oracle_us_per_step_median"] = 1e6 * float(np.median(tc))
     return out
 
 
@@ -409,6 +462,7 @@ def main():
                     agg[k] = agg.get(k, 0) + v
     per_pass = {k: v / args.steps for k, v in agg.items()}
 
+    c1 = c1_leg(X, torch, cpu=not args.no_cpu)
     ens = None if args.no_ensemble else ensemble_leg(X, torch, mesh)
     jet = None if args.no_jet else jet_leg(X, torch, args.event_every)
     adj = None if args.no_adjoint else adjoint_leg(X, torch, cpu=not args.no_cpu)
@@ -438,6 +492,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "krylov_per_step": per_pass,
+        "level4_c1": c1,
         "ensemble": ens,
         "level8_jet": jet,
         "adjoint": adj,

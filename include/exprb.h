@@ -152,6 +152,19 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out);
  * Device vectors of length 4N; out must not alias a or b. */
 xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
 
+/* Conserved quantities of the state u (the three the conservation
+ * paragraph of Sec. 6 monitors), summed over the cells with their areas A:
+ *   out3[0] = mass                sum A h,
+ *   out3[1] = total energy        sum A (h |u|^2 / 2 + g h^2 / 2),
+ *   out3[2] = potential enstrophy sum A (zeta + f)^2 / (2 h),
+ * zeta the Stokes vorticity of the grid and f = 2 Omega z.  (The paper
+ * prints the energy density as g h + |u|^2 / 2; the total energy the
+ * equations conserve without topography is the one above.)  u: device,
+ * [u_x | u_y | u_z | h], h > 0; out3: host, 3 doubles.  Synchronises the
+ * context's stream; the sums are in a fixed order (bitwise reproducible).
+ * XRB_EINVAL on null pointers. */
+xrb_status xrb_diagnostics(xrb_ctx *ctx, const double *u, double *out3);
+
 /* Vector-Jacobian product of one step (method XRB_EXPRB42 only):
  * ubar_n = (d u_{n+1} / d u_n)^T ubar_np1 for u_{n+1} = step(u_n, dt).
  * The step is recomputed on the device, following `sched` (host, sched_len

@@ -94,6 +94,7 @@ def lib():
                                         C.POINTER(PhiStats)]
         L.orc_step_vjp.argtypes = [C.POINTER(Swe), C.c_int, _dp, C.c_double, _dp, _dp,
                                    C.POINTER(PhiOpts), C.POINTER(PhiStats)]
+        L.orc_diagnostics.argtypes = [C.POINTER(Swe), _dp, _dp]
         L.orc_div.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
         L.orc_grad.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
         L.orc_curl.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
@@ -307,6 +308,12 @@ class SWE:
         o = np.empty(self.N)
         lib().orc_ktv(C.byref(self.s), _ptr(a), _ptr(b), _ptr(o))
         return o
+
+    def diagnostics(self, u):
+        """Mass, total energy and potential enstrophy of u (Sec. 6)."""
+        o = np.empty(3)
+        lib().orc_diagnostics(C.byref(self.s), _ptr(_f64(u)), _ptr(o))
+        return {"mass": o[0], "energy": o[1], "enstrophy": o[2]}
 
     def step_vjp(self, method, u, dt, ubar, o=None):
         """(d u_{n+1} / d u_n)^T ubar for one step from u (exprb42); pass

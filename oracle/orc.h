@@ -73,6 +73,14 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out);
 /* K(a, b) = grad_u <a, J(u) b>, independent of u because F is quadratic */
 void orc_ktv(const orc_swe *m, const double *a, const double *b, double *out);
 
+/* Conserved quantities monitored in Sec. 6 (conservation paragraph), summed
+ * over the cells with the cell areas: out[0] = mass sum A h, out[1] = total
+ * energy sum A (h |u|^2 / 2 + g h^2 / 2), out[2] = potential enstrophy
+ * sum A (zeta + f)^2 / (2 h), zeta by the Stokes vorticity.  (The paper
+ * prints the energy density as g h + |u|^2 / 2; the quantity the continuous
+ * equations conserve with h_s = 0 is the one above.) */
+void orc_diagnostics(const orc_swe *m, const double *u, double out[3]);
+
 /* ---------------- small dense linear algebra ---------------- */
 /* X = exp(A), A and X row-major KxK.  Returns the number of squarings. */
 int  orc_expm(int K, const double *A, double *X);

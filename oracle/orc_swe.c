@@ -477,3 +477,23 @@ void orc_swe_problem(orc_swe *m, orc_problem *pb)
     pb->jv = swe_jv_cb;
     pb->ctx = m;
 }
+
+void orc_diagnostics(const orc_swe *m, const double *u, double out[3])
+{
+    int n = m->n;
+    const double *ux = u, *uy = u + n, *uz = u + 2 * n, *h = u + 3 * n;
+    double *zeta = m->work;
+    orc_curl(m, ux, uy, uz, zeta);
+    double mass = 0.0, energy = 0.0, enstrophy = 0.0;
+    for (int i = 0; i < n; i++) {
+        double a = m->area[i];
+        double speed2 = ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i];
+        double absvort = zeta[i] + m->cor[i];
+        mass += a * h[i];
+        energy += a * (h[i] * speed2 / 2.0 + m->gravity * h[i] * h[i] / 2.0);
+        enstrophy += a * absvort * absvort / (2.0 * h[i]);
+    }
+    out[0] = mass;
+    out[1] = energy;
+    out[2] = enstrophy;
+}

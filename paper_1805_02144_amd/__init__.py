@@ -21,6 +21,7 @@ PMAX = 4
 
 EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
            "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
+           "xrb_diagnostics",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
            "xrb_ktv", "xrb_step_vjp"]
@@ -75,6 +76,7 @@ def lib():
         L.xrb_jv.argtypes = [vp, vp, vp, vp]
         L.xrb_jtv.argtypes = [vp, vp, vp, vp]
         L.xrb_ktv.argtypes = [vp, vp, vp, vp]
+        L.xrb_diagnostics.argtypes = [vp, vp, _dp]
         L.xrb_step_vjp.argtypes = [vp, C.c_int, vp, C.c_double, _dp, C.c_int, vp, vp,
                                    C.POINTER(PhiStats)]
         L.xrb_phi_combo.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(vp), C.c_int, _dp,
@@ -205,6 +207,14 @@ class Context:
         out = self.empty()
         self._check(lib().xrb_ktv(self.h, _ptr(a), _ptr(b), _ptr(out)))
         return out
+
+    def diagnostics(self, u):
+        """Mass, total energy and potential enstrophy of u (Sec. 6)."""
+        self._stream()
+        u = self._vec(u)
+        o = np.empty(3)
+        self._check(lib().xrb_diagnostics(self.h, _ptr(u), o.ctypes.data_as(_dp)))
+        return {"mass": float(o[0]), "energy": float(o[1]), "enstrophy": float(o[2])}
 
     def step_vjp(self, method, u, dt, ubar, sched=None, return_stats=False):
         """(d u_{n+1}/d u_n)^T ubar for one step from u; sched: that step's

@@ -1406,6 +1406,19 @@ xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out) 
     return XRB_OK;
 }
 
+xrb_status xrb_diagnostics(xrb_ctx *ctx, const double *u, double *out3) {
+    if (!ctx || !u || !out3) return (xrb_status)fail(ctx, XRB_EINVAL, "diagnostics: null");
+    if (int rc = io_ensure(ctx)) return (xrb_status)rc;
+    Work &W = ctx->one;
+    launch_diag(ctx->M, io_in(ctx, 0, u), W.v_parts, W.vnorm2, ctx->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(W.h_vn, W.vnorm2, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < 3; ++k) out3[k] = W.h_vn[k];
+    return XRB_OK;
+}
+
 xrb_status xrb_step_vjp(xrb_ctx *ctx, xrb_method method, const double *u, double dt,
                         const double *sched, int sched_len, const double *ubar_np1,
                         double *ubar_n, xrb_phi_stats *stats) {

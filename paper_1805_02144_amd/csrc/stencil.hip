@@ -392,6 +392,59 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
         for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
 }
 
+// Conserved quantities monitored in Sec. 6: per block, in its cells'
+// order, the partial sums of A h (mass), A (h |u|^2 / 2 + g h^2 / 2) (total
+// energy) and A (zeta + f)^2 / (2 h) (potential enstrophy); zeta + f is the
+// absolute vorticity k_linearize forms.
+template <int L>
+__global__ void __launch_bounds__(256) k_diag(DevMesh M, const double *__restrict__ u,
+                                              double *__restrict__ parts) {
+    __shared__ double lds[16 * 3];
+    const int n = M.n;
+    const int q = threadIdx.x & (L - 1);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+        const int i = r.i;
+        const Cell ci = load_cell(M.cen, i);
+        double ui[4];
+        load4(u, i, ui);
+        double z = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int s = slot_of<L>(q, k);
+            if (s < 0) continue;
+            const int e = 6 * i + s;
+            const int j = M.nbr[e];
+            const Cell cj = load_cell(M.cen, j);
+            const EdgeW w = edge_weights(ci, cj, 0.0, M.beta[e]);
+            double uj[4];
+            load4(u, j, uj);
+            z = acc_add(z, w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]));
+        }
+        z = grp_sum<L>(z);
+        if (q == 0) {
+            const double A = 1.0 / ci.ra, h = ui[3];
+            const double sp2 = ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2];
+            const double av = z + M.two_omega * ci.z;
+            acc[0] += A * h;
+            acc[1] += A * (0.5 * h * sp2 + 0.5 * M.g * h * h);
+            acc[2] += A * av * av / (2.0 * h);
+        }
+    }
+    block_sum_all<3>(acc, lds);
+    put_partials<3>(acc, parts);
+}
+
+// Totals of k_diag's partials, in block order, into out[0..2].
+__global__ void __launch_bounds__(256) k_diag_sum(const double *__restrict__ parts, int np,
+                                                  double *__restrict__ out) {
+    __shared__ double lds[16 * 3];
+    double t[3];
+    sum_partials<3>(t, parts, np, lds);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 3; ++k) out[k] = t[k];
+}
+
 template <int L, bool FL>
 void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
     if (epi == kEpiNone) {
@@ -442,6 +495,14 @@ void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, 
     hipLaunchKernelGGL(k_rhs<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, lu, f, b)
     XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
+}
+
+void launch_diag(const DevMesh &M, const double *u, double *parts, double *out, hipStream_t s) {
+    const int grid = red_parts(M.n);
+#define XRB_CALL(L) hipLaunchKernelGGL(k_diag<L>, dim3(grid), dim3(256), 0, s, M, u, parts)
+    XRB_LANES_DISPATCH(XRB_CALL)
+#undef XRB_CALL
+    hipLaunchKernelGGL(k_diag_sum, dim3(1), dim3(256), 0, s, parts, grid, out);
 }
 
 int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {

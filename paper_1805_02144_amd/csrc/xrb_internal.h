@@ -209,6 +209,9 @@ int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStr
 int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
                        const double *const *coef, PhiCtl *ctl0, double *nrm_out,
                        const Batch &b, hipStream_t s);
+// Mass, total energy and potential enstrophy of the cell-major state u into
+// out[0..2] (device); parts holds 3 red_parts(n) partials.
+void launch_diag(const DevMesh &M, const double *u, double *parts, double *out, hipStream_t s);
 // Caller layout [u_x | u_y | u_z | h] (component-major) to the kernels'
 // cell-major [cell][4] (to_cell) or back, for nm members at strides ss / ds
 // (doubles); src and dst must not overlap.

@@ -376,6 +376,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-c1", action="store_true", help="skip the level-4 single-step leg")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
     ap.add_argument("--jet-only", action="store_true",
@@ -462,7 +463,7 @@ def main():
                     agg[k] = agg.get(k, 0) + v
     per_pass = {k: v / args.steps for k, v in agg.items()}
 
-    c1 = c1_leg(X, torch, cpu=not args.no_cpu)
+    c1 = None if args.no_c1 else c1_leg(X, torch, cpu=not args.no_cpu)
     ens = None if args.no_ensemble else ensemble_leg(X, torch, mesh)
     jet = None if args.no_jet else jet_leg(X, torch, args.event_every)
     adj = None if args.no_adjoint else adjoint_leg(X, torch, cpu=not args.no_cpu)

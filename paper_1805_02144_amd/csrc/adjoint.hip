@@ -72,10 +72,10 @@ __global__ void __launch_bounds__(256) k_lapT(DevMesh M, const double *__restric
 //   velocity: -V^T(x . (n x u)) + eta (n x x) - (G^T x_vel) u - h D^T x_h
 //             - nu (L^T)^2 x_vel
 //   depth:    -g G^T x_vel - (D^T x_h) . u - nu (L^T)^2 x_h
-// Threads per block at most, as for the forward product: plain 256, norm
-// 512, IOM2 1024 (the smaller bounds leave registers enough to avoid spills).
+// Threads per block at most, as for the forward product: plain and norm 256,
+// IOM2 1024 (the smaller bound leaves registers enough to avoid spills).
 template <int EPI>
-constexpr int kJtvMaxBlock = EPI == kEpiNone ? 256 : (EPI == kEpiNorm ? 512 : 1024);
+constexpr int kJtvMaxBlock = EPI == kEpiIom2 ? 1024 : 256;
 
 template <int EPI, int L>
 __global__ void __launch_bounds__(kJtvMaxBlock<EPI>) k_jtv(DevMesh M, JvArgs a, Batch bt) {

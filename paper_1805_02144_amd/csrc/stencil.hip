@@ -196,11 +196,11 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 // tree k_lap4 applies, ((t0 + t2) + t4) + ((t1 + t3) + t5), products rounded
 // on their own; L x at i is the group sum of the lanes' own-edge terms.  The result is therefore bit-identical to the
 // two-pass form, and the launcher may choose either per call.
-// Threads per block at most: the plain product 256 and the norm variant 512
-// (the register budgets these bounds allow keep them free of spills), the
+// Threads per block at most: the plain product and the norm variant 256
+// (the register budget that bound allows keeps them free of spills), the
 // IOM2 variant 1024.
 template <int EPI>
-constexpr int kJvMaxBlock = EPI == kEpiNone ? 256 : (EPI == kEpiNorm ? 512 : 1024);
+constexpr int kJvMaxBlock = EPI == kEpiIom2 ? 1024 : 256;
 
 template <int EPI, int L, bool FL>
 __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Batch bt) {

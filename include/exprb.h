@@ -130,7 +130,8 @@ int64_t xrb_n_cells(const xrb_ctx *ctx);
 
 /* f = F(u): the semi-discrete shallow-water right-hand side of eq. sweqsinv
  * (vector-invariant momentum with absolute vorticity eq. vort, flux-form
- * continuity, h_s = 0) plus D_f = -nu L^2 on every variable (eq. swdis).
+ * continuity; h_s = 0 unless set by xrb_set_topography) plus D_f = -nu L^2
+ * on every variable (eq. swdis).
  * u, f: device, length 4N, must not alias. */
 xrb_status xrb_rhs(xrb_ctx *ctx, const double *u, double *f);
 
@@ -152,10 +153,19 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out);
  * Device vectors of length 4N; out must not alias a or b. */
 xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
 
+/* Surface topography h_s of the model (the h_s in the energy
+ * E = |u|^2 / 2 + g (h + h_s) of eq. sweqsinv, Sec. 2): hs is a HOST array of
+ * n_cells heights in metres, in the mesh's cell order, copied to the device
+ * (NULL restores the flat default).  Only F(u) depends on it (J does not:
+ * h_s is constant in time).  Synchronises the context's stream first.
+ * XRB_EINVAL for non-finite values, XRB_ENOMEM if the copy cannot be
+ * allocated. */
+xrb_status xrb_set_topography(xrb_ctx *ctx, const double *hs);
+
 /* Conserved quantities of the state u (the three the conservation
  * paragraph of Sec. 6 monitors), summed over the cells with their areas A:
  *   out3[0] = mass                sum A h,
- *   out3[1] = total energy        sum A (h |u|^2 / 2 + g h^2 / 2),
+ *   out3[1] = total energy        sum A (h |u|^2 / 2 + g h^2 / 2 + g h h_s),
  *   out3[2] = potential enstrophy sum A (zeta + f)^2 / (2 h),
  * zeta the Stokes vorticity of the grid and f = 2 Omega z.  (The paper
  * prints the energy density as g h + |u|^2 / 2; the total energy the

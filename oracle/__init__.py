@@ -27,7 +27,7 @@ class Swe(C.Structure):
                 ("gravity", C.c_double), ("gamma_h", C.c_double), ("dt_e", C.c_double),
                 ("nu", C.c_double), ("xyz", _dp), ("deg", _ip), ("nbr", _ip),
                 ("area", _dp), ("len", _dp), ("dist", _dp), ("nrm", _dp), ("tng", _dp),
-                ("cor", _dp), ("work", _dp)]
+                ("cor", _dp), ("work", _dp), ("hs", _dp)]
 
 
 class Attempt(C.Structure):
@@ -95,6 +95,7 @@ def lib():
         L.orc_step_vjp.argtypes = [C.POINTER(Swe), C.c_int, _dp, C.c_double, _dp, _dp,
                                    C.POINTER(PhiOpts), C.POINTER(PhiStats)]
         L.orc_diagnostics.argtypes = [C.POINTER(Swe), _dp, _dp]
+        L.orc_swe_set_topography.argtypes = [C.POINTER(Swe), _dp]
         L.orc_div.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
         L.orc_grad.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
         L.orc_curl.argtypes = [C.POINTER(Swe), _dp, _dp, _dp, _dp]
@@ -308,6 +309,15 @@ class SWE:
         o = np.empty(self.N)
         lib().orc_ktv(C.byref(self.s), _ptr(a), _ptr(b), _ptr(o))
         return o
+
+    def set_topography(self, hs):
+        """Surface topography h_s (n values, metres; None: flat)."""
+        if hs is None:
+            lib().orc_swe_set_topography(C.byref(self.s), None)
+        else:
+            hs = _f64(hs)
+            assert hs.shape == (self.n,)
+            lib().orc_swe_set_topography(C.byref(self.s), _ptr(hs))
 
     def diagnostics(self, u):
         """Mass, total energy and potential enstrophy of u (Sec. 6)."""

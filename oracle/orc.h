@@ -53,12 +53,15 @@ typedef struct {
     double *tng;           /* n*6*3 unit edge tangent t_{e,i} = rhat_e x n_{e,i} */
     double *cor;           /* n Coriolis f_i = 2 Omega sin(lat_i) */
     double *work;          /* scratch, 16*n */
+    double *hs;            /* n surface topography h_s (m); zero unless set */
 } orc_swe;
 
 int  orc_swe_init(orc_swe *m, int n, const double *xyz, const int *deg, const int *nbr,
                   const double *corners, double radius, double omega, double gravity,
                   double gamma_h, double dt_e);
 void orc_swe_free(orc_swe *m);
+/* h_s of the energy E = |u|^2/2 + g (h + h_s) in eq. sweqsinv (NULL: zero) */
+void orc_swe_set_topography(orc_swe *m, const double *hs);
 
 /* discrete operators (single field, length n) */
 void orc_div(const orc_swe *m, const double *fx, const double *fy, const double *fz, double *out);
@@ -75,10 +78,10 @@ void orc_ktv(const orc_swe *m, const double *a, const double *b, double *out);
 
 /* Conserved quantities monitored in Sec. 6 (conservation paragraph), summed
  * over the cells with the cell areas: out[0] = mass sum A h, out[1] = total
- * energy sum A (h |u|^2 / 2 + g h^2 / 2), out[2] = potential enstrophy
- * sum A (zeta + f)^2 / (2 h), zeta by the Stokes vorticity.  (The paper
- * prints the energy density as g h + |u|^2 / 2; the quantity the continuous
- * equations conserve with h_s = 0 is the one above.) */
+ * energy sum A (h |u|^2 / 2 + g h^2 / 2 + g h h_s), out[2] = potential
+ * enstrophy sum A (zeta + f)^2 / (2 h), zeta by the Stokes vorticity.  (The
+ * paper prints the energy density as g h + |u|^2 / 2; the quantity the
+ * continuous equations conserve is the one above.) */
 void orc_diagnostics(const orc_swe *m, const double *u, double out[3]);
 
 /* ---------------- small dense linear algebra ---------------- */

@@ -71,8 +71,9 @@ int orc_swe_init(orc_swe *m, int n, const double *xyz, const int *deg, const int
     m->tng = calloc(18 * (size_t)n, sizeof(double));
     m->cor = malloc(sizeof(double) * n);
     m->work = malloc(sizeof(double) * 16 * (size_t)n);
+    m->hs = calloc((size_t)n, sizeof(double));
     if (!m->xyz || !m->deg || !m->nbr || !m->area || !m->len || !m->dist || !m->nrm ||
-        !m->tng || !m->cor || !m->work)
+        !m->tng || !m->cor || !m->work || !m->hs)
         return ORC_ENOMEM;
     memcpy(m->xyz, xyz, sizeof(double) * 3 * n);
     memcpy(m->deg, deg, sizeof(int) * n);
@@ -113,7 +114,7 @@ int orc_swe_init(orc_swe *m, int n, const double *xyz, const int *deg, const int
 void orc_swe_free(orc_swe *m)
 {
     free(m->xyz); free(m->deg); free(m->nbr); free(m->area); free(m->len); free(m->dist);
-    free(m->nrm); free(m->tng); free(m->cor); free(m->work);
+    free(m->nrm); free(m->tng); free(m->cor); free(m->work); free(m->hs);
     memset(m, 0, sizeof(*m));
 }
 
@@ -258,9 +259,9 @@ void orc_rhs(const orc_swe *m, const double *u, double *f)
            *gz = m->work + 4 * n, *l1 = m->work + 5 * n, *l2 = m->work + 6 * n,
            *hx = m->work + 7 * n, *hy = m->work + 8 * n, *hz = m->work + 9 * n;
     double g = m->gravity;
-    /* total energy  E = |u|^2/2 + g (h + h_s), h_s = 0 */
+    /* total energy  E = |u|^2/2 + g (h + h_s) */
     for (int i = 0; i < n; i++)
-        E[i] = (ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i]) / 2.0 + g * h[i];
+        E[i] = (ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i]) / 2.0 + g * (h[i] + m->hs[i]);
     /* absolute vorticity eta = V.u + f (eq. vort) */
     orc_curl(m, ux, uy, uz, eta);
     for (int i = 0; i < n; i++) eta[i] += m->cor[i];
@@ -490,10 +491,16 @@ void orc_diagnostics(const orc_swe *m, const double *u, double out[3])
         double speed2 = ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i];
         double absvort = zeta[i] + m->cor[i];
         mass += a * h[i];
-        energy += a * (h[i] * speed2 / 2.0 + m->gravity * h[i] * h[i] / 2.0);
+        energy += a * (h[i] * speed2 / 2.0 + m->gravity * h[i] * h[i] / 2.0 +
+                       m->gravity * h[i] * m->hs[i]);
         enstrophy += a * absvort * absvort / (2.0 * h[i]);
     }
     out[0] = mass;
     out[1] = energy;
     out[2] = enstrophy;
+}
+
+void orc_swe_set_topography(orc_swe *m, const double *hs)
+{
+    for (int i = 0; i < m->n; i++) m->hs[i] = hs ? hs[i] : 0.0;
 }

@@ -21,7 +21,7 @@ PMAX = 4
 
 EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
            "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
-           "xrb_diagnostics",
+           "xrb_diagnostics", "xrb_set_topography",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
            "xrb_ktv", "xrb_step_vjp"]
@@ -77,6 +77,7 @@ def lib():
         L.xrb_jtv.argtypes = [vp, vp, vp, vp]
         L.xrb_ktv.argtypes = [vp, vp, vp, vp]
         L.xrb_diagnostics.argtypes = [vp, vp, _dp]
+        L.xrb_set_topography.argtypes = [vp, _dp]
         L.xrb_step_vjp.argtypes = [vp, C.c_int, vp, C.c_double, _dp, C.c_int, vp, vp,
                                    C.POINTER(PhiStats)]
         L.xrb_phi_combo.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(vp), C.c_int, _dp,
@@ -207,6 +208,16 @@ class Context:
         out = self.empty()
         self._check(lib().xrb_ktv(self.h, _ptr(a), _ptr(b), _ptr(out)))
         return out
+
+    def set_topography(self, hs):
+        """Surface topography h_s (n values in metres, host; None: flat)."""
+        if hs is None:
+            self._check(lib().xrb_set_topography(self.h, None))
+            return
+        self._hs = np.ascontiguousarray(hs, dtype=np.float64)
+        if self._hs.shape != (self.n,):
+            raise ValueError("h_s of length %d expected" % self.n)
+        self._check(lib().xrb_set_topography(self.h, self._hs.ctypes.data_as(_dp)))
 
     def diagnostics(self, u):
         """Mass, total energy and potential enstrophy of u (Sec. 6)."""

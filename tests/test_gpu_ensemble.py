@@ -110,3 +110,34 @@ def test_c4_level6_members_bitwise(X):
     assert blocks_rel(got[0] - U[0], ref - U[0], s.n) < TOL
     assert len(st) == nm and all(c[0]["accepted"] >= 1 for c in st)
     ctx.close()
+
+
+def test_c4_six_launches(X):
+    """C4 parity run: all 64 level-6 members through 6 batched launches
+    (one exprb42 step each, step sizes from {600, 1200, 2400, 3600} s);
+    the first and last members equal 6 single-state steps bit for bit, and
+    the first member matches the oracle's free-running 6 steps at 1e-11 on
+    the increment per block."""
+    import torch
+    level, nm = 6, 64
+    mesh, U, dts = members(level, nm)
+    say("C4 six launches, 64 members")
+    ctx = X.Context(mesh, "cuda:0")
+    Ub = torch.tensor(U, device="cuda:0")
+    ctx.reset_history()
+    for _ in range(6):
+        ctx.step_batch("exprb42", Ub, dts)
+    got = Ub.cpu().numpy()
+    for k in (0, nm - 1):
+        ctx.reset_history()
+        u = torch.tensor(U[k], device="cuda:0")
+        for _ in range(6):
+            ctx.step("exprb42", u, dts[k])
+        assert np.array_equal(u.cpu().numpy(), got[k]), k
+    ctx.close()
+    s = O.SWE(mesh)
+    st = O.swe_stepper(s, "exprb42")
+    ref = U[0].copy()
+    for _ in range(6):
+        ref = st.step(ref, dts[0])
+    assert blocks_rel(got[0] - U[0], ref - U[0], s.n) < TOL

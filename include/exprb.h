@@ -45,13 +45,18 @@ typedef enum {
 /* The schemes of Sec. 3.3 plus the comparison and starting methods:
  * exprb42 (eq. 3.11), pexprb43 (eq. 3.12), exprb53 (eq. 3.13),
  * epi3 (eq. epi3, started by one EPI2 step), EPI2 = exponential
- * Rosenbrock-Euler (eq. 3.5). */
+ * Rosenbrock-Euler (eq. 3.5), and EXPRB42M = exprb42 with its two
+ * phi_1(.) v evaluations in one call: (i) rho = [3/4, 1], v_1 = v gives U2 and
+ * phi_1(A) v; (ii) rho = [1] with only v_3 = 32/9 dt D2 (Sec. 4.4's mapping
+ * of eq. 3.11 with the first two outputs shared).  The same method as
+ * exprb42 in exact arithmetic; results differ at the Krylov tolerance. */
 typedef enum {
     XRB_EXPRB42 = 0,
     XRB_PEXPRB43 = 1,
     XRB_EXPRB53 = 2,
     XRB_EPI3 = 3,
-    XRB_EPI2 = 4
+    XRB_EPI2 = 4,
+    XRB_EXPRB42M = 5
 } xrb_method;
 
 /* Substep schedule handling of phi_combo: FREE = the device controller

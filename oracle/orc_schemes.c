@@ -19,6 +19,11 @@
  *                        R_{n-1} = F(u_{n-1}) - F(u_n) - J_n (u_{n-1} - u_n);
  *                        first step EPI2 (eq. 3.5): rho = [1], v_1 = v.
  *   EPI2     (eq. 3.5):  rho = [1], v_1 = v.
+ *   exprb42m (eq. 3.11 with the two phi_1 evaluations in one call, the
+ *             variant Sec. 4.4's mapping leaves open; the phi-combination is
+ *             linear in v_1..v_p, so call (ii) keeps only its v_3 part):
+ *                        (i)  rho = [3/4, 1], v_1 = v  -> U2 = u_n + W_1, W_2 = phi_1(A) v
+ *                        (ii) rho = [1], v_3 = 32/9 dt D2 -> u_{n+1} = u_n + W_2 + W
  *
  * D_i = N_n(U_i) - N_n(u_n) = F(U_i) - F(u_n) - J_n (U_i - u_n) (eq. Dni).
  * The rescaling factors of exprb53's U3 convert the rho^l-weighted outputs
@@ -97,6 +102,20 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         rc = orc_phi_combo(n, jmv, &jc, 3, vii, 1, rho2, wo2, o, &s->m_warm[1], &s->calls[1]);
         if (rc) goto out;
         for (int i = 0; i < n; i++) u[i] = u[i] + W2[i];
+    } else if (method == ORC_EXPRB42M) {
+        double rho1[2] = {0.75, 1.0}, rho2[1] = {1.0};
+        const double *vi[2] = {NULL, v};
+        double *wo[2] = {W1, X1};
+        rc = orc_phi_combo(n, jmv, &jc, 1, vi, 2, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
+        if (rc) goto out;
+        for (int i = 0; i < n; i++) U2[i] = u[i] + W1[i];
+        nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
+        for (int i = 0; i < n; i++) a3[i] = 32.0 / 9.0 * dt * D2[i];
+        const double *vii[4] = {NULL, NULL, NULL, a3};
+        double *wo2[1] = {W2};
+        rc = orc_phi_combo(n, jmv, &jc, 3, vii, 1, rho2, wo2, o, &s->m_warm[1], &s->calls[1]);
+        if (rc) goto out;
+        for (int i = 0; i < n; i++) u[i] = u[i] + X1[i] + W2[i];
     } else if (method == ORC_PEXPRB43) {
         double rho1[2] = {0.5, 1.0}, rho2[1] = {1.0};
         const double *vi[2] = {NULL, v};

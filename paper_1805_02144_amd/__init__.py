@@ -15,7 +15,7 @@ LIBPATH = os.path.join(_HERE, "libexprb.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, ENAN, ESTATE, ESCHED = 0, -1, -2, -3, -4, -5, -6, -7
 FREE, RECORD, REPLAY = 0, 1, 2
-METHODS = {"exprb42": 0, "pexprb43": 1, "exprb53": 2, "epi3": 3, "epi2": 4}
+METHODS = {"exprb42": 0, "pexprb43": 1, "exprb53": 2, "epi3": 3, "epi2": 4, "exprb42m": 5}
 MMAX_LIMIT = 44
 PMAX = 4
 

@@ -772,6 +772,23 @@ int scheme_step(xrb_ctx *ctx, Work &W, int method, double *u) {
         if (rc) return rc;
         site_stats(1);
         lincomb(ctx, W, u, {u, W2}, {1.0, 1.0});
+    } else if (method == XRB_EXPRB42M) {
+        // exprb42 with phi_1(3/4 A) v and phi_1(A) v from one call
+        const double r1[2] = {0.75, 1.0}, r2[1] = {1.0};
+        const double *vi[2] = {nullptr, v};
+        double *o1[2] = {W1, X1};
+        rc = phi_batch(ctx, W, u, 1, vi, 2, r1, o1, 0, tmp.data());
+        if (rc) return rc;
+        site_stats(0);
+        lincomb(ctx, W, U2, {u, W1}, {1.0, 1.0});
+        nonlin(U2, D2);
+        lincomb(ctx, W, a3, {D2}, {32.0 / 9.0}, 1u);
+        const double *vii[4] = {nullptr, nullptr, nullptr, a3};
+        double *o2[1] = {W2};
+        rc = phi_batch(ctx, W, u, 3, vii, 1, r2, o2, 1, tmp.data());
+        if (rc) return rc;
+        site_stats(1);
+        lincomb(ctx, W, u, {u, X1, W2}, {1.0, 1.0, 1.0});
     } else if (method == XRB_PEXPRB43) {
         const double r1[2] = {0.5, 1.0}, r2[1] = {1.0};
         const double *vi[2] = {nullptr, v};

@@ -195,7 +195,7 @@ def test_phi_combo_errors(X):
     assert blocks_rel(to_np(W[0]), ref[0], n) < TOL
 
 
-METHODS = ["exprb42", "pexprb43", "exprb53", "epi3", "epi2"]
+METHODS = ["exprb42", "pexprb43", "exprb53", "epi3", "epi2", "exprb42m"]
 
 
 def run_steps(X, ctx, s, method, u0, dt, nsteps, replay):

@@ -121,7 +121,7 @@ def _ode():
     return n, f, jac, u0
 
 
-NOMINAL = {"epi2": 2, "epi3": 3, "exprb42": 4, "pexprb43": 4, "exprb53": 5}
+NOMINAL = {"epi2": 2, "epi3": 3, "exprb42": 4, "pexprb43": 4, "exprb53": 5, "exprb42m": 4}
 
 
 @pytest.mark.parametrize("method", list(NOMINAL))
@@ -210,3 +210,19 @@ def test_mass_conservation(method):
     for _ in range(3):
         u = st.step(u, 3600.0)
         assert abs(a @ u[3 * n:] - mass0) <= 1e-13 * mass0
+
+
+def test_merged_exprb42_equals_exprb42_to_the_tolerance():
+    """exprb42m shares phi_1(3/4 A) v and phi_1(A) v in one call; in exact
+    arithmetic it is exprb42, so with a tight Krylov tolerance the two steps
+    agree far below the scheme's own error."""
+    m = get_mesh(3)
+    s = O.SWE(m)
+    n = s.n
+    u0 = F.initial_state("c2_l6_24x3600", level=3)
+    a = O.swe_stepper(s, "exprb42").step(u0, 3600.0, O.opts(tol=1e-13))
+    b = O.swe_stepper(s, "exprb42m").step(u0, 3600.0, O.opts(tol=1e-13))
+    for k in range(4):
+        sl = slice(k * n, (k + 1) * n)
+        d = a[sl] - u0[sl]
+        assert np.linalg.norm(b[sl] - a[sl]) <= 1e-10 * np.linalg.norm(d)

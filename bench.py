@@ -98,6 +98,7 @@ def ensemble_leg(X, torch, mesh, reps=3):
     from synth import fields as F
     U0, dts = F.ensemble_states(6, F.config_seed(3), 64)
     ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
+    tune = ctx.autotune(64)                      # launch shapes for this grid and batch
     Ub0 = torch.tensor(U0, dtype=torch.float64, device="cuda:0")
     Ub = Ub0.clone()
     ctx.reset_history()
@@ -132,6 +133,8 @@ def ensemble_leg(X, torch, mesh, reps=3):
             "batched_member_steps_per_s": 64 / tb, "loop_member_steps_per_s": 64 / tl,
             "speedup": tl / tb, "batched_ms": 1e3 * tb, "loop_ms": 1e3 * tl,
             "last_member_bitwise_equal": same,
+            "autotune": {"lanes": tune["lanes"], "lanes_batch": tune["lanes_batch"],
+                         "single_us": tune["single_us"], "batch_us": tune["batch_us"]},
             "dt_mix": {str(int(d)): int((dts == d).sum()) for d in sorted(set(dts))}}
 
 

@@ -158,6 +158,27 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out);
  * Device vectors of length 4N; out must not alias a or b. */
 xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
 
+/* Lanes-per-cell autotuner: the launch shape of the stencil kernels chosen
+ * by measurement on this context's grid.  For each lane count 1, 2, 4, 8 it
+ * times one IOM2 column's product (the Laplacian pass where that is
+ * separate, then the product with its dot epilogue; 3 warm-up and 20 timed
+ * launches on zero data, HIP events) for a single state and for a batch of
+ * nm_batch members (1..256), and sets the context's lanes for single-state
+ * launches and for launches over many cells to the pair that minimises the
+ * sum of the two times relative to each one's best, among the pairs that
+ * keep batched members bitwise equal to single runs (the same count, or two
+ * and eight on grids up to 65536 cells).  Overrides xrb_params.lanes.
+ * Synchronises the stream; allocates 6 nm_batch vectors for its duration.
+ * out (host): the timings in microseconds per launch and the choice. */
+typedef struct {
+    double single_us[4];   /* lanes 1, 2, 4, 8: one state */
+    double batch_us[4];    /* lanes 1, 2, 4, 8: nm_batch members in one launch */
+    int32_t lanes;         /* chosen for single-state launches */
+    int32_t lanes_batch;   /* chosen for launches over more than 200000 cells in all */
+    int32_t nm_batch;
+} xrb_tune_result;
+xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out);
+
 /* Surface topography h_s of the model (the h_s in the energy
  * E = |u|^2 / 2 + g (h + h_s) of eq. sweqsinv, Sec. 2): hs is a HOST array of
  * n_cells heights in metres, in the mesh's cell order, copied to the device

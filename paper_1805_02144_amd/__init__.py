@@ -21,7 +21,7 @@ PMAX = 4
 
 EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", "xrb_sync",
            "xrb_last_error", "xrb_n_cells", "xrb_rhs", "xrb_jv", "xrb_phi_combo", "xrb_step",
-           "xrb_diagnostics", "xrb_set_topography",
+           "xrb_diagnostics", "xrb_set_topography", "xrb_autotune",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
            "xrb_ktv", "xrb_step_vjp"]
@@ -41,6 +41,11 @@ class Params(C.Structure):
                 ("gamma_h", C.c_double), ("dt_e", C.c_double), ("tol", C.c_double),
                 ("m_init", C.c_int32), ("m_max", C.c_int32), ("delta", C.c_double),
                 ("gamma", C.c_double), ("max_attempts", C.c_int32), ("lanes", C.c_int32)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("single_us", C.c_double * 4), ("batch_us", C.c_double * 4),
+                ("lanes", C.c_int32), ("lanes_batch", C.c_int32), ("nm_batch", C.c_int32)]
 
 
 class PhiStats(C.Structure):
@@ -78,6 +83,7 @@ def lib():
         L.xrb_ktv.argtypes = [vp, vp, vp, vp]
         L.xrb_diagnostics.argtypes = [vp, vp, _dp]
         L.xrb_set_topography.argtypes = [vp, _dp]
+        L.xrb_autotune.argtypes = [vp, C.c_int, C.POINTER(TuneResult)]
         L.xrb_step_vjp.argtypes = [vp, C.c_int, vp, C.c_double, _dp, C.c_int, vp, vp,
                                    C.POINTER(PhiStats)]
         L.xrb_phi_combo.argtypes = [vp, C.c_double, vp, C.c_int, C.POINTER(vp), C.c_int, _dp,
@@ -208,6 +214,16 @@ class Context:
         out = self.empty()
         self._check(lib().xrb_ktv(self.h, _ptr(a), _ptr(b), _ptr(out)))
         return out
+
+    def autotune(self, nm_batch=16):
+        """Time the stencil launch shapes on this grid and keep the fastest
+        bitwise-consistent lanes pair (see xrb_autotune)."""
+        self._stream()
+        r = TuneResult()
+        self._check(lib().xrb_autotune(self.h, int(nm_batch), C.byref(r)))
+        return {"single_us": dict(zip((1, 2, 4, 8), r.single_us)),
+                "batch_us": dict(zip((1, 2, 4, 8), r.batch_us)),
+                "lanes": r.lanes, "lanes_batch": r.lanes_batch, "nm_batch": r.nm_batch}
 
     def set_topography(self, hs):
         """Surface topography h_s (n values in metres, host; None: flat)."""

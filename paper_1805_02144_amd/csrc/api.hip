@@ -1425,6 +1425,95 @@ xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out) 
     return XRB_OK;
 }
 
+xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
+    if (!ctx || !out || nm_batch < 1 || nm_batch > 256)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "autotune: bad argument");
+    const hipStream_t s = ctx->stream;
+    HIPCHK(hipStreamSynchronize(s));
+    const size_t n4 = (size_t)ctx->n4;
+    // per member: u, x, L x, out, R_{j-1}, eta; then the dot partials.  The
+    // data are zeros: the kernels' timing does not depend on the values.
+    const size_t ws = 6 * n4;
+    const size_t total = ws * nm_batch + (size_t)kPartStride * nm_batch;
+    double *buf = nullptr;
+    if (hipMalloc((void **)&buf, sizeof(double) * total) != hipSuccess)
+        return (xrb_status)fail(ctx, XRB_ENOMEM, "autotune: out of device memory");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = XRB_OK;
+    if (hipMemsetAsync(buf, 0, sizeof(double) * total, s) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(ctx, XRB_EDEVICE, "autotune: device setup failed");
+    JvArgs a;
+    a.u = buf;
+    a.x = buf + n4;
+    a.lx = buf + 2 * n4;
+    a.out = buf + 3 * n4;
+    a.rjm1 = buf + 4 * n4;
+    a.eta = buf + 5 * n4;
+    a.dot_out = buf + ws * nm_batch;
+    a.dt = 1.0;
+    const DevMesh saved = ctx->M;
+    const int cand[4] = {1, 2, 4, 8};
+    constexpr int kWarm = 3, kReps = 20;
+    // one IOM2 column's product: the Laplacian pass (where separate) and the
+    // product with its dot epilogue
+    auto time_launch = [&](int nm) -> double {
+        Batch b;
+        b.nm = nm;
+        b.ws = nm > 1 ? (int64_t)ws : 0;
+        auto once = [&] {
+            if (!jv_fuses_lap(ctx->M, nm)) launch_lap4(ctx->M, a.x, (double *)a.lx, b, s);
+            launch_jv(ctx->M, a, kEpiIom2, b, s);
+        };
+        for (int w = 0; w < kWarm; ++w) once();
+        float ms = 0.0f;
+        if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+        for (int r = 0; r < kReps; ++r) once();
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return -1.0;
+        return 1e3 * ms / kReps;
+    };
+    for (int c = 0; c < 4 && rc == XRB_OK; ++c) {
+        ctx->M.lanes = ctx->M.lanes_batch = cand[c];
+        out->single_us[c] = time_launch(1);
+        out->batch_us[c] = time_launch(nm_batch);
+        if (out->single_us[c] < 0.0 || out->batch_us[c] < 0.0 || hipGetLastError() != hipSuccess)
+            rc = fail(ctx, XRB_EDEVICE, "autotune: timing failed");
+    }
+    ctx->M = saved;
+    if (rc == XRB_OK) {
+        // fastest pair (relative to each mode's best) that keeps batched
+        // members bitwise equal to single runs
+        double bs = 1e300, bb = 1e300;
+        for (int c = 0; c < 4; ++c) {
+            bs = out->single_us[c] < bs ? out->single_us[c] : bs;
+            bb = out->batch_us[c] < bb ? out->batch_us[c] : bb;
+        }
+        double best = 1e300;
+        int la = saved.lanes, lb = saved.lanes_batch;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                if (!lanes_pair_bitwise(saved, cand[i], cand[j])) continue;
+                const double cost = out->single_us[i] / bs + out->batch_us[j] / bb;
+                if (cost < best) {
+                    best = cost;
+                    la = cand[i];
+                    lb = cand[j];
+                }
+            }
+        ctx->M.lanes = la;
+        ctx->M.lanes_batch = lb;
+        out->lanes = la;
+        out->lanes_batch = lb;
+        out->nm_batch = nm_batch;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    return (xrb_status)rc;
+}
+
 xrb_status xrb_set_topography(xrb_ctx *ctx, const double *hs) {
     if (!ctx) return XRB_EINVAL;
     HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -33,6 +33,15 @@ int launch_lanes(const DevMesh &M, int nm) {
     return (long)nm * M.n > 200000L ? M.lanes_batch : M.lanes;
 }
 
+// Whether single-state launches with a lanes and batched ones with b give
+// the same bits: the same count, or two and eight on grids whose reducing
+// products reduce per-cell terms in fixed order.
+bool lanes_pair_bitwise(const DevMesh &M, int a, int b) {
+    if (a == b) return true;
+    const bool two_eight = (a == 2 || a == 8) && (b == 2 || b == 8);
+    return two_eight && stc::red_cells(M.n) <= stc::kCellRedMax;
+}
+
 namespace {
 
 using namespace stc;

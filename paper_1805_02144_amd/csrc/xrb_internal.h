@@ -40,6 +40,8 @@ struct DevMesh {
 int stencil_lanes(int n);
 // lanes of a forward stencil launch over nm members (M.lanes or M.lanes_batch)
 int launch_lanes(const DevMesh &M, int nm);
+// whether lanes a (single states) and b (batches) give the same bits
+bool lanes_pair_bitwise(const DevMesh &M, int a, int b);
 
 // Decision of one substep attempt, read back by the host.
 struct Decision {

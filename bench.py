@@ -380,6 +380,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-c1", action="store_true", help="skip the level-4 single-step leg")
+    ap.add_argument("--lanes", type=int, default=-1,
+                    help="lanes per cell for the level-6 workload (default: autotune)")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
     ap.add_argument("--jet-only", action="store_true",
@@ -418,7 +420,12 @@ def main():
     mesh = get_mesh(level)
     n = len(mesh["xyz"])
     u0_host = F.initial_state("c2_l6_24x3600")
-    ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
+    if args.lanes >= 0:
+        ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40, lanes=args.lanes)
+        tune = None
+    else:
+        ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
+        tune = ctx.autotune(1)
     u0 = torch.tensor(u0_host, dtype=torch.float64, device="cuda:0")
     u = torch.empty_like(u0)
 
@@ -498,6 +505,9 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "krylov_per_step": per_pass,
+        "lanes": {"lanes": ctx.params.lanes if tune is None else tune["lanes"],
+                  "autotuned": tune is not None,
+                  "single_us": None if tune is None else tune["single_us"]},
         "level4_c1": c1,
         "ensemble": ens,
         "level8_jet": jet,

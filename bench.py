@@ -380,8 +380,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-c1", action="store_true", help="skip the level-4 single-step leg")
-    ap.add_argument("--lanes", type=int, default=-1,
-                    help="lanes per cell for the level-6 workload (default: autotune)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes per cell for the level-6 workload (0: the library's choice)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the level-6 context's lanes before measuring")
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-jet", action="store_true")
     ap.add_argument("--jet-only", action="store_true",
@@ -420,12 +422,8 @@ def main():
     mesh = get_mesh(level)
     n = len(mesh["xyz"])
     u0_host = F.initial_state("c2_l6_24x3600")
-    if args.lanes >= 0:
-        ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40, lanes=args.lanes)
-        tune = None
-    else:
-        ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
-        tune = ctx.autotune(1)
+    ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40, lanes=args.lanes)
+    tune = ctx.autotune(1) if args.autotune else None
     u0 = torch.tensor(u0_host, dtype=torch.float64, device="cuda:0")
     u = torch.empty_like(u0)
 
@@ -505,9 +503,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "krylov_per_step": per_pass,
-        "lanes": {"lanes": ctx.params.lanes if tune is None else tune["lanes"],
-                  "autotuned": tune is not None,
-                  "single_us": None if tune is None else tune["single_us"]},
+        "lanes": {"requested": args.lanes, "autotuned": tune},
         "level4_c1": c1,
         "ensemble": ens,
         "level8_jet": jet,

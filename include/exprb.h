@@ -93,7 +93,7 @@ typedef struct {
  *   max_attempts                 cap on substep attempts per phi_combo call
  *   lanes                        tuning: lanes per cell in the stencil kernels,
  *                                1, 2, 4 or 8, or 0 to choose from the grid size
- *                                (8 up to 100000 cells, else 2; with 0, batched
+ *                                (8 up to 16384 cells, else 2; with 0, batched
  *                                steps on grids up to 65536 cells use 2).  Two
  *                                and eight lanes give the same bits; 1 and 4
  *                                differ from them at the rounding level (the
@@ -162,12 +162,14 @@ xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
  * by measurement on this context's grid.  For each lane count 1, 2, 4, 8 it
  * times one IOM2 column's product (the Laplacian pass where that is
  * separate, then the product with its dot epilogue; 3 warm-up and 20 timed
- * launches on zero data, HIP events) for a single state and for a batch of
- * nm_batch members (1..256), and sets the context's lanes for single-state
- * launches and for launches over many cells to the pair that minimises the
- * sum of the two times relative to each one's best, among the pairs that
- * keep batched members bitwise equal to single runs (the same count, or two
- * and eight on grids up to 65536 cells).  Overrides xrb_params.lanes.
+ * launches on zero data, the fastest of 3 trials, HIP events) for a single
+ * state and for a batch of nm_batch members (1..256), and sets the context's
+ * lanes for single-state launches and for launches over many cells to the
+ * pair that minimises the sum of the two times relative to each one's best,
+ * among the pairs that keep batched members bitwise equal to single runs
+ * (the same count, or two and eight on grids up to 65536 cells); the current
+ * pair is kept unless that one is more than 3 % better.  Overrides
+ * xrb_params.lanes.
  * Synchronises the stream; allocates 6 nm_batch vectors for its duration.
  * out (host): the timings in microseconds per launch and the choice. */
 typedef struct {

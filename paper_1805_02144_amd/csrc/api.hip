@@ -1454,7 +1454,7 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
     a.dt = 1.0;
     const DevMesh saved = ctx->M;
     const int cand[4] = {1, 2, 4, 8};
-    constexpr int kWarm = 3, kReps = 20;
+    constexpr int kWarm = 3, kReps = 20, kTrials = 3;
     // one IOM2 column's product: the Laplacian pass (where separate) and the
     // product with its dot epilogue
     auto time_launch = [&](int nm) -> double {
@@ -1466,13 +1466,18 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
             launch_jv(ctx->M, a, kEpiIom2, b, s);
         };
         for (int w = 0; w < kWarm; ++w) once();
-        float ms = 0.0f;
-        if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
-        for (int r = 0; r < kReps; ++r) once();
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-            return -1.0;
-        return 1e3 * ms / kReps;
+        double best = 1e300;   // the fastest of a few trials: least disturbed
+        for (int t = 0; t < kTrials; ++t) {
+            float ms = 0.0f;
+            if (hipEventRecord(e0, s) != hipSuccess) return -1.0;
+            for (int r = 0; r < kReps; ++r) once();
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                return -1.0;
+            const double us = 1e3 * ms / kReps;
+            best = us < best ? us : best;
+        }
+        return best;
     };
     for (int c = 0; c < 4 && rc == XRB_OK; ++c) {
         ctx->M.lanes = ctx->M.lanes_batch = cand[c];
@@ -1490,18 +1495,24 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
             bs = out->single_us[c] < bs ? out->single_us[c] : bs;
             bb = out->batch_us[c] < bb ? out->batch_us[c] : bb;
         }
-        double best = 1e300;
+        double best = 1e300, now = 1e300;
         int la = saved.lanes, lb = saved.lanes_batch;
         for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 4; ++j) {
                 if (!lanes_pair_bitwise(saved, cand[i], cand[j])) continue;
                 const double cost = out->single_us[i] / bs + out->batch_us[j] / bb;
+                if (cand[i] == saved.lanes && cand[j] == saved.lanes_batch) now = cost;
                 if (cost < best) {
                     best = cost;
                     la = cand[i];
                     lb = cand[j];
                 }
             }
+        // keep the current pair unless another is clearly faster (3 %)
+        if (now <= best * 1.03) {
+            la = saved.lanes;
+            lb = saved.lanes_batch;
+        }
         ctx->M.lanes = la;
         ctx->M.lanes_batch = lb;
         out->lanes = la;

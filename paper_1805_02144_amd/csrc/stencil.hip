@@ -17,7 +17,7 @@
 
 namespace xrb {
 
-int stencil_lanes(int n) { return n > 100000 ? 2 : 8; }
+int stencil_lanes(int n) { return n > 16384 ? 2 : 8; }
 
 // The product forms L x itself (eight lanes per cell) for launches over few
 // cells in all, where the saved launch and round trip pay; large grids and

@@ -100,7 +100,8 @@ __global__ void __launch_bounds__(kJtvMaxBlock<EPI>) k_jtv(DevMesh M, JvArgs a, 
     double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
     const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
     double r0 = 0.0, r1 = 0.0;
-    for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
+    // several passes per block: sweep each XCD's cells window by window
+    for (CellRange r = block_cells_swept<L>(n); r.i < r.end; r.i += r.step) {
         const int i = r.i;
         double ui[4], xi[4], lxi[4];
         load4(u, i, ui);

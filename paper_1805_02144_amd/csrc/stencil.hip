@@ -240,7 +240,9 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
     double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
     const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
     double r0 = 0.0, r1 = 0.0;   // this lane's reduction partials
-    const CellRange r_init = block_cells<L>(n);
+    // per-cell reduction needs each block's cells contiguous; the per-lane
+    // accumulation of large grids sweeps each XCD's cells window by window
+    const CellRange r_init = cellred ? block_cells<L>(n) : block_cells_swept<L>(n);
     for (CellRange r = r_init; r.i < r.end; r.i += r.step) {
         const int i = r.i;
         double ui[4], xi[4], lxo[4] = {0.0, 0.0, 0.0, 0.0};

@@ -159,6 +159,24 @@ __device__ inline CellRange block_cells(int n) {
     return {i0 + (int)threadIdx.x / L, i1, (int)blockDim.x / L, i0};
 }
 
+// Multi-pass variant for the reducing kernels on large grids: XCD x owns
+// the cells [x per8, (x+1) per8), and its G/8 blocks sweep them together,
+// pass by pass, in contiguous windows of (G/8) (block/L) cells -- so the
+// lines the blocks of one XCD gather at any time lie in one window of the
+// grid rather than under G/8 separate cursors.  Falls back to block_cells
+// when G is not a multiple of 8.
+template <int L>
+__device__ inline CellRange block_cells_swept(int n) {
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    if (G % kXcd) return block_cells<L>(n);
+    const int x = b % kXcd, k = b / kXcd, nb = G / kXcd;
+    const int per8 = (n + kXcd - 1) / kXcd;
+    const int x0 = x * per8;
+    const int x1 = x0 + per8 < n ? x0 + per8 : n;
+    const int cpb = (int)blockDim.x / L;
+    return {x0 + k * cpb + (int)threadIdx.x / L, x1, nb * cpb, x0};
+}
+
 }  // namespace stc
 
 #define XRB_LANES_DISPATCH_N(NL, CALL)      \

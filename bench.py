@@ -253,6 +253,7 @@ def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
     u0h, uth, ost, oce, oer = F.adjoint_twin(level, F.config_seed(4), ADJ_STEPS, ADJ_OBS)
     dev = "cuda:0"
     ctx = X.Context(mesh, dev, gamma_h=4e-4, tol=1e-10, m_max=40)
+    tune = ctx.autotune(1)                       # launch shapes for this grid
     cells = [torch.tensor(3 * n + oce[ost == k], device=dev) for k in range(ADJ_STEPS + 1)]
     errs = [torch.tensor(oer[ost == k], dtype=torch.float64, device=dev)
             for k in range(ADJ_STEPS + 1)]
@@ -335,7 +336,8 @@ def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
                        "5000 depth observations (twin experiment), FP64, tol 1e-10, m_max 40",
            "loss": L0, "forward_ms": 1e3 * fwd, "reverse_ms": 1e3 * bwd,
            "adjoint_over_forward": bwd / fwd, "fd_rel_err_max": max(fd) if fd else None,
-           "fd_directions": fd_dirs, "fd_eps": eps, "adjoint_krylov": agg}
+           "fd_directions": fd_dirs, "fd_eps": eps, "adjoint_krylov": agg,
+           "lanes": tune["lanes"]}
     if cpu:
         s = O.SWE(mesh, gamma_h=4e-4)
         gh = np.zeros(4 * n)

@@ -66,6 +66,10 @@ def lib():
         if not os.path.exists(LIBPATH):
             raise RuntimeError("libexprb.so is not built: run paper_1805_02144_amd/build.py "
                                "(or __graft_entry__.build())")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so the process holds a single runtime (loading the library
+        # first can leave two, and device allocation fails)
+        import torch  # noqa: F401
         L = C.CDLL(LIBPATH)
         vp = C.c_void_p
         L.xrb_default_params.argtypes = [C.POINTER(Params)]

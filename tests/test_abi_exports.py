@@ -48,3 +48,20 @@ def test_oracle_and_library_share_no_source():
         if f.endswith((".c", ".h")):
             txt = open(os.path.join(osrc, f)).read()
             assert "xrb_" not in txt and "exprb.h" not in txt, f
+
+
+def test_binding_loads_torch_before_the_library():
+    """The library must bind to the HIP runtime torch loads (one runtime per
+    process); the binding imports torch before it opens the library."""
+    import subprocess
+    import sys
+    code = ("import sys, paper_1805_02144_amd as X\n"
+            "assert 'torch' not in sys.modules\n"
+            "X.lib()\n"
+            "assert 'torch' in sys.modules\n")
+    import paper_1805_02144_amd as X
+    if not os.path.exists(X.LIBPATH):
+        pytest.skip("library not built")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]

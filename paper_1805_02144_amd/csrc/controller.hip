@@ -9,8 +9,10 @@
 //   * (tau, m) update with the cost comparison of eq. cost (steps 4-5);
 //   * on acceptance, the coefficients of y_{k+1} (eq. 3.17) for the
 //     combination kernel and t^l/l! for the next w_j recurrence (eq. 3.18).
-// Matrices live in LDS (K <= 49, padded to 52); products use one 4x4
-// register tile per thread.
+// Matrices live in LDS (K <= 49, padded to 52).  The matrix products run on
+// the FP64 matrix cores (16 x 16 tiles, one wave per tile); the Pade
+// denominator solve is a Gauss-Jordan elimination with one barrier per
+// column.
 #include "column.h"
 #include "reduce.h"
 #include "xrb_internal.h"
@@ -23,40 +25,257 @@ constexpr int kLd = 52;                 // padded order, multiple of 4, >= kKmax
 constexpr int kMat = kLd * kLd;
 static_assert(kLd >= kKmax && kLd % 4 == 0, "LDS matrix padding");
 
-// C = A B over the leading K4 x K4 block (K4 multiple of 4).  Register tiles
-// of T x T per thread: T = 2 while (K4/2)^2 threads fit the block, else 4.
-template <int T>
-__device__ inline void mat_mul_tiles(const double *A, const double *B, double *C, int K4) {
-    const int nt = K4 / T;
-    for (int tile = threadIdx.x; tile < nt * nt; tile += blockDim.x) {
-        const int r0 = (tile / nt) * T, c0 = (tile % nt) * T;
-        double acc[T][T];
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// The dense part works on size classes KC in {16, 32, 52} (KC >= K4, rows
+// and columns below KC <= kLd are inside the LDS matrices), so that loops
+// unroll to fixed trip counts.  Loads are unconditional at in-range
+// addresses and masked by a select, with no branch between them: the LDS
+// reads of a phase then go out back to back.
+
+// Products on the FP64 matrix cores.  C = A B over the leading K4 x K4
+// block (K4 a multiple of 4), cut into 16 x 16 output tiles, one wave per
+// tile at a time; each tile is K4/4 rank-4 steps of v_mfma_f64_16x16x4.
+// Lane l supplies A(i0 + l%16, k0 + l/16) and B(k0 + l/16, j0 + l%16) and
+// holds C(i0 + l/16 + 4 v, j0 + l%16), v < 4.  Entries at or past K4 enter
+// as zeros and are never written.  The accumulator starts from
+// init(nb, row, col) (a term added to the product) and each result goes to
+// store(e, values), e the entry's LDS index, so elementwise terms fuse into
+// the product pass.
+// NB operand pairs share one pass (the same A, NB right-hand factors).
+template <int KC, int NB, class Init, class Store>
+__device__ inline void mfma_pass(const double *A, const double *const (&B)[NB], int K4, Init init,
+                                 Store store) {
+    constexpr int KS = KC / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nt = (K4 + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int tile = wave; tile < nt * nt; tile += (int)(blockDim.x >> 6)) {
+        const int i0 = (tile / nt) << 4, j0 = (tile % nt) << 4;
+        const int col = j0 + li, ar = i0 + li;
+        const int colc = col < kLd ? col : kLd - 1, arc = ar < kLd ? ar : kLd - 1;
+        double af[KS], bf[NB][KS];
 #pragma unroll
-        for (int r = 0; r < T; ++r)
+        for (int st = 0; st < KS; ++st) {
+            const int k = 4 * st + lk;
+            const bool ks = 4 * st < K4;
+            const double av = A[arc * kLd + k];
+            af[st] = (ks && ar < K4) ? av : 0.0;
 #pragma unroll
-            for (int c = 0; c < T; ++c) acc[r][c] = 0.0;
-        for (int k = 0; k < K4; ++k) {
-            double a[T], b[T];
+            for (int nb = 0; nb < NB; ++nb) {
+                const double bv = B[nb][k * kLd + colc];
+                bf[nb][st] = (ks && col < K4) ? bv : 0.0;
+            }
+        }
+        dbl4 acc[NB];
 #pragma unroll
-            for (int r = 0; r < T; ++r) a[r] = A[(r0 + r) * kLd + k];
+        for (int v = 0; v < 4; ++v) {
+            const int row = i0 + lk + 4 * v;
+            const int rowc = row < kLd ? row : kLd - 1;
+            const bool in = row < K4 && col < K4;
 #pragma unroll
-            for (int c = 0; c < T; ++c) b[c] = B[k * kLd + c0 + c];
-#pragma unroll
-            for (int r = 0; r < T; ++r)
-#pragma unroll
-                for (int c = 0; c < T; ++c) acc[r][c] += a[r] * b[c];
+            for (int nb = 0; nb < NB; ++nb) {
+                const double iv = init(nb, rowc, colc);
+                acc[nb][v] = in ? iv : 0.0;
+            }
         }
 #pragma unroll
-        for (int r = 0; r < T; ++r)
+        for (int st = 0; st < KS; ++st)
 #pragma unroll
-            for (int c = 0; c < T; ++c) C[(r0 + r) * kLd + c0 + c] = acc[r][c];
+            for (int nb = 0; nb < NB; ++nb)
+                acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[st], bf[nb][st], acc[nb], 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = i0 + lk + 4 * v;
+            if (row < K4 && col < K4) {
+                double out[NB];
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) out[nb] = acc[nb][v];
+                store(row * kLd + col, out);
+            }
+        }
     }
+    __syncthreads();
 }
 
-__device__ void mat_mul(const double *A, const double *B, double *C, int K4) {
-    if ((K4 / 2) * (K4 / 2) <= (int)blockDim.x) mat_mul_tiles<2>(A, B, C, K4);
-    else mat_mul_tiles<4>(A, B, C, K4);
+template <int KC>
+__device__ inline void mat_mul(const double *A, const double *B, double *C, int K4) {
+    const double *const bb[1] = {B};
+    mfma_pass<KC, 1>(A, bb, K4, [](int, int, int) { return 0.0; },
+                     [C](int e, const double(&v)[1]) { C[e] = v[0]; });
+}
+
+// Lane exchange inside a row of 16 lanes by a DPP control word.
+template <int CTRL>
+__device__ inline double dpp_row(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Largest value over the 64 lanes of the wave, returned in every lane:
+// xor-1, xor-2, half-row and row mirrors give each row of 16 its maximum,
+// then the four row results are read as scalars.
+__device__ inline double wave_max_all(double a) {
+    a = fmax(a, dpp_row<0xB1>(a));    // quad_perm [1,0,3,2]
+    a = fmax(a, dpp_row<0x4E>(a));    // quad_perm [2,3,0,1]
+    a = fmax(a, dpp_row<0x141>(a));   // row_half_mirror
+    a = fmax(a, dpp_row<0x140>(a));   // row_mirror
+    return fmax(fmax(read_lane(a, 0), read_lane(a, 16)), fmax(read_lane(a, 32), read_lane(a, 48)));
+}
+
+// X = M^{-1} R for K x K matrices M and R in LDS (row stride kLd, K <= KC),
+// by Gauss-Jordan elimination with partial pivoting: for each column the
+// pivot is the first not yet used row of largest |M(r, col)|, and that
+// column is eliminated from every other row of [M | R].  Rows are never
+// swapped; X(c, :) = R(p_c, :) / M(p_c, c) at the end, p_c the pivot row of
+// column c.  Thread t owns column t mod 128 of [M | R] on the rows of parity
+// t / 128, keeps them in registers and writes every update through to LDS
+// (rows K..KC-1 of M and R are padding and take zeros).  Every wave finds
+// the pivot itself (DPP maximum and a ballot over the column read from
+// LDS), so one barrier per column separates the updates.  X is written over
+// the whole kLd x kLd block (zero outside K x K).  Sets *status to ENAN on
+// a zero pivot.
+template <int KC>
+__device__ inline void gauss_jordan(double *Mt, double *R, double *X, int K, int *piv_of,
+                                    double *dinv_of, int *status) {
+    constexpr int NR = (KC + 1) / 2;   // rows per thread: h, h + 2, ... < KC <= kLd
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int q = tid & 127;
+    const int h = __builtin_amdgcn_readfirstlane(tid >> 7);   // the same in the whole wave
+    const bool live = q < 2 * K;
+    double *P = live ? (q < K ? Mt + q : R + (q - K)) : Mt;
+    const int lrow = lane < kLd ? lane : kLd - 1;
+    double x[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const double v = P[(h + 2 * k) * kLd];
+        x[k] = (live && h + 2 * k < K) ? v : 0.0;
+    }
+    uint64_t used = 0;
+    for (int col = 0; col < K; ++col) {
+        // column col: lane r reads row r (pivot search); every thread reads
+        // the entries of its own rows (multipliers, the same in the wave)
+        const double vr = Mt[lrow * kLd + col];
+        double cm[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) cm[k] = Mt[(h + 2 * k) * kLd + col];
+        const double vs = lane < K ? vr : 0.0;
+        double a = -1.0;
+        if (lane < K && !((used >> lane) & 1)) {
+            const double v = fabs(vs);
+            a = v >= 0.0 ? v : 0.0;   // a NaN entry ranks lowest
+        }
+        const double mx = wave_max_all(a);
+        const int piv = __ffsll((long long)__ballot(a == mx)) - 1;
+        used |= 1ull << piv;
+        const double dinv = 1.0 / read_lane(vs, piv);
+        if (tid == 0) {
+            piv_of[col] = piv;
+            dinv_of[col] = dinv;
+            if (!(mx > 0.0)) *status = XRB_ENAN;
+        }
+        const bool upd_col = live && (q >= K || q > col);
+        const double pv = P[piv * kLd];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const int r = h + 2 * k;
+            const double l = (upd_col && r < K && r != piv) ? cm[k] * dinv : 0.0;
+            x[k] -= l * pv;
+        }
+        if (live) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) P[(h + 2 * k) * kLd] = x[k];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < kMat; e += blockDim.x) {
+        const int c = e / kLd, j = e % kLd;
+        X[e] = (c < K && j < K) ? R[piv_of[c] * kLd + j] * dinv_of[c] : 0.0;
+    }
     __syncthreads();
+}
+
+// Pade [13/13] coefficients of exp from the closed form, b_0 = 1 (evaluated
+// at compile time with the same IEEE operations as at run time)
+struct Pade13 {
+    double b[14];
+};
+constexpr Pade13 pade13() {
+    Pade13 p{};
+    p.b[0] = 1.0;
+    for (int j = 0; j < 13; ++j) p.b[j + 1] = p.b[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
+    return p;
+}
+
+// LDS matrices of the exponential (each kLd x kLd)
+struct ExpmLds {
+    double *Bm, *B2, *B4, *B6, *Ue, *Uo, *Vm;
+    int *piv_of;
+    double *dinv_of;
+};
+
+// exp(Bm)^(2^n_sq) for the scaled matrix Bm of order K (zero padded); the
+// result is one of the LDS matrices, returned.
+template <int KC>
+__device__ double *pade13_expm(const ExpmLds &L, int K, int K4, int n_sq, int *status) {
+    constexpr Pade13 kPade = pade13();
+    const double *b = kPade.b;
+    double *Bm = L.Bm, *B2 = L.B2, *B4 = L.B4, *B6 = L.B6, *Ue = L.Ue, *Uo = L.Uo, *Vm = L.Vm;
+    // B^2, B^4, B^6; the pass forming B^6 also forms the two inner sums
+    //   Ue = b12 B^6 + b10 B^4 + b8 B^2,  Uo = b13 B^6 + b11 B^4 + b9 B^2
+    mat_mul<KC>(Bm, Bm, B2, K4);
+    mat_mul<KC>(B2, B2, B4, K4);
+    {
+        const double *const bb[1] = {B2};
+        mfma_pass<KC, 1>(B4, bb, K4, [](int, int, int) { return 0.0; },
+                         [&](int e, const double(&v)[1]) {
+                             B6[e] = v[0];
+                             Ue[e] = b[12] * v[0] + b[10] * B4[e] + b[8] * B2[e];
+                             Uo[e] = b[13] * v[0] + b[11] * B4[e] + b[9] * B2[e];
+                         });
+    }
+    // one pass, both polynomials (the same B^6 operand):
+    //   V = B^6 Ue + b6 B^6 + b4 B^4 + b2 B^2 + b0 I      -> Vm
+    //   W = B^6 Uo + b7 B^6 + b5 B^4 + b3 B^2 + b1 I      -> B2 (in place)
+    {
+        const double *const bb[2] = {Ue, Uo};
+        mfma_pass<KC, 2>(B6, bb, K4,
+                         [&](int nb, int r, int c) {
+                             const int e = r * kLd + c;
+                             const double id = (r == c && r < K) ? 1.0 : 0.0;
+                             return nb == 0 ? b[6] * B6[e] + b[4] * B4[e] + b[2] * B2[e] + b[0] * id
+                                            : b[7] * B6[e] + b[5] * B4[e] + b[3] * B2[e] + b[1] * id;
+                         },
+                         [&](int e, const double(&v)[2]) {
+                             Vm[e] = v[0];
+                             B2[e] = v[1];
+                         });
+    }
+    // U = B W; the pass writes M = V - U (into B4) and V + U (over V)
+    {
+        const double *const bb[1] = {B2};
+        mfma_pass<KC, 1>(Bm, bb, K4, [](int, int, int) { return 0.0; },
+                         [&](int e, const double(&u)[1]) {
+                             const double v = Vm[e];
+                             B4[e] = v - u[0];
+                             Vm[e] = v + u[0];
+                         });
+    }
+    // X = (V - U)^{-1} (V + U) into Bm, then the squarings
+    gauss_jordan<KC>(B4, Vm, Bm, K, L.piv_of, L.dinv_of, status);
+    double *X = Bm, *T = B2;
+    for (int q = 0; q < n_sq; ++q) {
+        mat_mul<KC>(X, X, T, K4);
+        double *tmp = X;
+        X = T;
+        T = tmp;
+    }
+    return X;
 }
 
 // round x > 0 down to two significant digits with exact decimal scalings
@@ -95,10 +314,11 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
     PhiCtl *c = ctl0 + mk;
     const CtlArgs a = dargs ? dargs[mk] : a0;
     const double *nrm_in = nrm_parts + (size_t)mk * kPartStride + (size_t)a.nrm_buf * kRedBlocks;
-    __shared__ double Bm[kMat], B2[kMat], B4[kMat], B6[kMat], Um[kMat], Vm[kMat];
-    __shared__ double mult[kLd];
+    __shared__ double Bm[kMat], B2[kMat], B4[kMat], B6[kMat], Ue[kMat], Uo[kMat], Vm[kMat];
+    __shared__ int piv_of[kLd];
+    __shared__ double dinv_of[kLd];
     __shared__ double sh_tau_u, sh_norm, sh_hsub;
-    __shared__ int sh_lands, sh_meff, sh_s, sh_piv, sh_status;
+    __shared__ int sh_lands, sh_meff, sh_status;
     __shared__ double red[32];
     const int tid = threadIdx.x;
     const int p = a.p;
@@ -152,166 +372,59 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
     __syncthreads();
     const int meff = sh_meff;
     const double tau_u = sh_tau_u;
-    int K = 0, K4 = 0;
+    int K = 0, K4 = 0, n_sq = 0;
     double *X = nullptr;
 
     if (meff > 0) {
         K = meff + p + 1;
         K4 = (K + 3) & ~3;
-        // Hhat scaled by tau_u, zero padded
-        for (int e = tid; e < kLd * kLd; e += blockDim.x) {
-            const int r = e / kLd, q = e % kLd;
-            double v = 0.0;
-            if (r < meff && q < meff) v = tau_u * c->H[r * kMmax + q];
-            else if (r == 0 && q == meff) v = tau_u;
-            else if (r >= meff && r < meff + p && q == r + 1) v = tau_u;
-            Bm[e] = v;
+        // 2^-s tau Hhat.  Thread q < m reads the IOM2 band of column q of H
+        // (rows q-1, q, q+1; H is zero elsewhere) and the threads of the
+        // augmentation columns hold their single tau; the 1-norm is the
+        // largest column sum.  Every thread derives s from it alike.
+        double hv0 = 0.0, hv1 = 0.0, hv2 = 0.0, csum = 0.0;
+        if (tid < meff) {
+            if (tid > 0) hv0 = tau_u * c->H[(tid - 1) * kMmax + tid];
+            hv1 = tau_u * c->H[tid * kMmax + tid];
+            if (tid + 1 < meff) hv2 = tau_u * c->H[(tid + 1) * kMmax + tid];
+            csum = fabs(hv0) + fabs(hv1) + fabs(hv2);
+        } else if (tid < K) {
+            csum = fabs(tau_u);
         }
-        __syncthreads();
-        // 1-norm of tau Hhat: a column per thread
-        double csum = 0.0;
-        if (tid < K)
-            for (int r = 0; r < K; ++r) csum += fabs(Bm[r * kLd + tid]);
+        for (int e = tid; e < kMat; e += blockDim.x) Bm[e] = 0.0;
         const double nrm = block_max(csum, red);
-        if (tid == 0) {
-            int s = 0;
-            double sc = 1.0;
-            if (!(nrm < 1e300)) {
-                sh_status = XRB_ENAN;   // non-finite Hessenberg entries
-            } else {
-                while (nrm * sc > 5.371920351148152) {
-                    ++s;
-                    sc *= 0.5;
-                }
+        double sc = 1.0;
+        if (!(nrm < 1e300)) {
+            if (tid == 0) sh_status = XRB_ENAN;   // non-finite Hessenberg entries
+        } else {
+            while (nrm * sc > 5.371920351148152) {
+                ++n_sq;
+                sc *= 0.5;
             }
-            sh_norm = nrm;
-            sh_s = s;
-            mult[0] = sc;
+        }
+        if (tid == 0) sh_norm = nrm;
+        if (tid < meff) {
+            if (tid > 0) Bm[(tid - 1) * kLd + tid] = hv0 * sc;
+            Bm[tid * kLd + tid] = hv1 * sc;
+            if (tid + 1 < meff) Bm[(tid + 1) * kLd + tid] = hv2 * sc;
+        } else if (tid == meff) {
+            Bm[meff] = tau_u * sc;                    // row 0 (e_1 e_1^T block)
+        } else if (tid < K) {
+            Bm[(tid - 1) * kLd + tid] = tau_u * sc;   // superdiagonal of N_{p+1}
         }
         __syncthreads();
-        const double sc = mult[0];
-        for (int e = tid; e < kMat; e += blockDim.x) Bm[e] *= sc;
-        __syncthreads();
-        // Pade [13/13] numerator coefficients from the closed form, b_0 = 1
-        double b[14];
-        b[0] = 1.0;
-        for (int j = 0; j < 13; ++j) b[j + 1] = b[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
-        mat_mul(Bm, Bm, B2, K4);
-        mat_mul(B2, B2, B4, K4);
-        mat_mul(B4, B2, B6, K4);
-        // even part V = B6 (b12 B6 + b10 B4 + b8 B2) + b6 B6 + b4 B4 + b2 B2 + b0 I
-        for (int e = tid; e < kMat; e += blockDim.x) Um[e] = b[12] * B6[e] + b[10] * B4[e] + b[8] * B2[e];
-        __syncthreads();
-        mat_mul(B6, Um, Vm, K4);
-        for (int e = tid; e < kMat; e += blockDim.x) {
-            const int r = e / kLd, q = e % kLd;
-            Vm[e] += b[6] * B6[e] + b[4] * B4[e] + b[2] * B2[e] + ((r == q && r < K) ? b[0] : 0.0);
-        }
-        // odd part U = B (B6 (b13 B6 + b11 B4 + b9 B2) + b7 B6 + b5 B4 + b3 B2 + b1 I)
-        for (int e = tid; e < kMat; e += blockDim.x) Um[e] = b[13] * B6[e] + b[11] * B4[e] + b[9] * B2[e];
-        __syncthreads();
-        for (int e = tid; e < kMat; e += blockDim.x) {
-            const int r = e / kLd, q = e % kLd;
-            B2[e] = b[7] * B6[e] + b[5] * B4[e] + b[3] * B2[e] + ((r == q && r < K) ? b[1] : 0.0);
-        }
-        __syncthreads();
-        mat_mul(B6, Um, B4, K4);
-        for (int e = tid; e < kMat; e += blockDim.x) B4[e] += B2[e];
-        __syncthreads();
-        mat_mul(Bm, B4, B6, K4);              // B6 <- U
-        // (V - U) X = (V + U): M in B4, right-hand sides in Vm
-        for (int e = tid; e < kMat; e += blockDim.x) {
-            const double v = Vm[e], u = B6[e];
-            B4[e] = v - u;
-            Vm[e] = v + u;
-        }
-        __syncthreads();
-        double *Mt = B4, *R = Vm;
-        for (int col = 0; col < K; ++col) {
-            // partial pivoting: first row of largest |M(r, col)|, one wave
-            if (tid < 64) {
-                double best = -1.0;
-                int piv = K;
-                for (int r = col + tid; r < K; r += 64) {
-                    const double v = fabs(Mt[r * kLd + col]);
-                    if (v > best) {
-                        best = v;
-                        piv = r;
-                    }
-                }
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ob = __shfl_down(best, off, 64);
-                    const int op = __shfl_down(piv, off, 64);
-                    if (ob > best || (ob == best && op < piv)) {
-                        best = ob;
-                        piv = op;
-                    }
-                }
-                if (tid == 0) {
-                    sh_piv = piv;
-                    if (!(best > 0.0)) sh_status = XRB_ENAN;
-                }
-            }
-            __syncthreads();
-            const int piv = sh_piv < K ? sh_piv : col;
-            if (piv != col) {
-                for (int q = tid; q < K; q += blockDim.x) {
-                    double t = Mt[col * kLd + q];
-                    Mt[col * kLd + q] = Mt[piv * kLd + q];
-                    Mt[piv * kLd + q] = t;
-                    t = R[col * kLd + q];
-                    R[col * kLd + q] = R[piv * kLd + q];
-                    R[piv * kLd + q] = t;
-                }
-                __syncthreads();
-            }
-            const double dinv = 1.0 / Mt[col * kLd + col];
-            const int rows = K - col - 1;
-            // rank-1 update of the trailing rows of M (columns > col) and R
-            const int width = (K - col - 1) + K;
-            for (int e = tid; e < rows * width; e += blockDim.x) {
-                const int r = col + 1 + e / width, q = e % width;
-                const double l = Mt[r * kLd + col] * dinv;
-                if (q < K - col - 1) {
-                    const int qq = col + 1 + q;
-                    Mt[r * kLd + qq] -= l * Mt[col * kLd + qq];
-                } else {
-                    const int qq = q - (K - col - 1);
-                    R[r * kLd + qq] -= l * R[col * kLd + qq];
-                }
-            }
-            __syncthreads();
-        }
-        // back substitution, column-oriented: X(r,:) = R(r,:)/M(r,r), then
-        // R(i,:) -= M(i,r) X(r,:) for i < r
-        for (int r = K - 1; r >= 0; --r) {
-            const double dinv = 1.0 / Mt[r * kLd + r];
-            for (int q = tid; q < K; q += blockDim.x) R[r * kLd + q] *= dinv;
-            __syncthreads();
-            for (int e = tid; e < r * K; e += blockDim.x) {
-                const int i = e / K, q = e % K;
-                R[i * kLd + q] -= Mt[i * kLd + r] * R[r * kLd + q];
-            }
-            __syncthreads();
-        }
-        // zero the padding of R before squaring
-        for (int e = tid; e < kMat; e += blockDim.x) {
-            const int r = e / kLd, q = e % kLd;
-            if (r >= K || q >= K) R[e] = 0.0;
-        }
-        __syncthreads();
-        X = R;
-        double *T = B4;
-        for (int q = 0; q < sh_s; ++q) {
-            mat_mul(X, X, T, K4);
-            double *tmp = X;
-            X = T;
-            T = tmp;
-        }
-        __syncthreads();
+        const ExpmLds L{Bm, B2, B4, B6, Ue, Uo, Vm, piv_of, dinv_of};
+        if (K4 <= 16) X = pade13_expm<16>(L, K, K4, n_sq, &sh_status);
+        else if (K4 <= 32) X = pade13_expm<32>(L, K, K4, n_sq, &sh_status);
+        else X = pade13_expm<kLd>(L, K, K4, n_sq, &sh_status);
     }
 
+    // combination coefficients of the basis, beta sigma_k X(k, m+p-1), a row per thread
+    if (meff > 0) {
+        const int cmain = p > 0 ? meff + p - 1 : 0;
+        const double beta = c->beta;
+        for (int k = tid; k < meff; k += blockDim.x) c->ycoef[p + k] = beta * c->sigma[k] * X[k * kLd + cmain];
+    }
     if (tid == 0) {
 #pragma clang fp contract(off)
         int status = sh_status;
@@ -370,11 +483,8 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
             if (j > 0) fac = fac * tau_u / j;
             c->ycoef[j] = fac;
         }
-        if (meff > 0) {
-            const int cmain = p > 0 ? meff + p - 1 : 0;
-            for (int k = 0; k < meff; ++k) c->ycoef[p + k] = beta * c->sigma[k] * X[k * kLd + cmain];
+        if (meff > 0)
             c->ycoef[p + meff] = beta * sh_hsub * c->sigma[meff] * X[(meff - 1) * kLd + meff + p];
-        }
         double t_new = c->t;
         if (accept) {
             t_new = sh_lands ? c->t_out : c->t + tau_u;

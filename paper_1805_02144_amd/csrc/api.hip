@@ -67,7 +67,8 @@ struct Work {
     CtlArgs *cargs = nullptr;   // [nm]
     int32_t *m0k = nullptr;     // [nm] warm starts
     // pinned host mirrors
-    Decision *h_dec = nullptr;
+    Decision *h_dec = nullptr;   // written by the controller kernel (d_dec: its device address)
+    Decision *d_dec = nullptr;
     int32_t *h_stage = nullptr;  // [2][nm][kPlanW] pinned staging of plan uploads
     std::vector<int32_t> h_plan; // [nm][kPlanW] host working copy of the plan
     CtlArgs *h_cargs = nullptr;
@@ -556,11 +557,9 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             const Batch bc = batch_of(W, W.plan, PF_CTL);
             const CtlArgs a0 = W.h_cargs[0];
             timed(ctx, XRB_K_CTL, [&] {
-                launch_controller(W.ctl, a0, nm > 1 ? W.cargs : nullptr, W.nrm_parts, bc, s);
+                launch_controller(W.ctl, a0, nm > 1 ? W.cargs : nullptr, W.nrm_parts, W.d_dec, bc, s);
             });
         }
-        HIPCHK(hipMemcpy2DAsync(W.h_dec, sizeof(Decision), &W.ctl[0].dec, sizeof(PhiCtl),
-                                sizeof(Decision), nm, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         prof_drain(ctx);
         bool any_comb = false;
@@ -697,6 +696,7 @@ int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
     ck(hipMalloc((void **)&W.cargs, sizeof(CtlArgs) * nm));
     ck(hipMalloc((void **)&W.m0k, sizeof(int32_t) * nm));
     ck(hipHostMalloc((void **)&W.h_dec, sizeof(Decision) * nm, hipHostMallocDefault));
+    if (W.h_dec) ck(hipHostGetDevicePointer((void **)&W.d_dec, W.h_dec, 0));
     ck(hipHostMalloc((void **)&W.h_stage, sizeof(int32_t) * 2 * kPlanW * nm, hipHostMallocDefault));
     W.h_plan.assign((size_t)kPlanW * nm, 0);
     ck(hipHostMalloc((void **)&W.h_cargs, sizeof(CtlArgs) * nm, hipHostMallocDefault));

@@ -308,7 +308,7 @@ __device__ double work_estimate(double tau, int m, int p, double t, double t_out
 
 __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
                                                        const CtlArgs *dargs, double *nrm_parts,
-                                                       Batch bt) {
+                                                       Decision *hdec, Batch bt) {
     const int mk = blockIdx.x;
     if (!member_active(bt.pred, mk)) return;
     PhiCtl *c = ctl0 + mk;
@@ -502,23 +502,27 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
             c->prev_tau = tau_u;
             c->prev_m = m;
         }
-        c->dec.tau_u = tau_u;
-        c->dec.omega = omega;
-        c->dec.t = t_new;
-        c->dec.accept = accept;
-        c->dec.lands = sh_lands;
-        c->dec.m_next = m_next;
-        c->dec.m_eff = meff;
-        c->dec.status = status;
-        c->dec.reached = (t_new >= c->t_out) ? 1 : 0;
+        Decision d;
+        d.tau_u = tau_u;
+        d.omega = omega;
+        d.t = t_new;
+        d.accept = accept;
+        d.lands = sh_lands;
+        d.m_next = m_next;
+        d.m_eff = meff;
+        d.status = status;
+        d.reached = (t_new >= c->t_out) ? 1 : 0;
+        c->dec = d;
+        hdec[mk] = d;
     }
 }
 
 }  // namespace
 
 void launch_controller(PhiCtl *ctl, const CtlArgs &a, const CtlArgs *dargs, double *nrm_parts,
-                       const Batch &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_controller, dim3(b.nm), dim3(kBlock), 0, s, ctl, a, dargs, nrm_parts, b);
+                       Decision *hdec, const Batch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_controller, dim3(b.nm), dim3(kBlock), 0, s, ctl, a, dargs, nrm_parts, hdec,
+                       b);
 }
 
 }  // namespace xrb

@@ -259,11 +259,13 @@ struct CtlArgs {
     ReplayIn rep;
 };
 // Small augmented-Hessenberg exponential + error estimate + (tau, m) controller
-// for the current attempt; writes ctl->dec and, on accept, the combine
-// coefficients and the next point's recurrence coefficients.  Per-member
-// arguments come from `dargs` (device, [nm]) when set, else from `a`.
+// for the current attempt; writes ctl->dec (and the same record to hdec[k],
+// pinned host memory mapped on the device, which the host reads after a
+// stream synchronisation) and, on accept, the combine coefficients and the
+// next point's recurrence coefficients.  Per-member arguments come from
+// `dargs` (device, [nm]) when set, else from `a`.
 void launch_controller(PhiCtl *ctl, const CtlArgs &a, const CtlArgs *dargs, double *nrm_parts,
-                       const Batch &b, hipStream_t s);
+                       Decision *hdec, const Batch &b, hipStream_t s);
 // Initialise a call: t = 0, tau = rho_1, m, q, kappa, tol_abs from the norm
 // partials of the nv input vectors; vnorm2[k*(kPmax+1) + l] = ||v_l||^2.
 // m0 per member from m0k (device, [nm]) when set, else m0.

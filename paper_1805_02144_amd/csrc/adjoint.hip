@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(kJtvMaxBlock<EPI>) k_jtv(DevMesh M, JvArgs a, 
             const double vx = xj[0], vy = xj[1], vz = xj[2], vh = xj[3];
             const double wx = uj[0], wy = uj[1], wz = uj[2];
             const Cell cj = load_cell(M.cen, j);
-            const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e]);
             const double c = M.cl[e];
             const double raj = cj.ra;
             const double sj = vx * (cj.y * wz - cj.z * wy) + vy * (cj.z * wx - cj.x * wz) +
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(256) k_kpairs(DevMesh M, KPairArgs k, Batch bt
                 const int e = 6 * i + s;
                 const int j = M.nbr[e];
                 const Cell cj = load_cell(M.cen, j);
-                const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+                const EdgeW w = edge_weights(ci, cj, M.alpha[e]);
                 double aj_[4], bj_[4];
                 load4(av, j, aj_);
                 load4(bv, j, bj_);

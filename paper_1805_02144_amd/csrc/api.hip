@@ -69,6 +69,7 @@ struct Work {
     // pinned host mirrors
     Decision *h_dec = nullptr;   // written by the controller kernel (d_dec: its device address)
     Decision *d_dec = nullptr;
+    int dec_seq = 0;             // sequence number of the last controller launch
     int32_t *h_stage = nullptr;  // [2][nm][kPlanW] pinned staging of plan uploads
     std::vector<int32_t> h_plan; // [nm][kPlanW] host working copy of the plan
     CtlArgs *h_cargs = nullptr;
@@ -205,9 +206,15 @@ void timed(xrb_ctx *ctx, int id, F &&launch) {
     ctx->ev_pend.push_back({id, a, b});
 }
 
-// Collect finished event pairs (called after a stream synchronisation).
-void prof_drain(xrb_ctx *ctx) {
+// Collect event pairs: all of them (waiting for each; called after a stream
+// synchronisation), or with block = false only those already complete.
+void prof_drain(xrb_ctx *ctx, bool block = true) {
+    size_t keep = 0;
     for (auto &p : ctx->ev_pend) {
+        if (!block && hipEventQuery(p.b) == hipErrorNotReady) {
+            ctx->ev_pend[keep++] = p;
+            continue;
+        }
         float ms = 0.f;
         if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
             ctx->prof_ms[p.id] += ms;
@@ -216,7 +223,28 @@ void prof_drain(xrb_ctx *ctx) {
         ctx->ev_free.push_back(p.a);
         ctx->ev_free.push_back(p.b);
     }
-    ctx->ev_pend.clear();
+    ctx->ev_pend.resize(keep);
+}
+
+// Wait until the controller launch numbered seq has stored the decision
+// records of the members whose plan entry has PF_CTL set (each record is
+// complete once its seq field holds the number; see launch_controller).
+// The stream is polled every 256 spins: once it has drained, or reports an
+// error, a missing record is an error rather than a wait.
+int wait_decisions(xrb_ctx *ctx, const Work &W, int seq) {
+    for (int k = 0; k < W.nm; ++k) {
+        if (W.nm > 1 && !W.h_plan[kPlanW * k + PF_CTL]) continue;
+        int spins = 0;
+        while (__atomic_load_n(&W.h_dec[k].seq, __ATOMIC_ACQUIRE) != seq) {
+            if (++spins % 256 != 0) continue;
+            const hipError_t q = hipStreamQuery(ctx->stream);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return fail(ctx, XRB_EDEVICE, hipGetErrorString(q));
+            if (__atomic_load_n(&W.h_dec[k].seq, __ATOMIC_ACQUIRE) != seq)
+                return fail(ctx, XRB_EDEVICE, "phi_combo: decision record missing");
+        }
+    }
+    return XRB_OK;
 }
 
 Batch batch_of(const Work &W, const int32_t *plan = nullptr, int field = 0, int j = 0) {
@@ -556,12 +584,17 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
         {
             const Batch bc = batch_of(W, W.plan, PF_CTL);
             const CtlArgs a0 = W.h_cargs[0];
+            W.dec_seq = W.dec_seq == INT32_MAX ? 1 : W.dec_seq + 1;   // never 0 (see the record)
             timed(ctx, XRB_K_CTL, [&] {
-                launch_controller(W.ctl, a0, nm > 1 ? W.cargs : nullptr, W.nrm_parts, W.d_dec, bc, s);
+                launch_controller(W.ctl, a0, nm > 1 ? W.cargs : nullptr, W.nrm_parts, W.d_dec,
+                                  W.dec_seq, bc, s);
             });
         }
-        HIPCHK(hipStreamSynchronize(s));
-        prof_drain(ctx);
+        {
+            const int rc = wait_decisions(ctx, W, W.dec_seq);
+            if (rc) return rc;
+        }
+        prof_drain(ctx, false);
         bool any_comb = false;
         int copy_slot = 0;
         for (int k = 0; k < nm; ++k) {
@@ -695,8 +728,13 @@ int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
     ck(hipMalloc((void **)&W.plan, sizeof(int32_t) * kPlanW * nm));
     ck(hipMalloc((void **)&W.cargs, sizeof(CtlArgs) * nm));
     ck(hipMalloc((void **)&W.m0k, sizeof(int32_t) * nm));
-    ck(hipHostMalloc((void **)&W.h_dec, sizeof(Decision) * nm, hipHostMallocDefault));
-    if (W.h_dec) ck(hipHostGetDevicePointer((void **)&W.d_dec, W.h_dec, 0));
+    // coherent mapped memory: the host polls the records' sequence numbers
+    ck(hipHostMalloc((void **)&W.h_dec, sizeof(Decision) * nm,
+                     hipHostMallocMapped | hipHostMallocCoherent));
+    if (W.h_dec) {
+        std::memset((void *)W.h_dec, 0, sizeof(Decision) * nm);
+        ck(hipHostGetDevicePointer((void **)&W.d_dec, W.h_dec, 0));
+    }
     ck(hipHostMalloc((void **)&W.h_stage, sizeof(int32_t) * 2 * kPlanW * nm, hipHostMallocDefault));
     W.h_plan.assign((size_t)kPlanW * nm, 0);
     ck(hipHostMalloc((void **)&W.h_cargs, sizeof(CtlArgs) * nm, hipHostMallocDefault));
@@ -1288,8 +1326,8 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ctx->n = n;
     ctx->n4 = 4 * n;
     const size_t nd = (size_t)n;
-    // geometry in one allocation: 3 x [n][6] edge scalars, [n][4] cell records, [n][6] int32
-    const size_t dbl = 3 * 6 * nd + 4 * nd;
+    // geometry in one allocation: 2 x [n][6] edge scalars, [n][4] cell records, [n][6] int32
+    const size_t dbl = 2 * 6 * nd + 4 * nd;
     const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t);
     if (hipMalloc(&ctx->geo_mem, bytes) != hipSuccess) {
         delete ctx;
@@ -1308,13 +1346,13 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
         }
     };
     double *g = (double *)ctx->geo_mem;
-    const std::vector<double> *srcs[3] = {&geo.alpha, &geo.beta, &geo.cl};
-    double *dst[3];
-    for (int k = 0; k < 3; ++k) {
+    const std::vector<double> *srcs[2] = {&geo.alpha, &geo.cl};
+    double *dst[2];
+    for (int k = 0; k < 2; ++k) {
         dst[k] = g + (size_t)k * 6 * nd;
         ck(hipMemcpy(dst[k], srcs[k]->data(), sizeof(double) * 6 * nd, hipMemcpyHostToDevice));
     }
-    double *cen = g + 3 * 6 * nd;     // byte offset 144 n: 16-byte aligned
+    double *cen = g + 2 * 6 * nd;     // byte offset 96 n: 16-byte aligned
     ck(hipMemcpy(cen, geo.cen.data(), sizeof(double) * 4 * nd, hipMemcpyHostToDevice));
     int32_t *nb = (int32_t *)(g + dbl);
     ck(hipMemcpy(nb, geo.nbr.data(), sizeof(int32_t) * 6 * nd, hipMemcpyHostToDevice));
@@ -1328,8 +1366,7 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     M.n = n;
     M.nbr = nb;
     M.alpha = dst[0];
-    M.beta = dst[1];
-    M.cl = dst[2];
+    M.cl = dst[1];
     M.cen = cen;
     M.lanes = params->lanes ? params->lanes : stencil_lanes(n);
     // batches of small grids take two lanes per cell (same bits as eight)

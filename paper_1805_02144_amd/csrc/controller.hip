@@ -308,7 +308,7 @@ __device__ double work_estimate(double tau, int m, int p, double t, double t_out
 
 __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
                                                        const CtlArgs *dargs, double *nrm_parts,
-                                                       Decision *hdec, Batch bt) {
+                                                       Decision *hdec, int seq, Batch bt) {
     const int mk = blockIdx.x;
     if (!member_active(bt.pred, mk)) return;
     PhiCtl *c = ctl0 + mk;
@@ -512,17 +512,21 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
         d.m_eff = meff;
         d.status = status;
         d.reached = (t_new >= c->t_out) ? 1 : 0;
+        d.seq = 0;
         c->dec = d;
+        // the host copy: record first, then its sequence number behind a
+        // system-scope release (vector stores to mapped host memory)
         hdec[mk] = d;
+        __hip_atomic_store(&hdec[mk].seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
 }  // namespace
 
 void launch_controller(PhiCtl *ctl, const CtlArgs &a, const CtlArgs *dargs, double *nrm_parts,
-                       Decision *hdec, const Batch &b, hipStream_t s) {
+                       Decision *hdec, int seq, const Batch &b, hipStream_t s) {
     hipLaunchKernelGGL(k_controller, dim3(b.nm), dim3(kBlock), 0, s, ctl, a, dargs, nrm_parts, hdec,
-                       b);
+                       seq, b);
 }
 
 }  // namespace xrb

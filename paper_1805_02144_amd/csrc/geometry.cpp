@@ -15,7 +15,8 @@
 // x_i + x_j, so n_e = (x_j - x_i)/|x_j - x_i| and t_e = 2 (x_i x x_j) /
 // (|x_i + x_j| |x_j - x_i|): the kernels rebuild a_s and b_s from two
 // scalars per edge and the centres they already load,
-//   alpha_s = l_e / (2 A_i |x_j - x_i|),  beta_s = 2 alpha_s / |x_i + x_j|.
+//   alpha_s = l_e / (2 A_i |x_j - x_i|),  beta_s = 2 alpha_s / |x_i + x_j|,
+// of which alpha_s is stored and beta_s formed in the kernels.
 // Pentagon slot 5 gets zero weights.
 #include <cmath>
 
@@ -28,7 +29,6 @@ struct V3 {
     double x, y, z;
 };
 inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 inline V3 cross(V3 a, V3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
@@ -60,7 +60,7 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
     geo.n = (int)n;
     auto resize6 = [&](std::vector<double> &v) { v.assign(6 * (size_t)n, 0.0); };
     geo.nbr.assign(6 * (size_t)n, 0);
-    resize6(geo.alpha); resize6(geo.beta); resize6(geo.cl);
+    resize6(geo.alpha); resize6(geo.cl);
     geo.cen.assign(4 * (size_t)n, 0.0);
 
     auto X = [&](int64_t i) { return V3{mesh.xyz[3 * i], mesh.xyz[3 * i + 1], mesh.xyz[3 * i + 2]}; };
@@ -96,9 +96,7 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
             const double le = R * angle(CRN(i, (s + d - 1) % d), CRN(i, s));
             const double de = R * angle(xi, xj);
             const double chord = len(sub(xj, xi));
-            const double alpha = le / (2.0 * area * chord);
-            geo.alpha[k] = alpha;
-            geo.beta[k] = 2.0 * alpha / len(add(xi, xj));
+            geo.alpha[k] = le / (2.0 * area * chord);
             geo.cl[k] = le / (de * area);
         }
         double *ce = &geo.cen[4 * (size_t)i];

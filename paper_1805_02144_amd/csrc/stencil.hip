@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             const Cell cj = load_cell(M.cen, j);
-            const EdgeW w = edge_weights(ci, cj, 0.0, M.beta[e]);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e]);
             double uj[4];
             load4(u, j, uj);
             z = acc_add(z, w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]));
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
             load4(lu, j, luj);
             const double vx = uj[0], vy = uj[1], vz = uj[2], hj = uj[3];
             const Cell cj = load_cell(M.cen, j);
-            const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e]);
             const double c = M.cl[e];
             const double Ej = 0.5 * (vx * vx + vy * vy + vz * vz) + g * (M.hs ? hj + M.hs[j] : hj);
             const double dE = Ej - Ei;
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
             const double vx = xj[0], vy = xj[1], vz = xj[2], vh = xj[3];
             const double wx = uj[0], wy = uj[1], wz = uj[2], wh = uj[3];
             const Cell cj = load_cell(M.cen, j);
-            const EdgeW w = edge_weights(ci, cj, M.alpha[e], M.beta[e]);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e]);
             const double c = M.cl[e];
             const double sj = wx * vx + wy * vy + wz * vz + g * vh;
             const double ds = sj - si;
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(256) k_diag(DevMesh M, const double *__restric
             const int e = 6 * i + s;
             const int j = M.nbr[e];
             const Cell cj = load_cell(M.cen, j);
-            const EdgeW w = edge_weights(ci, cj, 0.0, M.beta[e]);
+            const EdgeW w = edge_weights(ci, cj, M.alpha[e]);
             double uj[4];
             load4(u, j, uj);
             z = acc_add(z, w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]));
@@ -465,7 +465,7 @@ void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hip
                            0, s, M, a, b);
         return;
     }
-    const int grid = red_parts(M.n), block = red_block(M.n, b.nm);
+    const int grid = red_parts(M.n), block = red_block(M.n, b.nm, L);
     if (epi == kEpiIom2) {
         hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
     } else {

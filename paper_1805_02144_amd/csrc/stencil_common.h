@@ -32,13 +32,18 @@ inline int red_cells(int n) {
     return (n + g - 1) / g;
 }
 
-// Block size of a reducing product launch over nm members: with per-cell
-// reduction the block size is free, so a launch over few cells in all takes
-// 512 threads (about one pass over its chunk, for latency) and a large
-// batch keeps 256 (fewer idle lanes in the last pass, for throughput).
-inline int red_block(int n, int nm) {
-    if (red_cells(n) > kCellRedMax) return red_block(n);
-    return ((long)nm * n <= 200000L && n > 16384) ? 512 : 256;
+// Block size of a reducing product launch over nm members with L lanes per
+// cell: with per-cell reduction the block size is free, so a launch over few
+// cells in all takes 512 threads (one pass over its chunk, for latency) and a
+// large batch the fewest whole waves that cover the chunk in one pass, at
+// most 256 (fewer idle lanes, for throughput: a level-6 chunk of 81 cells on
+// two lanes fills 162 of 192 threads instead of 162 of 256).
+inline int red_block(int n, int nm, int L) {
+    const int per = red_cells(n);
+    if (per > kCellRedMax) return red_block(n);
+    if ((long)nm * n <= 200000L && n > 16384) return 512;
+    const int b = (per * L + 63) / 64 * 64;
+    return b < 256 ? b : 256;
 }
 
 // Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).
@@ -124,12 +129,22 @@ __device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]
     o[3] = b.y;
 }
 
-// Flux and circulation weights of the edge i -> j rebuilt from its two
-// scalars: a = alpha (x_j - x_i), b = beta (x_i x x_j).
+// Flux and circulation weights of the edge i -> j rebuilt from its stored
+// scalar alpha and the two unit centres: a = alpha (x_j - x_i) and
+// b = beta (x_i x x_j) with beta = 2 alpha / |x_i + x_j| (the edge's
+// circulation weight l t / (2 A_i)).  beta is evaluated without contraction,
+// so every kernel and lane count forms the same bits.
 struct EdgeW {
     double ax, ay, az, bx, by, bz;
 };
-__device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al, double be) {
+__device__ inline double edge_beta(const Cell &ci, const Cell &cj, double al) {
+#pragma clang fp contract(off)
+    const double sx = ci.x + cj.x, sy = ci.y + cj.y, sz = ci.z + cj.z;
+    const double s2 = (sx * sx + sy * sy) + sz * sz;
+    return (2.0 * al) * rsqrt(s2);
+}
+__device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al) {
+    const double be = edge_beta(ci, cj, al);
     EdgeW w;
     w.ax = al * (cj.x - ci.x);
     w.ay = al * (cj.y - ci.y);

@@ -21,12 +21,12 @@ constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix or
 // edge midpoint direction, so the flux and circulation weights are
 //   a = l n_e / (2 A_i)  = alpha (x_j - x_i),  alpha = l / (2 A_i |x_j - x_i|)
 //   b = l t_e / (2 A_i)  = beta  (x_i x x_j),  beta  = 2 alpha / |x_i + x_j|
-// and the Laplacian weight is c = l / (d A_i).
+// and the Laplacian weight is c = l / (d A_i).  alpha and c are stored per
+// edge slot; the kernels form beta from alpha and the two centres they load.
 struct DevMesh {
     int n = 0;
     const int32_t *nbr = nullptr;                  // [n][6]
     const double *alpha = nullptr;                 // [n][6]
-    const double *beta = nullptr;                  // [n][6]
     const double *cl = nullptr;                    // [n][6]
     const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, 1 / cell area
     double nu = 0.0, g = 0.0;
@@ -54,6 +54,7 @@ struct Decision {
     int32_t m_eff;      // basis size used (breakdown may shorten it)
     int32_t status;     // 0 or an xrb_status
     int32_t reached;    // t == t_out after the attempt
+    int32_t seq;        // host copy only: the attempt's sequence number, stored last
 };
 
 // Device-resident state of one phi_combo evaluation.
@@ -259,13 +260,14 @@ struct CtlArgs {
     ReplayIn rep;
 };
 // Small augmented-Hessenberg exponential + error estimate + (tau, m) controller
-// for the current attempt; writes ctl->dec (and the same record to hdec[k],
-// pinned host memory mapped on the device, which the host reads after a
-// stream synchronisation) and, on accept, the combine coefficients and the
-// next point's recurrence coefficients.  Per-member arguments come from
-// `dargs` (device, [nm]) when set, else from `a`.
+// for the current attempt; writes ctl->dec and, on accept, the combine
+// coefficients and the next point's recurrence coefficients.  The same record
+// goes to hdec[k] (pinned host memory mapped on the device) followed by a
+// system-scope release store of `seq` into hdec[k].seq, so the host may read
+// the record as soon as it sees that number, without a stream synchronisation.
+// Per-member arguments come from `dargs` (device, [nm]) when set, else from `a`.
 void launch_controller(PhiCtl *ctl, const CtlArgs &a, const CtlArgs *dargs, double *nrm_parts,
-                       Decision *hdec, const Batch &b, hipStream_t s);
+                       Decision *hdec, int seq, const Batch &b, hipStream_t s);
 // Initialise a call: t = 0, tau = rho_1, m, q, kappa, tol_abs from the norm
 // partials of the nv input vectors; vnorm2[k*(kPmax+1) + l] = ||v_l||^2.
 // m0 per member from m0k (device, [nm]) when set, else m0.
@@ -337,7 +339,7 @@ void launch_adj_vanloan(const PhiCtl *c, const PhiCtl *cy, const AdjVArgs &a, do
 struct HostGeometry {
     int n = 0;
     std::vector<int32_t> nbr;                              // [n][6]
-    std::vector<double> alpha, beta, cl;                   // [n][6]
+    std::vector<double> alpha, cl;                         // [n][6]
     std::vector<double> cen;                               // [n][4] x, y, z, 1 / area
     double nu = 0.0;
 };

@@ -401,6 +401,8 @@ def main():
                          "kernel for scaling PMC byte counters)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the level-7 adjoint leg")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the 64-member level-6 ensemble leg")
     ap.add_argument("--event-every", type=int, default=64,
                     help="time every N-th launch of each kernel of the level-6 workload with HIP "
                          "events (each timed launch adds two event records; 16 costs the "
@@ -425,6 +427,9 @@ def main():
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_leg(X, torch, cpu=not args.no_cpu)}))
+        return
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": ensemble_leg(X, torch, get_mesh(6))}))
         return
 
     level = 6

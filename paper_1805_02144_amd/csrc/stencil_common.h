@@ -33,17 +33,18 @@ inline int red_cells(int n) {
 }
 
 // Block size of a reducing product launch over nm members with L lanes per
-// cell: with per-cell reduction the block size is free, so a launch over few
-// cells in all takes 512 threads (one pass over its chunk, for latency) and a
-// large batch the fewest whole waves that cover the chunk in one pass, at
-// most 256 (fewer idle lanes, for throughput: a level-6 chunk of 81 cells on
-// two lanes fills 162 of 192 threads instead of 162 of 256).
+// cell: with per-cell reduction the block size is free, so a launch takes the
+// fewest whole waves that cover its chunk in one pass, at most 512 threads for
+// a launch over few cells in all on a grid above 16384 cells (latency) and 256
+// otherwise (throughput).  A level-6 chunk of 81 cells on two lanes fills 162
+// of 192 threads (fewer idle lanes than 256 in batches, and at least as fast
+// as 512 for a single state).
 inline int red_block(int n, int nm, int L) {
     const int per = red_cells(n);
     if (per > kCellRedMax) return red_block(n);
-    if ((long)nm * n <= 200000L && n > 16384) return 512;
+    const int cap = ((long)nm * n <= 200000L && n > 16384) ? 512 : 256;
     const int b = (per * L + 63) / 64 * 64;
-    return b < 256 ? b : 256;
+    return b < cap ? b : cap;
 }
 
 // Lane exchange inside a row by a DPP control word (VALU, no LDS traffic).

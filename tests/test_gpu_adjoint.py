@@ -248,3 +248,44 @@ def test_autograd_trajectory(X):
     for k in range(steps):
         ctx.step("exprb42", u, dt)
     assert np.array_equal(to_np(u), states[-1].detach().cpu().numpy())
+
+
+def test_c5_level7_step_vjp(X):
+    """C5 at full size (level 7, the twin-experiment state): one exprb42
+    step VJP of 1800 s on the oracle's recorded schedule, in the adjoint
+    workload's launch configuration (lanes chosen by the autotuner), against
+    the oracle's VJP, per variable block."""
+    import torch
+    level, dt = 7, 1800.0
+    mesh = get_mesh(level)
+    s = O.SWE(mesh)
+    n = s.n
+    u0h, _, ost, oce, _ = F.adjoint_twin(level, F.config_seed(4), 12, 5000)
+    sch = O.new_schedule()
+    u1 = O.swe_stepper(s, "exprb42").step(u0h, dt, O.opts(mode=O.RECORD, sched=sch))
+    arr = sch.as_array()
+    rng = np.random.default_rng(3)
+    ubar = np.zeros(4 * n)
+    sel = oce[ost == 1]
+    ubar[3 * n + sel] = rng.normal(0.0, 5.0, len(sel))
+    gref, _ = s.step_vjp("exprb42", u0h, dt, ubar,
+                         O.opts(mode=O.REPLAY, sched=O.schedule_from_array(arr)))
+    ctx = X.Context(mesh, "cuda:0")
+    try:
+        tune = ctx.autotune(1)
+        say("C5 level 7, lanes", tune["lanes"], "attempts", len(arr))
+        ctx.reset_history()
+        ctx.schedule_set(arr)
+        ctx.schedule_mode(X.REPLAY)
+        u = torch.tensor(u0h, device="cuda:0")
+        ctx.step("exprb42", u, dt)
+        ctx.schedule_mode(X.FREE)
+        g1 = to_np(u)
+        assert blocks_rel(g1, u1, n) < TOL
+        assert blocks_rel(g1 - u0h, u1 - u0h, n) < TOL
+        gg = to_np(ctx.step_vjp("exprb42", u0h, dt, ubar, sched=arr))
+        err = blocks_rel(gg, gref, n)
+        say("  vjp rel", err)
+        assert err < TOL
+    finally:
+        ctx.close()

@@ -267,6 +267,38 @@ def test_c2_level6_first_step(X, method):
     assert blocks_rel(outs[0] - u0, refs[0] - u0, s.n) < TOL
 
 
+def test_c3_level8_stencils(X):
+    """Level 8 (n = 2621448, the jet state, gamma_h = 1.25e-2): F(u) and J(u)v
+    in the launch configuration of the level-8 workload (two lanes per cell,
+    multi-pass 1024-thread reducing products).  F of the balanced zonal jet is
+    a small difference of large terms (the pressure gradient alone is 30-50
+    times the velocity tendency; the edge fluxes of the nearly non-divergent
+    jet cancel in the depth tendency), so rounding-level differences of the
+    two sides' geometry show up amplified: F is held to the method's 1e-11,
+    the product along a random direction to the stencil bar."""
+    mesh, ctx, s = setup(X, 8, gamma_h=1.25e-2)
+    u = F.initial_state("c3_l8_jet")
+    v = rand_dir(s.n, 8)
+    e_rhs = blocks_rel(to_np(ctx.rhs(u)), s.rhs(u), s.n)
+    e_jv = blocks_rel(to_np(ctx.jv(u, v)), s.jv(u, v), s.n)
+    say("level 8 rhs %.2e jv %.2e" % (e_rhs, e_jv))
+    assert e_rhs < TOL
+    assert e_jv < TOL_STENCIL
+
+
+def test_c3_level8_first_step(X):
+    """C3 at full size (level 8, jet + bump, gamma_h = 1.25e-2): the first
+    1800 s exprb53 step on the oracle's schedule (the oracle takes about a
+    minute for it)."""
+    mesh, ctx, s = setup(X, 8, gamma_h=1.25e-2)
+    u0 = F.initial_state("c3_l8_jet")
+    say("C3 exprb53 level 8")
+    outs, refs, rs, _ = run_steps(X, ctx, s, "exprb53", u0, 1800.0, 1, True)
+    say("  attempts", len(rs))
+    assert blocks_rel(outs[0], refs[0], s.n) < TOL
+    assert blocks_rel(outs[0] - u0, refs[0] - u0, s.n) < TOL
+
+
 def test_mass_and_rest_over_steps(X):
     import torch
     mesh, ctx, s = setup(X, 5)

@@ -263,11 +263,46 @@ xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt);
  *   stats  optional host [nm][3] per-member, per-call-site statistics
  * The ensemble keeps its own per-member warm starts and epi3 history; the
  * first call with a given nm allocates an nm-member workspace (about
- * nm (m_max + 28) 32 N bytes), a call with another nm replaces it.  Results
+ * nm (m_max + 35) 32 N bytes), a call with another nm replaces it.  Results
  * equal those of xrb_step on each member alone (same kernels, same
  * reduction order).  Replay scheduling is not available for ensembles. */
 xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, const double *dt,
                           xrb_phi_stats *stats);
+
+/* A general exponential Rosenbrock scheme (eq. 3.10: internal stages U_ni
+ * and weights built from phi_k functions of c_i dt J_n, whose stiff order
+ * conditions Table 1 lists) written as the sequence of phi-combination
+ * calls of Sec. 4.4.  With A = dt J(u_n), v = dt F(u_n) and the nonlinear
+ * remainders D_i = F(U_i) - F(u_n) - J(u_n)(U_i - u_n) (eq. Dni):
+ *   call c = 0..ncalls-1, in order:
+ *     v_l = vc[c][l][0] v + sum_s vc[c][l][1+s] dt D_{s+2}   (l = 1..p[c]; v_0 = 0),
+ *     outputs W_{c,o} = sum_l rho[c][o]^l phi_l(rho[c][o] A) v_l, o < ns[c]
+ *     (0 < rho[c][0] < rho[c][1] <= 1; the rho^l weights as in xrb_phi_combo);
+ *   after call c, each stage s with stage_call[s] == c:
+ *     U_{s+2} = u_n + sum_{c' <= c, o} uc[s][c'][o] W_{c',o}, then D_{s+2};
+ *   u_{n+1} = u_n + sum_{c, o} un1[c][o] W_{c,o}.
+ * A v_l may use only remainders of stages defined before call c.  Call site
+ * c keeps its own Krylov warm start, as in xrb_step.  The built-in schemes
+ * written this way give the same bits as xrb_step (the same vector
+ * combinations in the same order).  Limits: 3 calls of 2 outputs, 2
+ * internal stages, p[c] <= XRB_PMAX, at most 5 nonzero output terms in a
+ * stage or in u_{n+1}.  Errors: EINVAL (limits, rho order, a remainder used
+ * before its stage), then as xrb_step. */
+#define XRB_TAB_CALLS 3
+#define XRB_TAB_OUT 2
+#define XRB_TAB_STAGES 2
+typedef struct {
+    int ncalls;
+    int p[XRB_TAB_CALLS];
+    int ns[XRB_TAB_CALLS];
+    double rho[XRB_TAB_CALLS][XRB_TAB_OUT];
+    double vc[XRB_TAB_CALLS][XRB_PMAX + 1][1 + XRB_TAB_STAGES];
+    int nstages;
+    int stage_call[XRB_TAB_STAGES];
+    double uc[XRB_TAB_STAGES][XRB_TAB_CALLS][XRB_TAB_OUT];
+    double un1[XRB_TAB_CALLS][XRB_TAB_OUT];
+} xrb_tableau;
+xrb_status xrb_step_tableau(xrb_ctx *ctx, const xrb_tableau *tab, double *u, double dt);
 
 /* Per-call-site statistics of the last xrb_step (3 entries). */
 xrb_status xrb_step_stats(const xrb_ctx *ctx, xrb_phi_stats *out3);

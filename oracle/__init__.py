@@ -14,9 +14,9 @@ _LIBPATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 FREE, RECORD, REPLAY = 0, 1, 2
-EXPRB42, PEXPRB43, EXPRB53, EPI3, EPI2, EXPRB42M = 0, 1, 2, 3, 4, 5
+EXPRB42, PEXPRB43, EXPRB53, EPI3, EPI2, EXPRB42M, EXPRB32 = 0, 1, 2, 3, 4, 5, 6
 METHODS = {"exprb42": EXPRB42, "pexprb43": PEXPRB43, "exprb53": EXPRB53, "epi3": EPI3,
-           "epi2": EPI2, "exprb42m": EXPRB42M}
+           "epi2": EPI2, "exprb42m": EXPRB42M, "exprb32": EXPRB32}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)

@@ -177,7 +177,7 @@ int orc_phi_vjp_dense(int n, const double *A, int p, const double *const *v, int
 
 /* ---------------- exponential Rosenbrock schemes ---------------- */
 enum { ORC_EXPRB42 = 0, ORC_PEXPRB43 = 1, ORC_EXPRB53 = 2, ORC_EPI3 = 3, ORC_EPI2 = 4,
-       ORC_EXPRB42M = 5 };
+       ORC_EXPRB42M = 5, ORC_EXPRB32 = 6 };
 
 typedef void (*orc_rhs_fn)(void *ctx, const double *u, double *f);
 typedef void (*orc_jv_fn)(void *ctx, const double *u, const double *v, double *out);

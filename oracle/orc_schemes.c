@@ -25,6 +25,12 @@
  *                        (i)  rho = [3/4, 1], v_1 = v  -> U2 = u_n + W_1, W_2 = phi_1(A) v
  *                        (ii) rho = [1], v_3 = 32/9 dt D2 -> u_{n+1} = u_n + W_2 + W
  *
+ *   exprb32  (a third-order scheme of the form eq. 3.10 with c_2 = 1 and
+ *             b_2 = 2 phi_3, the solution of Table 1's condition 1; not one
+ *             of the paper's schemes, used to check the tableau driver):
+ *                        (i)  rho = [1], v_1 = v          -> U2 = u_n + W
+ *                        (ii) rho = [1], v_3 = 2 dt D2    -> u_{n+1} = U2 + W
+ *
  * D_i = N_n(U_i) - N_n(u_n) = F(U_i) - F(u_n) - J_n (U_i - u_n) (eq. Dni).
  * The rescaling factors of exprb53's U3 convert the rho^l-weighted outputs
  * back to the plain phi_3 terms of eq. 3.13 (coefficient 729/125).
@@ -163,6 +169,20 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         rc = orc_phi_combo(n, jmv, &jc, 4, viii, 1, rho3, wo3, o, &s->m_warm[2], &s->calls[2]);
         if (rc) goto out;
         for (int i = 0; i < n; i++) u[i] = u[i] + W1[i];
+    } else if (method == ORC_EXPRB32) {
+        double rho1[1] = {1.0};
+        const double *vi[2] = {NULL, v};
+        double *wo[1] = {W1};
+        rc = orc_phi_combo(n, jmv, &jc, 1, vi, 1, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
+        if (rc) goto out;
+        for (int i = 0; i < n; i++) U2[i] = u[i] + W1[i];
+        nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
+        for (int i = 0; i < n; i++) a3[i] = 2.0 * dt * D2[i];
+        const double *vii[4] = {NULL, NULL, NULL, a3};
+        double *wo2[1] = {W2};
+        rc = orc_phi_combo(n, jmv, &jc, 3, vii, 1, rho1, wo2, o, &s->m_warm[1], &s->calls[1]);
+        if (rc) goto out;
+        for (int i = 0; i < n; i++) u[i] = U2[i] + W2[i];
     } else if (method == ORC_EPI3 || method == ORC_EPI2) {
         double rho1[1] = {1.0};
         if (method == ORC_EPI3 && s->have_prev) {

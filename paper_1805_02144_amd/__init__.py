@@ -24,11 +24,75 @@ EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", 
            "xrb_diagnostics", "xrb_set_topography", "xrb_autotune",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
-           "xrb_ktv", "xrb_step_vjp"]
+           "xrb_ktv", "xrb_step_vjp", "xrb_step_tableau"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
 _dp = C.POINTER(C.c_double)
+
+
+TAB_CALLS, TAB_OUT, TAB_STAGES = 3, 2, 2
+
+
+class Tableau(C.Structure):
+    """xrb_tableau: a general exponential Rosenbrock scheme as phi-combination
+    calls (see include/exprb.h)."""
+    _fields_ = [("ncalls", C.c_int), ("p", C.c_int * TAB_CALLS), ("ns", C.c_int * TAB_CALLS),
+                ("rho", (C.c_double * TAB_OUT) * TAB_CALLS),
+                ("vc", ((C.c_double * (1 + TAB_STAGES)) * (PMAX + 1)) * TAB_CALLS),
+                ("nstages", C.c_int), ("stage_call", C.c_int * TAB_STAGES),
+                ("uc", ((C.c_double * TAB_OUT) * TAB_CALLS) * TAB_STAGES),
+                ("un1", (C.c_double * TAB_OUT) * TAB_CALLS)]
+
+
+def make_tableau(calls, stages, un1):
+    """Build a Tableau.  calls: list of dicts {"p", "rho": [..], "v": {l: {"v": c, "D2": c,
+    "D3": c}}}; stages: list of (call index, {(c, o): coef}) defining U2, U3; un1: {(c, o): coef}."""
+    T = Tableau()
+    T.ncalls = len(calls)
+    for c, cl in enumerate(calls):
+        T.p[c] = cl["p"]
+        T.ns[c] = len(cl["rho"])
+        for o, r in enumerate(cl["rho"]):
+            T.rho[c][o] = r
+        for l, terms in cl.get("v", {}).items():
+            for name, coef in terms.items():
+                q = {"v": 0, "D2": 1, "D3": 2}[name]
+                T.vc[c][l][q] = coef
+    T.nstages = len(stages)
+    for st, (c, terms) in enumerate(stages):
+        T.stage_call[st] = c
+        for (cc, o), coef in terms.items():
+            T.uc[st][cc][o] = coef
+    for (cc, o), coef in un1.items():
+        T.un1[cc][o] = coef
+    return T
+
+
+# The schemes of Sec. 4.4 (eqs. 3.11-3.13) and the third-order exprb32 in
+# the tableau form; the outputs carry rho^l, so exprb53's U3 rescales its
+# phi_3 terms by (27/25) 2^3 and (729/125) (10/9)^3.
+TABLEAUS = {
+    "exprb42": make_tableau(
+        [{"p": 1, "rho": [0.75], "v": {1: {"v": 1.0}}},
+         {"p": 3, "rho": [1.0], "v": {1: {"v": 1.0}, 3: {"D2": 32.0 / 9.0}}}],
+        [(0, {(0, 0): 1.0})], {(1, 0): 1.0}),
+    "pexprb43": make_tableau(
+        [{"p": 1, "rho": [0.5, 1.0], "v": {1: {"v": 1.0}}},
+         {"p": 4, "rho": [1.0], "v": {3: {"D2": 16.0, "D3": -2.0}, 4: {"D2": -48.0, "D3": 12.0}}}],
+        [(0, {(0, 0): 1.0}), (0, {(0, 1): 1.0})], {(0, 1): 1.0, (1, 0): 1.0}),
+    "exprb53": make_tableau(
+        [{"p": 1, "rho": [0.5, 0.9], "v": {1: {"v": 1.0}}},
+         {"p": 3, "rho": [0.5, 0.9], "v": {3: {"D2": 1.0}}},
+         {"p": 4, "rho": [1.0], "v": {1: {"v": 1.0}, 3: {"D2": 18.0, "D3": -250.0 / 81.0},
+                                      4: {"D2": -60.0, "D3": 500.0 / 27.0}}}],
+        [(0, {(0, 0): 1.0}), (1, {(0, 1): 1.0, (1, 0): 216.0 / 25.0, (1, 1): 8.0})],
+        {(2, 0): 1.0}),
+    "exprb32": make_tableau(
+        [{"p": 1, "rho": [1.0], "v": {1: {"v": 1.0}}},
+         {"p": 3, "rho": [1.0], "v": {3: {"D2": 2.0}}}],
+        [(0, {(0, 0): 1.0})], {(0, 0): 1.0, (1, 0): 1.0}),
+}
 
 
 class Mesh(C.Structure):
@@ -94,6 +158,7 @@ def lib():
                                     C.POINTER(vp), C.POINTER(PhiStats)]
         L.xrb_step.argtypes = [vp, C.c_int, vp, C.c_double]
         L.xrb_step_batch.argtypes = [vp, C.c_int, C.c_int, vp, _dp, C.POINTER(PhiStats)]
+        L.xrb_step_tableau.argtypes = [vp, C.POINTER(Tableau), vp, C.c_double]
         L.xrb_step_stats.argtypes = [vp, C.POINTER(PhiStats)]
         L.xrb_reset_history.argtypes = [vp]
         L.xrb_schedule_mode.argtypes = [vp, C.c_int]
@@ -289,6 +354,17 @@ class Context:
             raise ValueError("u must be a contiguous float64 tensor of length 4N on the device")
         mid = METHODS[method] if isinstance(method, str) else int(method)
         self._check(lib().xrb_step(self.h, mid, _ptr(u), float(dt)))
+        return u
+
+    def step_tableau(self, tab, u, dt):
+        """Advance u (float64 device tensor, in place) by one step of a scheme
+        given as a Tableau (or a name in TABLEAUS)."""
+        self._stream()
+        if not (u.is_contiguous() and u.dtype == self.torch.float64 and u.numel() == self.N
+                and u.device == self.device):
+            raise ValueError("u must be a contiguous float64 tensor of length 4N on the device")
+        T = TABLEAUS[tab] if isinstance(tab, str) else tab
+        self._check(lib().xrb_step_tableau(self.h, C.byref(T), _ptr(u), float(dt)))
         return u
 
     def step_batch(self, method, U, dts, return_stats=False):

@@ -31,7 +31,10 @@ struct SchedEntry {
 
 // stage slots of the scheme drivers
 enum { S_FN, S_V, S_W1, S_W2, S_X1, S_X2, S_U2, S_U3, S_D2, S_D3, S_A3, S_A4, S_T1, S_T2,
-       S_UPREV, S_FPREV, S_STATE, S_COUNT };
+       S_UPREV, S_FPREV, S_STATE,
+       S_G0, S_G1, S_G2, S_G3, S_G4, S_G5,    // tableau steps: outputs W_{c,o} at S_G0 + 2c + o
+       S_Q1, S_Q2, S_Q3, S_Q4,                // tableau steps: inputs v_1..v_4 of a call
+       S_COUNT };
 
 // What the solution of one accepted forward substep is made of (kept for
 // the adjoint): y(t + s) = sum_{j<p} s^j/j! w_j + beta V_{m+1} c(s), with the
@@ -904,6 +907,129 @@ int scheme_step(xrb_ctx *ctx, Work &W, int method, double *u) {
     return XRB_OK;
 }
 
+// A scheme given as a tableau of phi-combination calls (xrb_tableau): the
+// same building blocks as scheme_step, with every vector combination
+// emitted in the order scheme_step uses for the built-in schemes (u_n
+// first, then call outputs by call and output index; v before the stage
+// remainders), so a built-in scheme written as a tableau gives its bits.
+int check_tableau(xrb_ctx *ctx, const xrb_tableau &T) {
+    if (T.ncalls < 1 || T.ncalls > XRB_TAB_CALLS || T.nstages < 0 || T.nstages > XRB_TAB_STAGES)
+        return fail(ctx, XRB_EINVAL, "tableau: call or stage count");
+    for (int c = 0; c < T.ncalls; ++c) {
+        if (T.p[c] < 0 || T.p[c] > kPmax || T.ns[c] < 1 || T.ns[c] > XRB_TAB_OUT)
+            return fail(ctx, XRB_EINVAL, "tableau: p or output count");
+        for (int o = 0; o < T.ns[c]; ++o)
+            if (!(T.rho[c][o] > 0.0) || T.rho[c][o] > 1.0 || (o > 0 && !(T.rho[c][o] > T.rho[c][o - 1])))
+                return fail(ctx, XRB_EINVAL, "tableau: rho must increase within (0, 1]");
+        for (int l = 0; l <= kPmax; ++l)
+            for (int q = 0; q <= XRB_TAB_STAGES; ++q) {
+                const double x = T.vc[c][l][q];
+                if (x != x) return fail(ctx, XRB_EINVAL, "tableau: NaN coefficient");
+                if (x == 0.0) continue;
+                if (l == 0 || l > T.p[c]) return fail(ctx, XRB_EINVAL, "tableau: v_l beyond p (or v_0)");
+                if (q >= 1 && (q > T.nstages || T.stage_call[q - 1] >= c))
+                    return fail(ctx, XRB_EINVAL, "tableau: remainder used before its stage");
+            }
+    }
+    auto terms_ok = [&](const double (*w)[XRB_TAB_OUT], int upto) {
+        int nz = 0;
+        for (int c = 0; c < XRB_TAB_CALLS; ++c)
+            for (int o = 0; o < XRB_TAB_OUT; ++o) {
+                if (w[c][o] != w[c][o]) return false;
+                if (w[c][o] == 0.0) continue;
+                if (c > upto || o >= T.ns[c]) return false;
+                ++nz;
+            }
+        return nz <= 5;
+    };
+    for (int st = 0; st < T.nstages; ++st) {
+        if (T.stage_call[st] < 0 || T.stage_call[st] >= T.ncalls)
+            return fail(ctx, XRB_EINVAL, "tableau: stage_call");
+        if (!terms_ok(T.uc[st], T.stage_call[st]))
+            return fail(ctx, XRB_EINVAL, "tableau: stage terms");
+    }
+    if (!terms_ok(T.un1, T.ncalls - 1)) return fail(ctx, XRB_EINVAL, "tableau: u_{n+1} terms");
+    return XRB_OK;
+}
+
+int tableau_step(xrb_ctx *ctx, Work &W, const xrb_tableau &T, double *u) {
+    const int nm = W.nm;
+    const hipStream_t s = ctx->stream;
+    auto SV = [&](int k) { return stage_vec(ctx, W, k); };
+    double *Fn = SV(S_FN), *v = SV(S_V), *t1 = SV(S_T1), *t2 = SV(S_T2);
+    double *U[XRB_TAB_STAGES] = {SV(S_U2), SV(S_U3)};
+    double *D[XRB_TAB_STAGES] = {SV(S_D2), SV(S_D3)};
+    auto Wout = [&](int c, int o) { return SV(S_G0 + XRB_TAB_OUT * c + o); };
+    for (auto &st : W.stats) st = xrb_phi_stats{};
+    std::vector<xrb_phi_stats> tmp(nm);
+    rhs_plain(ctx, W, u, Fn);
+    lincomb(ctx, W, v, {Fn}, {1.0}, 1u);                      // v = dt F(u_n)
+    launch_linearize(ctx->M, u, W.eta, batch_of(W), s);
+    const Batch b = batch_of(W);
+    // out = u_n + sum of the nonzero output terms
+    auto combine = [&](double *out, const double (*w)[XRB_TAB_OUT]) {
+        const double *vv[6];
+        double cc[6];
+        int k = 0;
+        vv[k] = u;
+        cc[k++] = 1.0;
+        for (int c = 0; c < T.ncalls; ++c)
+            for (int o = 0; o < T.ns[c]; ++o)
+                if (w[c][o] != 0.0) {
+                    vv[k] = Wout(c, o);
+                    cc[k++] = w[c][o];
+                }
+        timed(ctx, XRB_K_VEC, [&] { launch_lincomb(ctx->n4, out, k, vv, cc, 0u, b, s); });
+    };
+    for (int c = 0; c < T.ncalls; ++c) {
+        const int p = T.p[c];
+        const double *vin[kPmax + 1] = {};
+        for (int l = 1; l <= p; ++l) {
+            const double *vv[1 + XRB_TAB_STAGES];
+            double cc[1 + XRB_TAB_STAGES];
+            unsigned mask = 0;
+            int k = 0;
+            if (T.vc[c][l][0] != 0.0) {
+                vv[k] = v;
+                cc[k++] = T.vc[c][l][0];
+            }
+            for (int st = 0; st < T.nstages; ++st)
+                if (T.vc[c][l][1 + st] != 0.0) {
+                    mask |= 1u << k;
+                    vv[k] = D[st];
+                    cc[k++] = T.vc[c][l][1 + st];
+                }
+            if (k == 0) continue;                            // v_l = 0
+            if (k == 1 && vv[0] == v && cc[0] == 1.0) {      // v_l = v itself
+                vin[l] = v;
+                continue;
+            }
+            double *q = SV(S_Q1 + l - 1);
+            timed(ctx, XRB_K_VEC, [&] { launch_lincomb(ctx->n4, q, k, vv, cc, mask, b, s); });
+            vin[l] = q;
+        }
+        double *wo[XRB_TAB_OUT];
+        for (int o = 0; o < T.ns[c]; ++o) wo[o] = Wout(c, o);
+        int rc = phi_batch(ctx, W, u, p, vin, T.ns[c], T.rho[c], wo, c, tmp.data());
+        if (rc) return rc;
+        for (int k = 0; k < nm; ++k) W.stats[3 * k + c] = tmp[k];
+        for (int st = 0; st < T.nstages; ++st) {
+            if (T.stage_call[st] != c) continue;
+            combine(U[st], T.uc[st]);
+            // D = F(U) - Fn - J_n (U - u_n)
+            lincomb(ctx, W, t1, {U[st], u}, {1.0, -1.0});
+            jv_plain(ctx, W, u, t1, t2, false);
+            rhs_plain(ctx, W, U[st], D[st]);
+            lincomb(ctx, W, D[st], {D[st], Fn, t2}, {1.0, -1.0, -1.0});
+        }
+    }
+    combine(u, T.un1);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    prof_drain(ctx);
+    return XRB_OK;
+}
+
 int set_dt(xrb_ctx *ctx, Work &W, const double *dt) {
     for (int k = 0; k < W.nm; ++k) {
         if (!(dt[k] > 0.0) && !(dt[k] < 0.0))
@@ -1674,6 +1800,21 @@ xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt) {
     if (rc) return (xrb_status)rc;
     double *uc = io_in(ctx, 0, u);
     rc = scheme_step(ctx, ctx->one, (int)method, uc);
+    if (rc) return (xrb_status)rc;
+    io_out(ctx, 0, u);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+xrb_status xrb_step_tableau(xrb_ctx *ctx, const xrb_tableau *tab, double *u, double dt) {
+    if (!ctx || !tab || !u || !(dt > 0.0))
+        return (xrb_status)fail(ctx, XRB_EINVAL, "step_tableau: bad argument");
+    int rc = check_tableau(ctx, *tab);
+    if (!rc) rc = set_dt(ctx, ctx->one, &dt);
+    if (!rc) rc = io_ensure(ctx);
+    if (rc) return (xrb_status)rc;
+    double *uc = io_in(ctx, 0, u);
+    rc = tableau_step(ctx, ctx->one, *tab, uc);
     if (rc) return (xrb_status)rc;
     io_out(ctx, 0, u);
     HIPCHK(hipGetLastError());

@@ -65,3 +65,29 @@ def test_binding_loads_torch_before_the_library():
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
+
+
+def test_tableau_layout_matches_the_header():
+    """The binding's Tableau has the size and field offsets of the C struct
+    xrb_tableau (compiled from include/exprb.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    import tempfile
+    import paper_1805_02144_amd as X
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = [f[0] for f in X.Tableau._fields_]
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "exprb.h"\nint main(void){\n'
+           'printf("%zu", sizeof(xrb_tableau));\n' +
+           "".join('printf(" %%zu", offsetof(xrb_tableau, %s));\n' % f for f in fields) +
+           "return 0;}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    got = [int(x) for x in out]
+    assert got[0] == ctypes.sizeof(X.Tableau)
+    assert got[1:] == [getattr(X.Tableau, f).offset for f in fields]

@@ -86,7 +86,7 @@ def order_conditions(sch):
     return res
 
 
-@pytest.mark.parametrize("name", ["exprb42", "pexprb43", "exprb53"])
+@pytest.mark.parametrize("name", ["exprb42", "pexprb43", "exprb53", "exprb32"])
 def test_stiff_order_conditions(name):
     sch = json.load(open(GOLD))[name]
     res = order_conditions(sch)
@@ -121,7 +121,8 @@ def _ode():
     return n, f, jac, u0
 
 
-NOMINAL = {"epi2": 2, "epi3": 3, "exprb42": 4, "pexprb43": 4, "exprb53": 5, "exprb42m": 4}
+NOMINAL = {"epi2": 2, "epi3": 3, "exprb42": 4, "pexprb43": 4, "exprb53": 5, "exprb42m": 4,
+           "exprb32": 3}
 
 
 @pytest.mark.parametrize("method", list(NOMINAL))

@@ -128,6 +128,14 @@ __device__ inline double wave_max_all(double a) {
     return fmax(fmax(read_lane(a, 0), read_lane(a, 16)), fmax(read_lane(a, 32), read_lane(a, 48)));
 }
 
+// 1/d from the hardware reciprocal refined by one Newton step (the pivot
+// reciprocal sits on the elimination's critical path; a division there costs
+// several dependent operations more)
+__device__ inline double recip(double d) {
+    const double r = __builtin_amdgcn_rcp(d);
+    return fma(r, fma(-d, r, 1.0), r);
+}
+
 // X = M^{-1} R for K x K matrices M and R in LDS (row stride kLd, K <= KC),
 // by Gauss-Jordan elimination with partial pivoting: for each column the
 // pivot is the first not yet used row of largest |M(r, col)|, and that
@@ -173,7 +181,7 @@ __device__ inline void gauss_jordan(double *Mt, double *R, double *X, int K, int
         const double mx = wave_max_all(a);
         const int piv = __ffsll((long long)__ballot(a == mx)) - 1;
         used |= 1ull << piv;
-        const double dinv = 1.0 / read_lane(vs, piv);
+        const double dinv = recip(read_lane(vs, piv));
         if (tid == 0) {
             piv_of[col] = piv;
             dinv_of[col] = dinv;
@@ -425,83 +433,111 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
         const double beta = c->beta;
         for (int k = tid; k < meff; k += blockDim.x) c->ycoef[p + k] = beta * c->sigma[k] * X[k * kLd + cmain];
     }
-    if (tid == 0) {
+    // The scalar controller (steps 3-6) runs on the first wave: every lane
+    // evaluates omega and the history update alike, then lane 1 the new
+    // substep (and its cost), lane 2 the new Krylov size (and its cost),
+    // lanes 3 and 4 the combination and recurrence coefficients, side by side;
+    // lane 0 takes the decision and writes the record.  Each quantity is the
+    // same expression one thread evaluated before, so the bits are unchanged.
+    if (tid < 64) {
 #pragma clang fp contract(off)
+        const int lane = tid;
         int status = sh_status;
         int accept;
         double omega = 0.0;
         const double beta = c->beta;
+        const double t_cur = c->t, t_out = c->t_out;
         if (meff == 0) {
             accept = 1;   // w_p = 0: the substep is exact
         } else {
             const double eps = beta * sh_hsub * fabs(X[(meff - 1) * kLd + meff + p]);
-            omega = c->t_out * eps / (tau_u * c->tol_abs);
+            omega = t_out * eps / (tau_u * c->tol_abs);
             if (omega != omega) status = XRB_ENAN;
             accept = (a.mode == XRB_REPLAY) ? (a.rep.flags & 1) : (omega <= a.delta);
         }
         int m_next = m;
         if (a.mode != XRB_REPLAY && meff > 0) {
             // order / error-ratio estimates from the previous rejected attempt
+            double q = c->q, kappa = c->kappa;
             if (c->have_prev && omega > 0.0 && c->prev_omega > 0.0) {
                 if (m == c->prev_m && tau_u != c->prev_tau) {
                     const double qq = log(omega / c->prev_omega) / log(tau_u / c->prev_tau);
-                    c->q = qq > 1.0 ? qq : 1.0;
+                    q = qq > 1.0 ? qq : 1.0;
                 } else if (tau_u == c->prev_tau && m != c->prev_m) {
                     const double kk = pow(omega / c->prev_omega, 1.0 / (double)(c->prev_m - m));
-                    c->kappa = kk > 1.1 ? kk : 1.1;
+                    kappa = kk > 1.1 ? kk : 1.1;
                 }
             }
-            double tau_new, mnew;
-            if (omega > 0.0) {
-                tau_new = tau_u * pow(a.gamma / omega, 1.0 / c->q);
-                mnew = (double)m + ceil(log(omega / a.gamma) / log(c->kappa));
-            } else {
-                tau_new = 2.0 * tau_u;
-                mnew = -1e300;
+            double tau_new = 0.0, c_tau = 0.0, c_m = 0.0;
+            int m_new = m;
+            if (lane == 1) {
+                if (omega > 0.0) tau_new = tau_u * pow(a.gamma / omega, 1.0 / q);
+                else tau_new = 2.0 * tau_u;
+                if (tau_new > 2.0 * tau_u) tau_new = 2.0 * tau_u;
+                if (tau_new < tau_u / 5.0) tau_new = tau_u / 5.0;
+                tau_new = quantise_2sig(tau_new);
+                c_tau = work_estimate(tau_new, m, p, t_cur, t_out, a.n4, sh_norm, tau_u);
+            } else if (lane == 2) {
+                double mnew;
+                if (omega > 0.0) mnew = (double)m + ceil(log(omega / a.gamma) / log(kappa));
+                else mnew = -1e300;
+                int lo = (3 * m + 3) / 4;
+                if (lo < 1) lo = 1;
+                int hi = (4 * m) / 3 + 1;
+                if (hi > a.m_max) hi = a.m_max;
+                if (mnew < lo) mnew = lo;
+                if (mnew > hi) mnew = hi;
+                m_new = (int)mnew;
+                c_m = work_estimate(tau_u, m_new, p, t_cur, t_out, a.n4, sh_norm, tau_u);
             }
-            if (tau_new > 2.0 * tau_u) tau_new = 2.0 * tau_u;
-            if (tau_new < tau_u / 5.0) tau_new = tau_u / 5.0;
-            tau_new = quantise_2sig(tau_new);
-            int lo = (3 * m + 3) / 4;
-            if (lo < 1) lo = 1;
-            int hi = (4 * m) / 3 + 1;
-            if (hi > a.m_max) hi = a.m_max;
-            if (mnew < lo) mnew = lo;
-            if (mnew > hi) mnew = hi;
-            const int m_new = (int)mnew;
-            const double c_tau = work_estimate(tau_new, m, p, c->t, c->t_out, a.n4, sh_norm, tau_u);
-            const double c_m = work_estimate(tau_u, m_new, p, c->t, c->t_out, a.n4, sh_norm, tau_u);
+            tau_new = read_lane(tau_new, 1);
+            c_tau = read_lane(c_tau, 1);
+            m_new = __builtin_amdgcn_readlane(m_new, 2);
+            c_m = read_lane(c_m, 2);
             int change_tau = c_tau < c_m;
             if (!accept && !change_tau && m_new == m) change_tau = 1;
-            if (change_tau) c->tau = tau_new;
-            else m_next = m_new;
-        }
-        c->m = m_next;
-        // combine coefficients: tau^j/j! w_j, beta sigma_k X(k, m+p-1), correction
-        double fac = 1.0;
-        for (int j = 0; j < p; ++j) {
-            if (j > 0) fac = fac * tau_u / j;
-            c->ycoef[j] = fac;
-        }
-        if (meff > 0)
-            c->ycoef[p + meff] = beta * sh_hsub * c->sigma[meff] * X[(meff - 1) * kLd + meff + p];
-        double t_new = c->t;
-        if (accept) {
-            t_new = sh_lands ? c->t_out : c->t + tau_u;
-            c->t = t_new;
-            c->have_prev = 0;
-            double f2 = 1.0;
-            c->rec_coef[0] = 1.0;
-            for (int l = 1; l <= kPmax; ++l) {
-                f2 = f2 * t_new / l;
-                c->rec_coef[l] = f2;
+            if (change_tau) {
+                if (lane == 0) c->tau = tau_new;
+            } else {
+                m_next = m_new;
             }
-        } else {
+            if (lane == 0) {
+                c->q = q;
+                c->kappa = kappa;
+            }
+        }
+        if (lane == 0) c->m = m_next;
+        // combine coefficients: tau^j/j! w_j, beta sigma_k X(k, m+p-1), correction
+        if (lane == 3) {
+            double fac = 1.0;
+            for (int j = 0; j < p; ++j) {
+                if (j > 0) fac = fac * tau_u / j;
+                c->ycoef[j] = fac;
+            }
+            if (meff > 0)
+                c->ycoef[p + meff] = beta * sh_hsub * c->sigma[meff] * X[(meff - 1) * kLd + meff + p];
+        }
+        const double t_new = accept ? (sh_lands ? t_out : t_cur + tau_u) : t_cur;
+        if (accept) {
+            if (lane == 4) {
+                double f2 = 1.0;
+                c->rec_coef[0] = 1.0;
+                for (int l = 1; l <= kPmax; ++l) {
+                    f2 = f2 * t_new / l;
+                    c->rec_coef[l] = f2;
+                }
+            }
+            if (lane == 0) {
+                c->t = t_new;
+                c->have_prev = 0;
+            }
+        } else if (lane == 0) {
             c->have_prev = 1;
             c->prev_omega = omega;
             c->prev_tau = tau_u;
             c->prev_m = m;
         }
+        if (lane != 0) return;
         Decision d;
         d.tau_u = tau_u;
         d.omega = omega;

@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(256) k_rhs(DevMesh M, const double *__restrict
 template <int EPI>
 constexpr int kJvMaxBlock = EPI == kEpiIom2 ? 1024 : 256;
 
-template <int EPI, int L, bool FL>
+template <int EPI, int L, bool FL, bool CR>
 __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Batch bt) {
     __shared__ double lds[64];
     __shared__ double cterm[2 * kCellRedMax];   // per-cell reduction terms
@@ -223,8 +223,11 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
     const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
     // small grids reduce per-cell terms (fixed order, any block size);
     // large ones accumulate per lane (block size fixed by n)
-    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-    const bool cellred = EPI != kEpiNone && per <= kCellRedMax;
+    // CR: the launch's chunks hold at most kCellRedMax cells (the launcher
+    // decides from red_cells(n)); such launches run one pass per block, where
+    // requesting the epilogue's own-cell operands with the gathers pays, while
+    // the multi-pass launches of large grids keep their registers for the loop
+    constexpr bool cellred = EPI != kEpiNone && CR;
     const int q = threadIdx.x & (L - 1);
     double cax[kPmax];
     const double *axv[kPmax];
@@ -252,6 +255,18 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
         const double ux = ui[0], uy = ui[1], uz = ui[2], uh = ui[3];
         const double xx = xi[0], xy = xi[1], xz = xi[2], xh = xi[3];
         const Cell ci = load_cell(M.cen, i);
+        // one-pass launches request the cell's own epilogue operands with
+        // the gathers, not after them
+        double eta = 0.0;
+        double pm[kCompIter<L>];
+        if constexpr (cellred) {
+            eta = etak[i];
+#pragma unroll
+            for (int kc = 0; kc < kCompIter<L>; ++kc) {
+                const int b = comp_of<L>(q, kc);
+                pm[kc] = (EPI == kEpiIom2 && rjm1 && b >= 0) ? rjm1[4 * i + b] : 0.0;
+            }
+        }
         const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
         const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
@@ -333,7 +348,7 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
-        const double eta = etak[i];
+        if constexpr (!cellred) eta = etak[i];
         // J_v x: -(V.x) (n x u);  J_r x: -eta (n x x) - nu L^2 x;
         // J_m x: -G(u.x + g x_h), -D(h x + x_h u)
         const double pux = ny * uz - nz * uy, puy = nz * ux - nx * uz, puz = nx * uy - ny * ux;
@@ -357,7 +372,7 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
             outk[oi] = ob;
             if (EPI == kEpiIom2) {
                 c0 = acc_add(c0, ob * xs[b]);
-                if (rjm1) c1 = acc_add(c1, ob * rjm1[oi]);
+                if (rjm1) c1 = acc_add(c1, ob * (cellred ? pm[kc] : rjm1[oi]));
             } else if (EPI == kEpiNorm) {
                 c0 = acc_add(c0, ob * ob);
             }
@@ -461,16 +476,22 @@ __global__ void __launch_bounds__(256) k_diag_sum(const double *__restrict__ par
 template <int L, bool FL>
 void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
     if (epi == kEpiNone) {
-        hipLaunchKernelGGL((k_jv<kEpiNone, L, FL>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256),
+        hipLaunchKernelGGL((k_jv<kEpiNone, L, FL, false>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256),
                            0, s, M, a, b);
         return;
     }
     const int grid = red_parts(M.n), block = red_block(M.n, b.nm, L);
     if (epi == kEpiIom2) {
-        hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+        if (red_cells(M.n) <= kCellRedMax)
+            hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL, true>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
+        else
+            hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL, false>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
     } else {
         const int nb = block < kJvMaxBlock<kEpiNorm> ? block : kJvMaxBlock<kEpiNorm>;
-        hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
+        if (red_cells(M.n) <= kCellRedMax)
+            hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL, true>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
+        else
+            hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL, false>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
     }
 }
 

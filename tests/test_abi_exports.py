@@ -91,3 +91,40 @@ def test_tableau_layout_matches_the_header():
     got = [int(x) for x in out]
     assert got[0] == ctypes.sizeof(X.Tableau)
     assert got[1:] == [getattr(X.Tableau, f).offset for f in fields]
+
+
+def test_scheme_tableaus_follow_the_printed_coefficients():
+    """The binding's tableau encodings of exprb42, pexprb43 and exprb53 carry
+    the coefficients of eqs. 3.11-3.13 (tests/golden): stage times c_i as the
+    first call's output times, b_i(Z) = sum_k beta_ik phi_k(Z) as the last
+    call's v_k weights of D_i, and exprb53's a_32 phi_3(c Z) terms as stage
+    weights divided by c^3 (the outputs carry rho^l = c^3 on v_3)."""
+    import json
+    from fractions import Fraction as Fr
+    import paper_1805_02144_amd as X
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "exprb_coefficients.json")))
+    for name in ("exprb42", "pexprb43", "exprb53", "exprb32"):
+        T, g = X.TABLEAUS[name], gold[name]
+        # internal stage times: the outputs the stages take, U_i = u_n + W(c_i)
+        cs = sorted(Fr(v) for v in g["c"].values())
+        first = [T.rho[0][o] for o in range(T.ns[0])]
+        for c in cs:
+            if c < 1:
+                assert any(abs(float(c) - r) < 1e-15 for r in first), (name, c)
+        # final weights: b_i's phi_k coefficient times D_i in v_k of the last call
+        last = T.ncalls - 1
+        for i, terms in g["b"].items():
+            stage = int(i) - 2
+            for k, coef in terms.items():
+                k = int(k)
+                assert abs(T.vc[last][k][1 + stage] - float(Fr(coef))) < 1e-12, (name, i, k)
+        # exprb53: a_32 = 27/25 phi_3(Z/2) + 729/125 phi_3(9Z/10) through the
+        # rho^3-weighted outputs of the second call (rho = 1/2, 9/10)
+        for key, terms in g["a"].items():
+            st = int(key.split(",")[0]) - 2
+            for kc, coef in terms.items():
+                k, c = kc.split("@")
+                c = Fr(c)
+                o = [T.rho[1][q] for q in range(T.ns[1])].index(float(c))
+                want = Fr(coef) / c ** int(k)
+                assert abs(T.uc[st][1][o] - float(want)) < 1e-12, (name, key, kc)

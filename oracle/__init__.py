@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "liboracle.so")
+# ORC_LIBPATH selects another build of the same sources (the sanitizer
+# build of the CPU test job); the default is the plain one.
+_LIBPATH = os.environ.get("ORC_LIBPATH") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 FREE, RECORD, REPLAY = 0, 1, 2
@@ -114,8 +116,29 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(Problem), C.c_int, _dp, C.c_double,
                                C.POINTER(StepState), C.POINTER(PhiOpts)]
         L.orc_swe_problem.argtypes = [C.POINTER(Swe), C.POINTER(Problem)]
+        L.orc_phi_cost.argtypes = [C.c_double, C.c_int, C.c_int, C.c_double, C.c_double,
+                                   C.c_double]
+        L.orc_phi_cost.restype = C.c_double
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's independent cell loops (results do not depend
+    on the count: every sum keeps its serial order)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads():
+    return lib().orc_get_threads()
+
+
+def phi_cost(tau, m, p, remaining, n, hnorm):
+    """eq. cost: the controller's work estimate C(tau, m) (Sec. 4.3)."""
+    return lib().orc_phi_cost(float(tau), int(m), int(p), float(remaining), float(n),
+                              float(hnorm))
 
 
 def _ptr(a):

@@ -1,5 +1,6 @@
 """Compile the CPU oracle into oracle/liboracle.so (plain gcc, -O2, no
-fast-math, no OpenMP).  Test infrastructure only."""
+fast-math; OpenMP only for the independent cell loops, one thread unless
+orc_set_threads asks for more).  Test infrastructure only."""
 import os
 import subprocess
 import sys
@@ -10,8 +11,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose=False):
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
-           "-o", LIB] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-Wall",
+           "-Wno-unused-function", "-o", LIB] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

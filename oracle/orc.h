@@ -143,6 +143,18 @@ typedef struct {
 
 void orc_phi_default_opts(orc_phi_opts *o);
 
+/* eq. cost (Sec. 4.3): estimated work of reaching the output time from t
+ * with substeps tau and Krylov size m; remaining = t_out - t, n = problem
+ * size, hnorm = ||tau Hhat||_1 of the augmented matrix at this tau.  The
+ * controller changes tau iff C(tau_new, m) < C(tau, m_new). */
+double orc_phi_cost(double tau, int m, int p, double remaining, double n, double hnorm);
+
+/* Threads of the oracle's cell loops (OpenMP; default 1).  Only loops whose
+ * iterations write disjoint outputs run in parallel; every sum keeps its
+ * serial order, so results are bitwise the same for any thread count. */
+void orc_set_threads(int nthreads);
+int  orc_get_threads(void);
+
 /* W_i = sum_l rho_i^l phi_l(rho_i A) v_l, i = 1..ns.  v[l] == NULL means the
  * zero vector.  *m_warm: in = starting Krylov size (<= 0: opts->m_init),
  * out = Krylov size of the last accepted attempt. */

@@ -45,6 +45,7 @@
  * The HIP library implements the same readings in code of its own.
  */
 #include "orc.h"
+#include "orc_par.h"
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -132,16 +133,20 @@ static double quantise2(double x)
     return floor(x / unit) * unit;
 }
 
-/* eq. cost: estimated work to reach t_out from t with substeps tau, size m */
-static double cost(double tau, int m, int p, double t, double t_out, double n, double normH, double tau_ref)
+/* eq. cost: the estimated work C(tau, m) of reaching the output time with
+ * substeps tau and Krylov size m, remaining = t_out - t, hnorm = ||tau Hhat||_1:
+ *   max(1, nint(remaining / tau)) m (n + n_A) + 2 (p - 1)(n_A + n)
+ *     + M (m + p + 1)^3 + (2p + 1) n,
+ *   M = 44/3 + 2 max(0, nint(log2(hnorm / 5.37))),  n_A = 40 n,
+ * nint rounding half away from zero (C's round). */
+double orc_phi_cost(double tau, int m, int p, double remaining, double n, double hnorm)
 {
     double nA = 40.0 * n;
-    double ks = round((t_out - t) / tau);
+    double ks = round(remaining / tau);
     if (ks < 1.0) ks = 1.0;
     double M = 44.0 / 3.0;
-    double hn = normH * tau / tau_ref;
-    if (hn > 0.0) {
-        double r = round(log2(hn / 5.37));
+    if (hnorm > 0.0) {
+        double r = round(log2(hnorm / 5.37));
         if (r > 0.0) M += 2.0 * r;
     }
     double K = (double)(m + p + 1);
@@ -263,6 +268,7 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                     for (int l = 0; l <= p - j; l++) {
                         if (l > 0) fac = fac * t / l;
                         if (!v[j + l] || (l > 0 && t == 0.0)) continue;
+                        ORC_PARFOR
                         for (int k = 0; k < n; k++) wj[k] += fac * v[j + l][k];
                         z = 0;
                     }
@@ -274,6 +280,7 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                 m_break = 0;
                 if (beta > 0.0) {
                     const double *wp = wv + (size_t)p * n;
+                    ORC_PARFOR
                     for (int k = 0; k < n; k++) V[k] = wp[k] / beta;
                 }
                 point_ready = 1;
@@ -296,9 +303,12 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                      * against the unmodified A v_j */
                     double hjj = dotp(n, w, V + (size_t)j * n);
                     double hmj = j > 0 ? dotp(n, w, V + (size_t)(j - 1) * n) : 0.0;
+                    ORC_PARFOR
                     for (int k = 0; k < n; k++) w[k] -= hjj * V[(size_t)j * n + k];
-                    if (j > 0)
+                    if (j > 0) {
+                        ORC_PARFOR
                         for (int k = 0; k < n; k++) w[k] -= hmj * V[(size_t)(j - 1) * n + k];
+                    }
                     H[j * mmax + j] = hjj;
                     if (j > 0) H[(j - 1) * mmax + j] = hmj;
                     double hn = nrm2(n, w);
@@ -316,6 +326,7 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                         m_break = j + 1;
                     } else {
                         H[(j + 1) * mmax + j] = hn;
+                        ORC_PARFOR
                         for (int k = 0; k < n; k++) w[k] /= hn;
                     }
                     built++;
@@ -386,8 +397,11 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                     if (mnew_d < lo) mnew_d = lo;
                     if (mnew_d > hi) mnew_d = hi;
                     int m_new = (int)mnew_d;
-                    double c_tau = cost(tau_new, m_att, p, t, t_out, (double)n, normH, tau_u);
-                    double c_m = cost(tau_u, m_new, p, t, t_out, (double)n, normH, tau_u);
+                    /* ||tau Hhat||_1 scales linearly with tau */
+                    double c_tau = orc_phi_cost(tau_new, m_att, p, t_out - t, (double)n,
+                                                normH * tau_new / tau_u);
+                    double c_m = orc_phi_cost(tau_u, m_new, p, t_out - t, (double)n,
+                                              normH * tau_u / tau_u);
                     int change_tau = c_tau < c_m;
                     /* a rejected attempt must change something */
                     if (!accept && !change_tau && m_new == m_att) change_tau = 1;
@@ -407,6 +421,7 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                     if (j > 0) fac = fac * tau_u / j;
                     if (wzero[j]) continue;
                     const double *wj = wv + (size_t)j * n;
+                    ORC_PARFOR
                     for (int k = 0; k < n; k++) yn[k] += fac * wj[k];
                 }
                 if (beta > 0.0) {
@@ -415,12 +430,14 @@ int orc_phi_combo(int n, orc_matvec_fn A, void *actx, int p, const double *const
                     for (int c = 0; c < meff; c++) {
                         double a = beta * X[c * K + cmain];
                         const double *vc = V + (size_t)c * n;
+                        ORC_PARFOR
                         for (int k = 0; k < n; k++) yn[k] += a * vc[k];
                     }
                     double hsub = (m_break && meff == m_break) ? 0.0 : H[meff * mmax + meff - 1];
                     double a = beta * hsub * X[(meff - 1) * K + meff + p];
                     if (a != 0.0) {
                         const double *vc = V + (size_t)meff * n;
+                        ORC_PARFOR
                         for (int k = 0; k < n; k++) yn[k] += a * vc[k];
                     }
                 }

@@ -36,6 +36,7 @@
  * back to the plain phi_3 terms of eq. 3.13 (coefficient 729/125).
  */
 #include "orc.h"
+#include "orc_par.h"
 #include <stdlib.h>
 #include <string.h>
 
@@ -46,6 +47,7 @@ static void jmv(void *ctx, const double *x, double *y)
     const jmv_ctx *c = ctx;
     c->pb->jv(c->pb->ctx, c->u, x, y);
     int n = c->pb->n;
+    ORC_PARFOR
     for (int i = 0; i < n; i++) y[i] *= c->dt;
 }
 
@@ -70,8 +72,10 @@ static void nonlin_diff(const orc_problem *pb, const double *un, const double *F
 {
     int n = pb->n;
     pb->rhs(pb->ctx, U, D);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) t1[i] = U[i] - un[i];
     pb->jv(pb->ctx, un, t1, t2);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) D[i] = D[i] - Fn[i] - t2[i];
 }
 
@@ -92,6 +96,7 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
 
     jmv_ctx jc = {pb, u, dt};
     pb->rhs(pb->ctx, u, Fn);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) v[i] = dt * Fn[i];
 
     if (method == ORC_EXPRB42) {
@@ -100,13 +105,16 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo[1] = {W1};
         rc = orc_phi_combo(n, jmv, &jc, 1, vi, 1, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) U2[i] = u[i] + W1[i];
         nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) a3[i] = 32.0 / 9.0 * dt * D2[i];
         const double *vii[4] = {NULL, v, NULL, a3};
         double *wo2[1] = {W2};
         rc = orc_phi_combo(n, jmv, &jc, 3, vii, 1, rho2, wo2, o, &s->m_warm[1], &s->calls[1]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) u[i] = u[i] + W2[i];
     } else if (method == ORC_EXPRB42M) {
         double rho1[2] = {0.75, 1.0}, rho2[1] = {1.0};
@@ -114,13 +122,16 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo[2] = {W1, X1};
         rc = orc_phi_combo(n, jmv, &jc, 1, vi, 2, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) U2[i] = u[i] + W1[i];
         nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) a3[i] = 32.0 / 9.0 * dt * D2[i];
         const double *vii[4] = {NULL, NULL, NULL, a3};
         double *wo2[1] = {W2};
         rc = orc_phi_combo(n, jmv, &jc, 3, vii, 1, rho2, wo2, o, &s->m_warm[1], &s->calls[1]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) u[i] = u[i] + X1[i] + W2[i];
     } else if (method == ORC_PEXPRB43) {
         double rho1[2] = {0.5, 1.0}, rho2[1] = {1.0};
@@ -128,12 +139,14 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo[2] = {W1, W2};
         rc = orc_phi_combo(n, jmv, &jc, 1, vi, 2, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) {
             U2[i] = u[i] + W1[i];
             U3[i] = u[i] + W2[i];
         }
         nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
         nonlin_diff(pb, u, Fn, U3, D3, t1, t2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) {
             a3[i] = dt * (16.0 * D2[i] - 2.0 * D3[i]);
             a4[i] = dt * (-48.0 * D2[i] + 12.0 * D3[i]);
@@ -142,6 +155,7 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo2[1] = {X1};
         rc = orc_phi_combo(n, jmv, &jc, 4, vii, 1, rho2, wo2, o, &s->m_warm[1], &s->calls[1]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) u[i] = U3[i] + X1[i];
     } else if (method == ORC_EXPRB53) {
         double rho1[2] = {0.5, 0.9}, rho3[1] = {1.0};
@@ -149,8 +163,10 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo[2] = {W1, W2};
         rc = orc_phi_combo(n, jmv, &jc, 1, vi, 2, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) U2[i] = u[i] + W1[i];
         nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) a3[i] = dt * D2[i];
         const double *vii[4] = {NULL, NULL, NULL, a3};
         double *wo2[2] = {X1, X2};
@@ -158,8 +174,10 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         if (rc) goto out;
         /* 27/25 phi_3(Z/2) D2 = 27/25 * 2^3 * W(ii)_1 ; 729/125 phi_3(9Z/10) D2 =
          * 729/125 * (10/9)^3 * W(ii)_2 = 8 W(ii)_2 */
+        ORC_PARFOR
         for (int i = 0; i < n; i++) U3[i] = u[i] + W2[i] + 216.0 / 25.0 * X1[i] + 8.0 * X2[i];
         nonlin_diff(pb, u, Fn, U3, D3, t1, t2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) {
             a3[i] = dt * (18.0 * D2[i] - 250.0 / 81.0 * D3[i]);
             a4[i] = dt * (-60.0 * D2[i] + 500.0 / 27.0 * D3[i]);
@@ -168,6 +186,7 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo3[1] = {W1};
         rc = orc_phi_combo(n, jmv, &jc, 4, viii, 1, rho3, wo3, o, &s->m_warm[2], &s->calls[2]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) u[i] = u[i] + W1[i];
     } else if (method == ORC_EXPRB32) {
         double rho1[1] = {1.0};
@@ -175,20 +194,25 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         double *wo[1] = {W1};
         rc = orc_phi_combo(n, jmv, &jc, 1, vi, 1, rho1, wo, o, &s->m_warm[0], &s->calls[0]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) U2[i] = u[i] + W1[i];
         nonlin_diff(pb, u, Fn, U2, D2, t1, t2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) a3[i] = 2.0 * dt * D2[i];
         const double *vii[4] = {NULL, NULL, NULL, a3};
         double *wo2[1] = {W2};
         rc = orc_phi_combo(n, jmv, &jc, 3, vii, 1, rho1, wo2, o, &s->m_warm[1], &s->calls[1]);
         if (rc) goto out;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) u[i] = U2[i] + W2[i];
     } else if (method == ORC_EPI3 || method == ORC_EPI2) {
         double rho1[1] = {1.0};
         if (method == ORC_EPI3 && s->have_prev) {
             /* R_{n-1} = F(u_{n-1}) - F(u_n) - J_n (u_{n-1} - u_n) */
+            ORC_PARFOR
             for (int i = 0; i < n; i++) t1[i] = s->u_prev[i] - u[i];
             pb->jv(pb->ctx, u, t1, t2);
+            ORC_PARFOR
             for (int i = 0; i < n; i++) a3[i] = 2.0 / 3.0 * dt * (s->f_prev[i] - Fn[i] - t2[i]);
             const double *vi[3] = {NULL, v, a3};
             double *wo[1] = {W1};
@@ -202,6 +226,7 @@ int orc_step(const orc_problem *pb, int method, double *u, double dt, orc_step_s
         memcpy(s->u_prev, u, sizeof(double) * n);
         memcpy(s->f_prev, Fn, sizeof(double) * n);
         s->have_prev = 1;
+        ORC_PARFOR
         for (int i = 0; i < n; i++) u[i] = u[i] + W1[i];
     } else {
         rc = ORC_EINVAL;

@@ -18,9 +18,15 @@
  * t_{e,i} = rhat_e x n_{e,i}.
  */
 #include "orc.h"
+#include "orc_par.h"
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+int orc_threads = 1;
+
+void orc_set_threads(int nthreads) { orc_threads = nthreads > 1 ? nthreads : 1; }
+int orc_get_threads(void) { return orc_threads; }
 
 static void cross3(const double *a, const double *b, double *c)
 {
@@ -79,6 +85,7 @@ int orc_swe_init(orc_swe *m, int n, const double *xyz, const int *deg, const int
     memcpy(m->deg, deg, sizeof(int) * n);
     memcpy(m->nbr, nbr, sizeof(int) * 6 * n);
 
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *xi = xyz + 3 * i;
         int d = deg[i];
@@ -123,6 +130,7 @@ void orc_swe_free(orc_swe *m)
 /* ------------------------------------------------------------------ */
 void orc_div(const orc_swe *m, const double *fx, const double *fy, const double *fz, double *out)
 {
+    ORC_PARFOR
     for (int i = 0; i < m->n; i++) {
         double acc = 0.0;
         for (int s = 0; s < m->deg[i]; s++) {
@@ -137,6 +145,7 @@ void orc_div(const orc_swe *m, const double *fx, const double *fy, const double 
 
 void orc_grad(const orc_swe *m, const double *psi, double *gx, double *gy, double *gz)
 {
+    ORC_PARFOR
     for (int i = 0; i < m->n; i++) {
         double g[3] = {0.0, 0.0, 0.0};
         for (int s = 0; s < m->deg[i]; s++) {
@@ -156,6 +165,7 @@ void orc_grad(const orc_swe *m, const double *psi, double *gx, double *gy, doubl
 
 void orc_curl(const orc_swe *m, const double *ux, const double *uy, const double *uz, double *out)
 {
+    ORC_PARFOR
     for (int i = 0; i < m->n; i++) {
         double acc = 0.0;
         for (int s = 0; s < m->deg[i]; s++) {
@@ -170,6 +180,7 @@ void orc_curl(const orc_swe *m, const double *ux, const double *uy, const double
 
 void orc_lap(const orc_swe *m, const double *psi, double *out)
 {
+    ORC_PARFOR
     for (int i = 0; i < m->n; i++) {
         double acc = 0.0;
         for (int s = 0; s < m->deg[i]; s++) {
@@ -260,12 +271,15 @@ void orc_rhs(const orc_swe *m, const double *u, double *f)
            *hx = m->work + 7 * n, *hy = m->work + 8 * n, *hz = m->work + 9 * n;
     double g = m->gravity;
     /* total energy  E = |u|^2/2 + g (h + h_s) */
+    ORC_PARFOR
     for (int i = 0; i < n; i++)
         E[i] = (ux[i] * ux[i] + uy[i] * uy[i] + uz[i] * uz[i]) / 2.0 + g * (h[i] + m->hs[i]);
     /* absolute vorticity eta = V.u + f (eq. vort) */
     orc_curl(m, ux, uy, uz, eta);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) eta[i] += m->cor[i];
     orc_grad(m, E, gx, gy, gz);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *ni = m->xyz + 3 * i;
         double Px = ni[1] * uz[i] - ni[2] * uy[i];
@@ -275,17 +289,20 @@ void orc_rhs(const orc_swe *m, const double *u, double *f)
         f[n + i] = -eta[i] * Py - gy[i];
         f[2 * n + i] = -eta[i] * Pz - gz[i];
     }
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         hx[i] = ux[i] * h[i];
         hy[i] = uy[i] * h[i];
         hz[i] = uz[i] * h[i];
     }
     orc_div(m, hx, hy, hz, f + 3 * n);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) f[3 * n + i] = -f[3 * n + i];
     /* dissipation D_f psi = -nu L(L psi) for each prognostic variable */
     for (int c = 0; c < 4; c++) {
         orc_lap(m, u + c * n, l1);
         orc_lap(m, l1, l2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) f[c * n + i] -= m->nu * l2[i];
     }
 }
@@ -304,10 +321,12 @@ void orc_jv(const orc_swe *m, const double *u, const double *v, double *out)
            *fz = m->work + 10 * n, *dv = m->work + 11 * n;
     double g = m->gravity;
     orc_curl(m, ux, uy, uz, eta);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) eta[i] += m->cor[i];
 
     /* J_v v: -P^i (V v)_i in each velocity row */
     orc_curl(m, vx, vy, vz, zv);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *ni = m->xyz + 3 * i;
         double Px = ni[1] * uz[i] - ni[2] * uy[i];
@@ -319,6 +338,7 @@ void orc_jv(const orc_swe *m, const double *u, const double *v, double *out)
         out[3 * n + i] = 0.0;
     }
     /* J_r v: rotation rows (row 2 with the signs of d(-eta P_y)/du) */
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *ni = m->xyz + 3 * i;
         out[i] += eta[i] * ni[2] * vy[i] - eta[i] * ni[1] * vz[i];
@@ -329,23 +349,28 @@ void orc_jv(const orc_swe *m, const double *u, const double *v, double *out)
     for (int c = 0; c < 4; c++) {
         orc_lap(m, v + c * n, l1);
         orc_lap(m, l1, l2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) out[c * n + i] -= m->nu * l2[i];
     }
     /* J_m v: velocity rows -G (u . v_vel + g v_h) */
+    ORC_PARFOR
     for (int i = 0; i < n; i++) s[i] = ux[i] * vx[i] + uy[i] * vy[i] + uz[i] * vz[i] + g * vh[i];
     orc_grad(m, s, gx, gy, gz);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] -= gx[i];
         out[n + i] -= gy[i];
         out[2 * n + i] -= gz[i];
     }
     /* J_m v: height row -D.(h v_vel) - D.(u v_h) */
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         fx[i] = h[i] * vx[i] + ux[i] * vh[i];
         fy[i] = h[i] * vy[i] + uy[i] * vh[i];
         fz[i] = h[i] * vz[i] + uz[i] * vh[i];
     }
     orc_div(m, fx, fy, fz, dv);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) out[3 * n + i] -= dv[i];
 }
 
@@ -361,9 +386,11 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out)
            *dz = m->work + 10 * n;
     double g = m->gravity;
     orc_curl(m, ux, uy, uz, eta);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) eta[i] += m->cor[i];
 
     /* (J_v)^T: -V^T (w_vel . P) */
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *ni = m->xyz + 3 * i;
         double Px = ni[1] * uz[i] - ni[2] * uy[i];
@@ -372,6 +399,7 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out)
         a[i] = wx[i] * Px + wy[i] * Py + wz[i] * Pz;
     }
     curl_T(m, a, rx, ry, rz);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] = -rx[i];
         out[n + i] = -ry[i];
@@ -379,6 +407,7 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out)
         out[3 * n + i] = 0.0;
     }
     /* (J_r)^T rotation: transpose of the 3x3 per-cell block */
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *ni = m->xyz + 3 * i;
         out[i] += -eta[i] * ni[2] * wy[i] + eta[i] * ni[1] * wz[i];
@@ -389,10 +418,12 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out)
     for (int c = 0; c < 4; c++) {
         lap_T(m, w + c * n, l1);
         lap_T(m, l1, l2);
+        ORC_PARFOR
         for (int i = 0; i < n; i++) out[c * n + i] -= m->nu * l2[i];
     }
     /* (J_m)^T velocity rows: q = G^T w_vel; v_vel gets -q u, v_h gets -g q */
     grad_T(m, wx, wy, wz, q);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] -= q[i] * ux[i];
         out[n + i] -= q[i] * uy[i];
@@ -401,6 +432,7 @@ void orc_jtv(const orc_swe *m, const double *u, const double *w, double *out)
     }
     /* (J_m)^T height row: r = D^T w_h; v_vel gets -h r, v_h gets -r . u */
     div_T(m, wh, dx, dy, dz);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] -= h[i] * dx[i];
         out[n + i] -= h[i] * dy[i];
@@ -427,6 +459,7 @@ void orc_ktv(const orc_swe *m, const double *a, const double *b, double *out)
            *rz = m->work + 4 * n, *q = m->work + 5 * n, *dx = m->work + 6 * n,
            *dy = m->work + 7 * n, *dz = m->work + 8 * n;
     orc_curl(m, bx, by, bz, zb);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         const double *ni = m->xyz + 3 * i;
         /* a x n */
@@ -444,18 +477,21 @@ void orc_ktv(const orc_swe *m, const double *a, const double *b, double *out)
         c[i] = ax[i] * ex + ay[i] * ey + az[i] * ez;
     }
     curl_T(m, c, rx, ry, rz);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] += rx[i];
         out[n + i] += ry[i];
         out[2 * n + i] += rz[i];
     }
     grad_T(m, ax, ay, az, q);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] -= q[i] * bx[i];
         out[n + i] -= q[i] * by[i];
         out[2 * n + i] -= q[i] * bz[i];
     }
     div_T(m, ah, dx, dy, dz);
+    ORC_PARFOR
     for (int i = 0; i < n; i++) {
         out[i] -= bh[i] * dx[i];
         out[n + i] -= bh[i] * dy[i];

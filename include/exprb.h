@@ -18,8 +18,13 @@
  *    Krylov iterations to launch), so they return after their work is done.
  *  - A context is not thread-safe; use one context per stream.
  *  - On error the call returns a negative xrb_status and xrb_last_error()
- *    describes it; device-side failures (NaN, non-convergence) are reported
- *    by the call that detects them.
+ *    describes it.  Failures found on the device or by the HIP runtime (NaN,
+ *    non-convergence, a failing runtime call) are returned by the call that
+ *    finds them and are also latched: xrb_sync returns the first one since
+ *    the previous xrb_sync.
+ *  - The mesh is given to xrb_create as host arrays (xrb_mesh) rather than a
+ *    file: the grids are generated in memory, and the caller keeps the choice
+ *    of file format.
  */
 #ifndef EXPRB_H
 #define EXPRB_H
@@ -128,10 +133,22 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
                       xrb_ctx **out);
 xrb_status xrb_destroy(xrb_ctx *ctx);
 xrb_status xrb_set_stream(xrb_ctx *ctx, void *stream);
-/* Wait for all work enqueued on the context's stream. */
+/* Wait for all work enqueued on the context's stream, then return the first
+ * device-side failure (XRB_ENAN, XRB_ENOTCONV or XRB_EDEVICE) latched since
+ * the previous xrb_sync and clear it; XRB_OK if there was none.  A failing
+ * stream synchronisation itself returns XRB_EDEVICE. */
 xrb_status xrb_sync(xrb_ctx *ctx);
 const char *xrb_last_error(const xrb_ctx *ctx);
 int64_t xrb_n_cells(const xrb_ctx *ctx);
+
+/* The context's grid: *n_cells, and (each optional, NULL to skip) HOST
+ * pointers to the cell centres xyz[3 n_cells] (unit vectors, the mesh's cell
+ * order) and the cell areas area[n_cells] in m^2 (spherical polygon areas on
+ * the sphere of params.radius, the A_i of the finite-volume operators of
+ * Sec. 2).  The arrays belong to the context and stay valid until
+ * xrb_destroy. */
+xrb_status xrb_mesh_info(const xrb_ctx *ctx, int64_t *n_cells, const double **xyz,
+                         const double **area);
 
 /* f = F(u): the semi-discrete shallow-water right-hand side of eq. sweqsinv
  * (vector-invariant momentum with absolute vorticity eq. vort, flux-form
@@ -265,7 +282,8 @@ xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt);
  * first call with a given nm allocates an nm-member workspace (about
  * nm (m_max + 35) 32 N bytes), a call with another nm replaces it.  Results
  * equal those of xrb_step on each member alone (same kernels, same
- * reduction order).  Replay scheduling is not available for ensembles. */
+ * reduction order).  In RECORD and REPLAY mode each member has a schedule
+ * of its own (xrb_schedule_get_member / xrb_schedule_set_member). */
 xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, const double *dt,
                           xrb_phi_stats *stats);
 
@@ -317,6 +335,14 @@ xrb_status xrb_reset_history(xrb_ctx *ctx);
 xrb_status xrb_schedule_mode(xrb_ctx *ctx, int mode);
 xrb_status xrb_schedule_set(xrb_ctx *ctx, const double *entries, int len);
 xrb_status xrb_schedule_get(const xrb_ctx *ctx, double *entries, int cap, int *len);
+/* The same for member k of the batched steps (xrb_step_batch): every member
+ * records into, or replays from, a schedule of its own.  A batched step in
+ * REPLAY mode fails with XRB_ESCHED if a member has no schedule or runs out
+ * of entries.  xrb_schedule_mode rewinds every member's replay cursor and
+ * xrb_reset_history forgets the member schedules. */
+xrb_status xrb_schedule_set_member(xrb_ctx *ctx, int k, const double *entries, int len);
+xrb_status xrb_schedule_get_member(const xrb_ctx *ctx, int k, double *entries, int cap,
+                                   int *len);
 
 /* Optional per-kernel timing.  xrb_profile(ctx, N) with N >= 1 zeroes the
  * counters and brackets every N-th launch of each kernel below (made by

@@ -397,11 +397,13 @@ class SWE:
         return outs, st.asdict(), mw.value
 
 
-def exprb42_loss_grad(swe, u0, dt, steps, obs_step, obs_cell, obs_val, tol=1e-10, m_max=40):
+def exprb42_loss_grad(swe, u0, dt, steps, obs_step, obs_cell, obs_val, tol=1e-10, m_max=40,
+                      progress=None):
     """Loss L = 1/2 sum_k (h[obs_cell_k] after step obs_step_k - obs_val_k)^2
     over an exprb42 trajectory of `steps` steps from u0, and dL/du0 by
     per-step vector-Jacobian products on the recorded schedule.
-    Returns (L, grad, schedules)."""
+    progress(phase, k), if given, is called after each forward and reverse
+    step.  Returns (L, grad, schedules)."""
     obs_step = np.asarray(obs_step, dtype=np.int64)
     obs_cell = np.asarray(obs_cell, dtype=np.int64)
     obs_val = np.asarray(obs_val, dtype=np.float64)
@@ -413,6 +415,8 @@ def exprb42_loss_grad(swe, u0, dt, steps, obs_step, obs_cell, obs_val, tol=1e-10
         sch = new_schedule()
         us.append(st.step(us[-1], dt, opts(tol=tol, m_max=m_max, mode=RECORD, sched=sch)))
         scheds.append(sch.as_array())
+        if progress:
+            progress("forward", k + 1)
     loss = 0.0
     res = []
     for k in range(steps + 1):
@@ -427,6 +431,8 @@ def exprb42_loss_grad(swe, u0, dt, steps, obs_step, obs_cell, obs_val, tol=1e-10
         g, _ = swe.step_vjp("exprb42", us[k - 1], dt, g,
                             opts(tol=tol, m_max=m_max, mode=REPLAY,
                                  sched=schedule_from_array(scheds[k - 1])))
+        if progress:
+            progress("reverse", k)
     c, r = res[0]
     np.add.at(g, 3 * n + c, r)
     return loss, g, scheds

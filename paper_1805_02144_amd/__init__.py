@@ -24,7 +24,8 @@ EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", 
            "xrb_diagnostics", "xrb_set_topography", "xrb_autotune",
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
-           "xrb_ktv", "xrb_step_vjp", "xrb_step_tableau"]
+           "xrb_ktv", "xrb_step_vjp", "xrb_step_tableau", "xrb_mesh_info",
+           "xrb_schedule_set_member", "xrb_schedule_get_member"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
@@ -145,6 +146,7 @@ def lib():
         L.xrb_last_error.restype = C.c_char_p
         L.xrb_n_cells.argtypes = [vp]
         L.xrb_n_cells.restype = C.c_int64
+        L.xrb_mesh_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(_dp), C.POINTER(_dp)]
         L.xrb_rhs.argtypes = [vp, vp, vp]
         L.xrb_jv.argtypes = [vp, vp, vp, vp]
         L.xrb_jtv.argtypes = [vp, vp, vp, vp]
@@ -164,6 +166,8 @@ def lib():
         L.xrb_schedule_mode.argtypes = [vp, C.c_int]
         L.xrb_schedule_set.argtypes = [vp, _dp, C.c_int]
         L.xrb_schedule_get.argtypes = [vp, _dp, C.c_int, C.POINTER(C.c_int)]
+        L.xrb_schedule_set_member.argtypes = [vp, C.c_int, _dp, C.c_int]
+        L.xrb_schedule_get_member.argtypes = [vp, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)]
         L.xrb_profile.argtypes = [vp, C.c_int]
         L.xrb_profile_get.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]
@@ -252,7 +256,18 @@ class Context:
         return self.torch.empty(self.N, dtype=self.torch.float64, device=self.device)
 
     def sync(self):
+        """Wait for the context's stream; raises the first device-side failure
+        latched since the previous sync."""
         self._check(lib().xrb_sync(self.h))
+
+    def mesh_info(self):
+        """(n_cells, centres [n, 3], areas [n] in m^2) as the library holds them."""
+        n = C.c_int64()
+        xyz, area = _dp(), _dp()
+        self._check(lib().xrb_mesh_info(self.h, C.byref(n), C.byref(xyz), C.byref(area)))
+        k = n.value
+        return (k, np.ctypeslib.as_array(xyz, (k, 3)).copy(),
+                np.ctypeslib.as_array(area, (k,)).copy())
 
     def rhs(self, u):
         self._stream()
@@ -399,6 +414,20 @@ class Context:
     def schedule_set(self, arr):
         a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(-1, 3))
         self._check(lib().xrb_schedule_set(self.h, a.ctypes.data_as(_dp), len(a)))
+
+    def schedule_set_member(self, k, arr):
+        """Replay schedule of ensemble member k (rows tau, m, flags)."""
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(-1, 3))
+        self._check(lib().xrb_schedule_set_member(self.h, int(k), a.ctypes.data_as(_dp), len(a)))
+
+    def schedule_get_member(self, k):
+        """Schedule recorded for ensemble member k."""
+        n = C.c_int()
+        self._check(lib().xrb_schedule_get_member(self.h, int(k), None, 0, C.byref(n)))
+        a = np.zeros((max(1, n.value), 3))
+        self._check(lib().xrb_schedule_get_member(self.h, int(k), a.ctypes.data_as(_dp),
+                                                  n.value, C.byref(n)))
+        return a[:n.value]
 
     def profile(self, every=1):
         """Time every `every`-th launch of each kernel with HIP events

@@ -73,7 +73,7 @@ struct Work {
     Decision *h_dec = nullptr;   // written by the controller kernel (d_dec: its device address)
     Decision *d_dec = nullptr;
     int dec_seq = 0;             // sequence number of the last controller launch
-    int32_t *h_stage = nullptr;  // [2][nm][kPlanW] pinned staging of plan uploads
+    int32_t *h_stage = nullptr;  // [3][nm][kPlanW] pinned staging of plan uploads
     std::vector<int32_t> h_plan; // [nm][kPlanW] host working copy of the plan
     CtlArgs *h_cargs = nullptr;
     double *h_vn = nullptr;
@@ -117,6 +117,9 @@ struct xrb_ctx {
     int mode = XRB_FREE;
     std::vector<SchedEntry> sched;
     size_t sched_pos = 0;
+    // per-member schedules of batched steps (record / replay of ensembles)
+    std::vector<std::vector<SchedEntry>> msched;
+    std::vector<size_t> mpos;
     // optional per-kernel event timing
     struct Pending {
         int id;
@@ -137,6 +140,10 @@ struct xrb_ctx {
     // outputs
     double *io = nullptr;
     double *hs = nullptr;   // device copy of the surface topography (M.hs)
+    // host copies of the cell centres (unit vectors) and areas, for xrb_mesh_info
+    std::vector<double> h_xyz, h_area;
+    // first device-side failure since the last xrb_sync (0 = none)
+    int latched = 0;
 };
 
 namespace {
@@ -150,12 +157,20 @@ constexpr int kIoOutSlot = 1 + (kPmax + 1);
         hipError_t e_ = (call);                                                       \
         if (e_ != hipSuccess) {                                                       \
             ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);             \
+            if (!ctx->latched) ctx->latched = XRB_EDEVICE;                            \
             return XRB_EDEVICE;                                                       \
         }                                                                             \
     } while (0)
 
+// Record a failure.  Failures found on the device or by the HIP runtime
+// (NaN, non-convergence, a failing runtime call) are also latched for
+// xrb_sync, which reports the first one since the previous xrb_sync.
 int fail(xrb_ctx *ctx, int code, const char *msg) {
-    if (ctx) ctx->err = msg;
+    if (ctx) {
+        ctx->err = msg;
+        if (!ctx->latched && (code == XRB_ENAN || code == XRB_ENOTCONV || code == XRB_EDEVICE))
+            ctx->latched = code;
+    }
     return code;
 }
 
@@ -313,10 +328,13 @@ struct MemberPhi {
     xrb_phi_stats st{};
 };
 
-// Upload the plan through staging half `half`: half 0 before the IOM2
-// launches, half 1 after the decisions, so a staging buffer is never
-// rewritten while its asynchronous copy may still be pending (each half is
-// reused only after the next decision synchronisation).
+// Upload the plan through staging slot `half`: slot 0 before the IOM2
+// launches, slot 1 after the decisions, so a staging buffer is never
+// rewritten while its asynchronous copy may still be pending (each of the
+// two is reused only after the next decision synchronisation).  Slot 2
+// carries the zero-output plan a call uploads before its first round; it is
+// reused only by the next call, after that call's own stream
+// synchronisation.
 int upload_plan(xrb_ctx *ctx, Work &W, int half) {
     if (W.nm <= 1) return XRB_OK;
     int32_t *stg = W.h_stage + (size_t)half * kPlanW * W.nm;
@@ -360,8 +378,12 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
         for (int l = 0; l <= p; ++l)
             if (v[l] && v[l] == w_out[i]) return fail(ctx, XRB_EINVAL, "phi_combo: output aliases input");
     }
-    if (ctx->mode == XRB_REPLAY && nm > 1)
-        return fail(ctx, XRB_EINVAL, "phi_combo: replay is available for single states only");
+    if (nm > 1 && ctx->mode != XRB_FREE && (int)ctx->msched.size() < nm) {
+        if (ctx->mode == XRB_REPLAY)
+            return fail(ctx, XRB_ESCHED, "phi_combo: no replay schedule for some members");
+        ctx->msched.resize(nm);
+        ctx->mpos.resize(nm, 0);
+    }
     if (tape && nm > 1) return fail(ctx, XRB_EINVAL, "phi_combo: substep store is single-state");
     if (tape) {
         tape->p = p;
@@ -405,7 +427,7 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
     }
     // all-zero inputs give W = 0 exactly
     if (live < nm) {
-        int rc = upload_plan(ctx, W, 0);
+        int rc = upload_plan(ctx, W, 2);
         if (rc) return rc;
         const Batch bz = batch_of(W, W.plan, PF_INIT);
         for (int i = 0; i < ns; ++i) {
@@ -474,9 +496,11 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             mm.st.attempts++;
             ReplayIn rep{};
             if (ctx->mode == XRB_REPLAY) {
-                if (ctx->sched_pos >= ctx->sched.size())
+                std::vector<SchedEntry> &sv = nm > 1 ? ctx->msched[k] : ctx->sched;
+                size_t &pos = nm > 1 ? ctx->mpos[k] : ctx->sched_pos;
+                if (pos >= sv.size())
                     return fail(ctx, XRB_ESCHED, "phi_combo: replay schedule exhausted");
-                const SchedEntry &e = ctx->sched[ctx->sched_pos++];
+                const SchedEntry &e = sv[pos++];
                 if (e.m < 1 || e.m > P.m_max) return fail(ctx, XRB_ESCHED, "phi_combo: bad replay m");
                 rep.tau = e.tau;
                 rep.m = e.m;
@@ -613,8 +637,9 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             if (d.m_eff > 0) mm.st.expms++;
             mm.st.sum_m += mm.m;
             mm.st.max_m = std::max(mm.st.max_m, mm.m);
-            if (ctx->mode == XRB_RECORD && nm == 1)
-                ctx->sched.push_back({d.tau_u, mm.m, (d.accept ? 1 : 0) | (d.lands ? 2 : 0)});
+            if (ctx->mode == XRB_RECORD)
+                (nm > 1 ? ctx->msched[k] : ctx->sched)
+                    .push_back({d.tau_u, mm.m, (d.accept ? 1 : 0) | (d.lands ? 2 : 0)});
             if (d.accept && tape) {
                 // keep this substep's solution basis before the combine overwrites y = w_0
                 TapeSub ts;
@@ -738,7 +763,7 @@ int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
         std::memset((void *)W.h_dec, 0, sizeof(Decision) * nm);
         ck(hipHostGetDevicePointer((void **)&W.d_dec, W.h_dec, 0));
     }
-    ck(hipHostMalloc((void **)&W.h_stage, sizeof(int32_t) * 2 * kPlanW * nm, hipHostMallocDefault));
+    ck(hipHostMalloc((void **)&W.h_stage, sizeof(int32_t) * 3 * kPlanW * nm, hipHostMallocDefault));
     W.h_plan.assign((size_t)kPlanW * nm, 0);
     ck(hipHostMalloc((void **)&W.h_cargs, sizeof(CtlArgs) * nm, hipHostMallocDefault));
     ck(hipHostMalloc((void **)&W.h_vn, sizeof(double) * (kPmax + 1) * nm, hipHostMallocDefault));
@@ -1452,6 +1477,8 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ctx->n = n;
     ctx->n4 = 4 * n;
     const size_t nd = (size_t)n;
+    ctx->h_xyz.assign(mesh->xyz, mesh->xyz + 3 * nd);
+    ctx->h_area.swap(geo.area);
     // geometry in one allocation: 2 x [n][6] edge scalars, [n][4] cell records, [n][6] int32
     const size_t dbl = 2 * 6 * nd + 4 * nd;
     const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t);
@@ -1529,6 +1556,17 @@ xrb_status xrb_set_stream(xrb_ctx *ctx, void *stream) {
 xrb_status xrb_sync(xrb_ctx *ctx) {
     if (!ctx) return XRB_EINVAL;
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int rc = ctx->latched;
+    ctx->latched = 0;
+    return (xrb_status)rc;
+}
+
+xrb_status xrb_mesh_info(const xrb_ctx *ctx, int64_t *n_cells, const double **xyz,
+                         const double **area) {
+    if (!ctx || !n_cells) return XRB_EINVAL;
+    *n_cells = ctx->n;
+    if (xyz) *xyz = ctx->h_xyz.data();
+    if (area) *area = ctx->h_area.data();
     return XRB_OK;
 }
 
@@ -1861,6 +1899,8 @@ xrb_status xrb_reset_history(xrb_ctx *ctx) {
     }
     ctx->sched.clear();
     ctx->sched_pos = 0;
+    ctx->msched.clear();
+    ctx->mpos.clear();
     return XRB_OK;
 }
 
@@ -1868,6 +1908,37 @@ xrb_status xrb_schedule_mode(xrb_ctx *ctx, int mode) {
     if (!ctx || mode < XRB_FREE || mode > XRB_REPLAY) return XRB_EINVAL;
     ctx->mode = mode;
     ctx->sched_pos = 0;
+    std::fill(ctx->mpos.begin(), ctx->mpos.end(), (size_t)0);
+    return XRB_OK;
+}
+
+xrb_status xrb_schedule_set_member(xrb_ctx *ctx, int k, const double *entries, int len) {
+    if (!ctx || k < 0 || len < 0 || (len > 0 && !entries)) return XRB_EINVAL;
+    if ((int)ctx->msched.size() <= k) {
+        ctx->msched.resize(k + 1);
+        ctx->mpos.resize(k + 1, 0);
+    }
+    std::vector<SchedEntry> &sv = ctx->msched[k];
+    sv.resize(len);
+    for (int i = 0; i < len; ++i)
+        sv[i] = {entries[3 * i], (int32_t)entries[3 * i + 1], (int32_t)entries[3 * i + 2]};
+    ctx->mpos[k] = 0;
+    return XRB_OK;
+}
+
+xrb_status xrb_schedule_get_member(const xrb_ctx *ctx, int k, double *entries, int cap,
+                                   int *len) {
+    if (!ctx || k < 0 || !len || cap < 0 || (cap > 0 && !entries)) return XRB_EINVAL;
+    *len = 0;
+    if (k >= (int)ctx->msched.size()) return XRB_OK;
+    const std::vector<SchedEntry> &sv = ctx->msched[k];
+    const int L = (int)sv.size();
+    *len = L;
+    for (int i = 0; i < L && i < cap; ++i) {
+        entries[3 * i] = sv[i].tau;
+        entries[3 * i + 1] = sv[i].m;
+        entries[3 * i + 2] = sv[i].flags;
+    }
     return XRB_OK;
 }
 

@@ -62,6 +62,7 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
     geo.nbr.assign(6 * (size_t)n, 0);
     resize6(geo.alpha); resize6(geo.cl);
     geo.cen.assign(4 * (size_t)n, 0.0);
+    geo.area.assign((size_t)n, 0.0);
 
     auto X = [&](int64_t i) { return V3{mesh.xyz[3 * i], mesh.xyz[3 * i + 1], mesh.xyz[3 * i + 2]}; };
     auto CRN = [&](int64_t i, int s) {
@@ -102,6 +103,7 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
         double *ce = &geo.cen[4 * (size_t)i];
         ce[0] = xi.x; ce[1] = xi.y; ce[2] = xi.z;
         ce[3] = 1.0 / area;
+        geo.area[i] = area;
     }
     const double dxbar = std::sqrt(4.0 * M_PI * R * R / (double)n);
     geo.nu = prm.gamma_h * dxbar * dxbar * dxbar * dxbar / prm.dt_e;

@@ -341,6 +341,7 @@ struct HostGeometry {
     std::vector<int32_t> nbr;                              // [n][6]
     std::vector<double> alpha, cl;                         // [n][6]
     std::vector<double> cen;                               // [n][4] x, y, z, 1 / area
+    std::vector<double> area;                              // [n] cell areas (m^2)
     double nu = 0.0;
 };
 int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,

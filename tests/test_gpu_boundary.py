@@ -92,3 +92,32 @@ def test_phi_combo_rejects_aliased_outputs(X):
                            rho.ctypes.data_as(C.POINTER(C.c_double)), oa, None)
     assert rc == -1   # XRB_EINVAL
     ctx.close()
+
+
+def test_mesh_info_and_latched_errors(X):
+    """xrb_mesh_info returns the grid the context was made from (centres as
+    given, areas summing to the sphere's); a device-side failure (a NaN
+    input met by a norm) is returned by the call and again, once, by the
+    next xrb_sync."""
+    import ctypes as C
+    level = 3
+    mesh = get_mesh(level)
+    ctx = X.Context(mesh, "cuda:0")
+    n, xyz, area = ctx.mesh_info()
+    assert n == len(mesh["xyz"])
+    assert np.array_equal(xyz, np.asarray(mesh["xyz"], dtype=np.float64))
+    a = 6.371e6
+    assert abs(area.sum() / (4 * np.pi * a * a) - 1.0) < 1e-12 and np.all(area > 0)
+    lib = X.lib()
+    assert lib.xrb_sync(ctx.h) == 0
+    u = F.initial_state("c1_exprb42_l4", level=level)
+    bad = np.ones(4 * n)
+    bad[3] = np.nan
+    with pytest.raises(X.ExprbError):
+        ctx.phi_combo(u, 600.0, [None, bad], [1.0])
+    assert lib.xrb_sync(ctx.h) == -5      # XRB_ENAN, latched
+    assert lib.xrb_sync(ctx.h) == 0       # and cleared
+    ctx.sync()
+    n2 = C.c_int64()
+    assert lib.xrb_mesh_info(ctx.h, C.byref(n2), None, None) == 0 and n2.value == n
+    ctx.close()

@@ -141,3 +141,36 @@ def test_c4_six_launches(X):
     for _ in range(6):
         ref = st.step(ref, dts[0])
     assert blocks_rel(got[0] - U[0], ref - U[0], s.n) < TOL
+
+
+def test_batch_with_a_resting_member_bitwise(X):
+    """A member whose inputs are all zero (a resting ocean: F = 0, so every
+    phi-combination input vanishes) takes the zero-output path of a batched
+    call while the others iterate; its outputs must be exact zeros, not the
+    previous step's values left in its buffers.  Step 1 runs three perturbed
+    members, then member 1 is replaced by a resting ocean for step 2; each
+    member must equal the same sequence of single-state steps bitwise."""
+    import torch
+    level, nm = 4, 3
+    mesh, U, dts = members(level, nm)
+    n = len(mesh["xyz"])
+    dts = np.array([1200.0, 2400.0, 3600.0])
+    rest = np.concatenate([np.zeros(3 * n), np.full(n, 5000.0)])
+    say("ensemble with a resting member")
+    ctx = X.Context(mesh, "cuda:0")
+    Ub = torch.tensor(U, device="cuda:0")
+    ctx.reset_history()
+    ctx.step_batch("exprb42", Ub, dts)
+    Ub[1] = torch.as_tensor(rest, device="cuda:0")
+    ctx.step_batch("exprb42", Ub, dts)
+    got = Ub.cpu().numpy()
+    assert np.array_equal(got[1], rest)
+    for k in range(nm):
+        ctx.reset_history()
+        u = torch.tensor(U[k], device="cuda:0")
+        ctx.step("exprb42", u, dts[k])
+        if k == 1:
+            u.copy_(torch.as_tensor(rest, device="cuda:0"))
+        ctx.step("exprb42", u, dts[k])
+        assert np.array_equal(u.cpu().numpy(), got[k]), k
+    ctx.close()

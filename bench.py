@@ -1,19 +1,27 @@
 """Benchmark of the phi-combination hot path on one MI355X.
 
-Workload (one bench step): from the seeded level-6 state (solid-body zonal
-flow u0 = 38.6 m/s, balanced depth, 120 m Gaussian bump; N = 40962 cells,
-n = 163848 unknowns, FP64) run pexprb43 for 24 steps of 3600 s and exprb53
-for 24 steps of 3600 s (tol 1e-10 relative, m_max 40).  That is 120
-phipm_simul_iom2 evaluations per bench step.  value = evaluations per second
-with all inputs resident in device memory.
+Headline workload (one bench step): the seeded level-8 jet (N = 655362
+cells, n = 2621448 unknowns, FP64, gamma_h = 1.25e-2; a balanced zonal jet
+plus a 120 m Gaussian bump), six exprb53 steps of 1800 s (tol 1e-10
+relative, m_max 40): 18 phipm_simul_iom2 evaluations.  value = evaluations
+per second with every input resident in device memory.
 
-Also reported: the roofline of the fused Jacobian-product/IOM2 kernel
-(algorithmic bytes per launch over its HIP-event-timed average duration),
-a per-kernel time breakdown, the CPU oracle timed on a bounded sample of
-the same workload, and the other workloads' legs: one level-4 exprb42 step
-(latency), the 64-member level-6 ensemble (batched vs per-member loop), the
-level-8 jet (rooflines of the product and the update) and the level-7
-adjoint twin experiment.
+roofline: the fused Jacobian-product / IOM2-dot kernel at level 8,
+algorithmic bytes per launch over its average duration, timed live with
+HIP events on the library's stream (every 16th launch) and corrected for
+what an event pair adds to a launch (measured on an empty kernel in the
+same run); traffic = HBM bytes per launch from the committed PMC summary,
+while the kernel's sources hash to the value it was taken on.
+
+cpu_baseline: the CPU oracle on the first step of the same workload, on
+all host cores (its independent cell loops threaded), and on one core for
+that step's first evaluation.
+
+Extra legs: the level-6 pexprb43 + exprb53 workload (24 steps of 3600 s
+each), one level-4 exprb42 step (latency), the 64-member level-6 ensemble
+(batched vs per-member loop, medians of 20, and the oracle over all host
+cores) and the level-7 adjoint twin experiment (forward vs reverse sweep,
+central differences along 8 seeded directions).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
@@ -36,16 +44,28 @@ HBM_PEAK_GBS = 8000.0
 JV_IOM2_BYTES_PER_CELL = 192.0
 # IOM2 update per cell: read w, v_j, v_{j-1}, write v_{j+1} (4 x 32 B)
 IOM2_BYTES_PER_CELL = 128.0
-STEPS_PER_METHOD = 24
-DT = 3600.0
+# one-ring Laplacian pass: x 32 + out 32 + neighbour ids 24 + Laplacian weights 48
+LAP_BYTES_PER_CELL = 136.0
+KERNEL_BYTES = {"jv_iom2": JV_IOM2_BYTES_PER_CELL, "iom2_update": IOM2_BYTES_PER_CELL,
+                "lap": LAP_BYTES_PER_CELL}
+
+# headline: level-8 jet, exprb53
+JET_STEPS, JET_DT, JET_EVALS_PER_STEP = 6, 1800.0, 3
+# level-6 leg: pexprb43 and exprb53
+C2_STEPS, C2_DT = 24, 3600.0
 EVALS_PER_STEP = {"pexprb43": 2, "exprb53": 3}
+# the level-8 kernels last 15-150 us: sampling every 16th launch costs little
+# there and gives enough samples; the level-6 ones last 4-10 us: every 64th
+JET_EVENT_EVERY = 16
+C2_EVENT_EVERY = 64
 
-
-# Kernel sources of the roofline kernel: a PMC traffic figure in profiles/ is
-# used only while these hash to the value it was taken on.
+# Kernel sources of the roofline kernel: a PMC traffic figure or a rocprof
+# average in profiles/ is used only while these hash to the value it was
+# taken on.
 TRAFFIC_SOURCES = ["paper_1805_02144_amd/csrc/stencil.hip", "paper_1805_02144_amd/csrc/stencil_common.h",
                    "paper_1805_02144_amd/csrc/reduce.h", "paper_1805_02144_amd/csrc/xrb_internal.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_l6_jv_iom2_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_l8_jet_traffic.md")
+TRAFFIC_FILE_L6 = os.path.join(ROOT, "profiles", "c2_l6_jv_iom2_traffic.md")
 
 
 def kernel_source_hash():
@@ -57,20 +77,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the roofline kernel from the committed PMC
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the factor a plain
-    device copy of known size gives), or None if the kernel changed since."""
+def profile_keys(path):
+    """The '- key: value' lines of a committed profile summary, or {} if the
+    kernel sources changed since it was taken."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 kv[k.strip()] = v.strip().strip("`")
-        if kv.get("source_sha") != kernel_source_hash():
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (OSError, KeyError, ValueError):
+        return kv if kv.get("source_sha") == kernel_source_hash() else {}
+    except OSError:
+        return {}
+
+
+def _float(kv, key):
+    try:
+        return float(kv[key])
+    except (KeyError, ValueError):
         return None
 
 
@@ -78,24 +102,220 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_pass(ctx, u, u0, torch):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Host threads for the oracle: the machine's CPU share (at most 16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def kernel_table(prof, overhead_us, n_cells):
+    """Per-kernel averages from the sampled event pairs: raw, and corrected by
+    the event-pair overhead; estimated device time over all launches."""
+    out = {}
+    for k, (ms, timed, launches) in prof.items():
+        raw = 1e3 * ms / timed if timed else 0.0
+        cor = max(raw - overhead_us, 0.0) if timed else 0.0
+        row = {"avg_us": cor, "avg_us_events": raw, "launches": launches, "timed": timed,
+               "est_ms": cor * launches * 1e-3}
+        if k in KERNEL_BYTES and cor > 0:
+            ach = KERNEL_BYTES[k] * n_cells / (cor * 1e-6) / 1e9
+            row.update(bytes_per_cell=KERNEL_BYTES[k], achieved_gbs=ach,
+                       frac=ach / HBM_PEAK_GBS)
+        out[k] = row
+    tot = sum(r["est_ms"] for r in out.values())
+    for r in out.values():
+        r["share"] = r["est_ms"] / tot if tot else 0.0
+    return out, tot
+
+
+def roofline_of(table, name, n_cells, kv):
+    r = table[name]
+    traffic = _float(kv, "traffic_bytes_per_launch")
+    alg = KERNEL_BYTES[name] * n_cells
+    return {"bound": "hbm", "kernel": "k_jv<kEpiIom2> (fused Jacobian product + IOM2 dots)",
+            "achieved": r.get("achieved_gbs", 0.0), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r.get("frac", 0.0), "traffic": traffic,
+            "traffic_over_algorithmic": traffic / alg if traffic else None,
+            "avg_us": r["avg_us"], "avg_us_events": r["avg_us_events"],
+            "rocprof_avg_us": _float(kv, "rocprof_avg_us"),
+            "launches": r["launches"], "timed_launches": r["timed"],
+            "bytes_per_cell": KERNEL_BYTES[name], "cells": n_cells,
+            "algorithmic_bytes_per_launch": alg}
+
+
+# ---------------------------------------------------------------- headline
+def jet_pass(ctx, u, u0):
+    u.copy_(u0)
+    ctx.reset_history()
+    for _ in range(JET_STEPS):
+        ctx.step("exprb53", u, JET_DT)
+    return JET_STEPS * JET_EVALS_PER_STEP
+
+
+def jet_leg(X, torch, steps, warmup, event_every=JET_EVENT_EVERY, lanes=0, autotune=False):
+    """Level-8 jet (N = 655362, n = 2621448): exprb53, 6 steps of 1800 s,
+    gamma_h = 1.25e-2 -- the bandwidth-bound workload."""
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(8)
+    n = len(mesh["xyz"])
+    u0 = torch.tensor(F.initial_state("c3_l8_jet"), dtype=torch.float64, device="cuda:0")
+    ctx = X.Context(mesh, "cuda:0", gamma_h=1.25e-2, tol=1e-10, m_max=40, lanes=lanes)
+    tune = ctx.autotune(1) if autotune else None
+    u = u0.clone()
+    for _ in range(warmup):
+        jet_pass(ctx, u, u0)
+    torch.cuda.synchronize()
+    overhead = ctx.profile_overhead(200)
+    ctx.profile(event_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    stats = []
+    for _ in range(steps):
+        evals += jet_pass(ctx, u, u0)
+        stats.append(ctx.step_stats())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_get()
+    ctx.profile(0)
+    ctx.close()
+    table, dev_ms = kernel_table(prof, overhead, n)
+    kv = profile_keys(TRAFFIC_FILE)
+    return {"value": evals / el, "elapsed_s": el, "evals": evals, "n": n,
+            "roofline": roofline_of(table, "jv_iom2", n, kv), "kernels": table,
+            "event_overhead_us": overhead, "device_time_fraction": dev_ms * 1e-3 / el,
+            "autotuned": tune}
+
+
+def cpu_baseline_jet(threads):
+    """The oracle on the level-8 jet: the first exprb53 step (3 evaluations)
+    with its independent cell loops on `threads` host threads, and the first
+    evaluation of that step (exprb53's call (i), rho = [1/2, 9/10]) on one
+    thread."""
+    import numpy as np
+    import oracle as O
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(8)
+    s = O.SWE(mesh, gamma_h=1.25e-2)
+    u0 = F.initial_state("c3_l8_jet")
+    O.set_threads(threads)
+    try:
+        t0 = time.perf_counter()
+        O.swe_stepper(s, "exprb53").step(u0, JET_DT)
+        t_all = time.perf_counter() - t0
+    finally:
+        O.set_threads(1)
+    v = JET_DT * s.rhs(u0)
+    t0 = time.perf_counter()
+    s.phi_combo(u0, JET_DT, [None, v / JET_DT], [0.5, 0.9])
+    t_one = time.perf_counter() - t0
+    del np
+    return {"value": JET_EVALS_PER_STEP / t_all, "unit": "phi-combination evals/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "the first exprb53 step of the level-8 jet workload (3 of the 18 "
+                      "evaluations of one bench step), %.1f s on %d threads" % (t_all, threads),
+            "single_core": {"value": 1.0 / t_one, "unit": "phi-combination evals/s", "cores": 1,
+                            "sample": "the first evaluation of that step (exprb53 call (i)), "
+                                      "%.1f s on one thread" % t_one},
+            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+
+
+# ---------------------------------------------------------------- level 6
+def c2_pass(ctx, u, u0):
     evals = 0
     stats = []
     for method in ("pexprb43", "exprb53"):
         ctx.reset_history()
         u.copy_(u0)
-        for _ in range(STEPS_PER_METHOD):
-            ctx.step(method, u, DT)
+        for _ in range(C2_STEPS):
+            ctx.step(method, u, C2_DT)
             evals += EVALS_PER_STEP[method]
             stats.append(ctx.step_stats())
     return evals, stats
 
 
-def ensemble_leg(X, torch, mesh, reps=3):
-    """64 level-6 members, exprb42, one step each: one batched launch sequence
-    against the per-member loop of single steps (member-steps/s)."""
+def c2_leg(X, torch, steps=2, warmup=1, lanes=0, cpu=True, cpu_steps=6):
+    """Level 6 (N = 40962): pexprb43 and exprb53, 24 steps of 3600 s each from
+    the seeded solid-body flow with a bump (120 evaluations per pass); a
+    latency-bound workload (vectors of 1.3 MB)."""
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(6)
+    n = len(mesh["xyz"])
+    u0h = F.initial_state("c2_l6_24x3600")
+    ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40, lanes=lanes)
+    u0 = torch.tensor(u0h, dtype=torch.float64, device="cuda:0")
+    u = torch.empty_like(u0)
+    for _ in range(warmup):
+        c2_pass(ctx, u, u0)
+    torch.cuda.synchronize()
+    overhead = ctx.profile_overhead(200)
+    ctx.profile(C2_EVENT_EVERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    agg = {}
+    for _ in range(steps):
+        e, st = c2_pass(ctx, u, u0)
+        evals += e
+        for s_ in st:
+            for c in s_:
+                for k in ("attempts", "rejected", "accepted", "matvecs", "expms", "sum_m"):
+                    agg[k] = agg.get(k, 0) + c[k]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = ctx.profile_get()
+    ctx.profile(0)
+    ctx.close()
+    table, dev_ms = kernel_table(prof, overhead, n)
+    out = {"workload": "pexprb43 and exprb53, 24 steps of 3600 s each, level-6 grid "
+                       "(N=40962, n=163848), FP64, tol 1e-10, m_max 40",
+           "phi_evals_per_s": evals / el, "ms_per_pass": 1e3 * el / steps, "passes": steps,
+           "roofline_jv_iom2": roofline_of(table, "jv_iom2", n, profile_keys(TRAFFIC_FILE_L6)),
+           "kernels": table, "event_overhead_us": overhead,
+           "device_time_fraction": dev_ms * 1e-3 / el,
+           "krylov_per_pass": {k: v / steps for k, v in agg.items()}}
+    if cpu:
+        import oracle as O
+        s = O.SWE(mesh)
+        ev = 0
+        t0 = time.perf_counter()
+        for method in ("pexprb43", "exprb53"):
+            st = O.swe_stepper(s, method)
+            uh = u0h.copy()
+            for _ in range(cpu_steps):
+                uh = st.step(uh, C2_DT)
+                ev += EVALS_PER_STEP[method]
+        t = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": ev / t, "unit": "phi-combination evals/s", "cores": 1,
+                             "sample": "first %d steps of each scheme, %.1f s" % (cpu_steps, t)}
+    return out
+
+
+def ensemble_leg(X, torch, reps=20, cpu=True):
+    """64 level-6 members, exprb42, one step each with its own step size: the
+    batched launch sequence against the per-member loop of single steps
+    (member-steps/s, medians of `reps` runs each), and the oracle with one
+    member per host thread."""
     import numpy as np
     from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(6)
     U0, dts = F.ensemble_states(6, F.config_seed(3), 64)
     ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40)
     tune = ctx.autotune(64)                      # launch shapes for this grid and batch
@@ -104,81 +324,65 @@ def ensemble_leg(X, torch, mesh, reps=3):
     ctx.reset_history()
     ctx.step_batch("exprb42", Ub, dts)          # warm-up (allocates the workspace)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    tb = []
     for _ in range(reps):
         Ub.copy_(Ub0)
         ctx.reset_history()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         ctx.step_batch("exprb42", Ub, dts)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
     u = torch.empty(Ub0.shape[1], dtype=torch.float64, device="cuda:0")
     u.copy_(Ub0[0])
     ctx.reset_history()
     ctx.step("exprb42", u, float(dts[0]))
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    tl = []
     last = None
-    for k in range(64):
-        u.copy_(Ub0[k])
-        ctx.reset_history()
-        ctx.step("exprb42", u, float(dts[k]))
-        if k == 63:
-            last = u.clone()
-    torch.cuda.synchronize()
-    tl = time.perf_counter() - t0
+    for r in range(reps):
+        t0 = time.perf_counter()
+        for k in range(64):
+            u.copy_(Ub0[k])
+            ctx.reset_history()
+            ctx.step("exprb42", u, float(dts[k]))
+            if k == 63 and r == reps - 1:
+                last = u.clone()
+        torch.cuda.synchronize()
+        tl.append(time.perf_counter() - t0)
     same = bool(torch.equal(last, Ub[63]))
     ctx.close()
-    return {"workload": "64 members, level-6 grid, exprb42, one step each, dt from "
-                        "{600, 1200, 2400, 3600} s (seeded), FP64",
-            "batched_member_steps_per_s": 64 / tb, "loop_member_steps_per_s": 64 / tl,
-            "speedup": tl / tb, "batched_ms": 1e3 * tb, "loop_ms": 1e3 * tl,
-            "last_member_bitwise_equal": same,
-            "autotune": {"lanes": tune["lanes"], "lanes_batch": tune["lanes_batch"],
-                         "single_us": tune["single_us"], "batch_us": tune["batch_us"]},
-            "dt_mix": {str(int(d)): int((dts == d).sum()) for d in sorted(set(dts))}}
+    mb, ml = float(np.median(tb)), float(np.median(tl))
+    out = {"workload": "64 members, level-6 grid, exprb42, one step each, dt from "
+                       "{600, 1200, 2400, 3600} s (seeded), FP64",
+           "batched_member_steps_per_s": 64 / mb, "loop_member_steps_per_s": 64 / ml,
+           "speedup": ml / mb, "batched_ms_median": 1e3 * mb, "loop_ms_median": 1e3 * ml,
+           "batched_ms_min": 1e3 * min(tb), "loop_ms_min": 1e3 * min(tl), "runs": reps,
+           "last_member_bitwise_equal": same,
+           "autotune": {"lanes": tune["lanes"], "lanes_batch": tune["lanes_batch"],
+                        "single_us": tune["single_us"], "batch_us": tune["batch_us"]},
+           "dt_mix": {str(int(d)): int((dts == d).sum()) for d in sorted(set(dts))}}
+    if cpu:
+        import threading
+        from concurrent.futures import ThreadPoolExecutor
+        import oracle as O
+        threads = host_threads()
+        local = threading.local()
 
+        def one(k):
+            if not hasattr(local, "s"):
+                local.s = O.SWE(mesh)
+            O.swe_stepper(local.s, "exprb42").step(U0[k], float(dts[k]))
 
-# the level-8 kernels last 20-150 us, so sampling every 16th launch costs
-# little there and gives enough samples over six steps
-JET_EVENT_EVERY = 16
-
-
-def jet_leg(X, torch, event_every):
-    """Level-8 jet (N = 655362, n = 2621448): exprb53, 6 steps of 1800 s,
-    gamma_h = 1.25e-2 -- the bandwidth-bound roofline run of the Jacobian
-    product and the IOM2 update."""
-    from synth import fields as F
-    from synth.mesh import get_mesh
-    mesh = get_mesh(8)
-    n = len(mesh["xyz"])
-    u0 = torch.tensor(F.initial_state("c3_l8_jet"), dtype=torch.float64, device="cuda:0")
-    ctx = X.Context(mesh, "cuda:0", gamma_h=1.25e-2, tol=1e-10, m_max=40)
-    u = u0.clone()
-    ctx.reset_history()
-    ctx.step("exprb53", u, 1800.0)              # warm-up
-    torch.cuda.synchronize()
-    u.copy_(u0)
-    ctx.reset_history()
-    ctx.profile(event_every)
-    t0 = time.perf_counter()
-    for _ in range(6):
-        ctx.step("exprb53", u, 1800.0)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    prof = ctx.profile_get()
-    ctx.profile(0)
-    ctx.close()
-    out = {"workload": "exprb53, 6 steps of 1800 s, level-8 jet + bump, N=655362, "
-                       "n=2621448, FP64, gamma_h 1.25e-2",
-           "phi_evals_per_s": 18 / el, "ms": 1e3 * el}
-    for name, bpc in (("jv_iom2", JV_IOM2_BYTES_PER_CELL), ("iom2_update", IOM2_BYTES_PER_CELL)):
-        ms, tn, an = prof[name]
-        avg = ms * 1e-3 / max(tn, 1)
-        ach = bpc * n / avg / 1e9 if tn else 0.0
-        out["roofline_" + name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                                   "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                                   "avg_us": 1e6 * avg, "launches": an,
-                                   "bytes_per_cell": bpc}
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(one, range(64)))
+        t = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": 64 / t, "unit": "member-steps/s", "cores": threads,
+                             "kind": "oracle",
+                             "sample": "all 64 member steps, one member per host thread, "
+                                       "%.1f s" % t}
     return out
 
 
@@ -214,12 +418,27 @@ def c1_leg(X, torch, cpu=True, reps=100):
         b.record()
         b.synchronize()
         ts.append(1e3 * a.elapsed_time(b))
+    # per-kernel times of the same steps (every launch between events,
+    # corrected by the event-pair overhead; a separate pass)
+    overhead = ctx.profile_overhead(200)
+    ctx.profile(1)
+    for _ in range(10):
+        u.copy_(u0)
+        ctx.reset_history()
+        ctx.step("exprb42", u, 900.0)
+    torch.cuda.synchronize()
+    prof = ctx.profile_get()
+    ctx.profile(0)
     ctx.close()
+    table, _ = kernel_table(prof, overhead, len(mesh["xyz"]))
     med = float(np.median(ts))
     out = {"workload": "exprb42, one step of 900 s, level-4 grid (N=2562, n=10248), FP64, "
                        "tol 1e-10, m_max 40, state reset before each step",
            "us_per_step_median": med, "us_per_step_mean": float(np.mean(ts)),
-           "phi_evals_per_s": 2.0 / (med * 1e-6), "steps": reps}
+           "phi_evals_per_s": 2.0 / (med * 1e-6), "steps": reps,
+           "kernels": table, "event_overhead_us": overhead,
+           "note": "latency-bound: the vectors (82 KB) live in cache; achieved_gbs is the "
+                   "byte model over the kernel time, not an HBM figure"}
     if cpu:
         s_ = O.SWE(mesh, gamma_h=4e-4)
         st = O.swe_stepper(s_, "exprb42")
@@ -235,14 +454,21 @@ def c1_leg(X, torch, cpu=True, reps=100):
 ADJ_STEPS, ADJ_DT, ADJ_OBS = 12, 1800.0, 5000
 
 
-def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
+FD_TOL = 1e-14
+
+
+def adjoint_leg(X, torch, fd_dirs=8, fd_eps=1e-6, reps=3, cpu=True):
     """Level-7 twin experiment (N = 163842, n = 655368): the gradient of
     L = 1/2 sum (h - y)^2 over 5000 observations of a 12-step exprb42
     trajectory (1800 s steps) with respect to the whole initial state, by
     per-step vector-Jacobian products on the schedules recorded by the
     forward.  Reported: forward time (recording), reverse-sweep time (with
-    its forward recomputation), their ratio, and central differences of the
-    replayed forward along seeded directions."""
+    its forward recomputation) and their ratio at the workload's Krylov
+    tolerance (1e-10); central differences of the replayed forward along
+    seeded directions d = r * (block RMS of u_0), r ~ N(0, 1), against
+    <grad, d> -- with the Krylov tolerance at 1e-14 (forward and adjoint),
+    and, for context, at 1e-10, where the replayed map carries the Krylov
+    error's variation along d (about tol ||v|| / eps)."""
     import numpy as np
     import oracle as O
     from synth import fields as F
@@ -259,24 +485,24 @@ def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
             for k in range(ADJ_STEPS + 1)]
     empty = np.zeros((0, 3))
 
-    def run(u_init, record=False, scheds=None):
+    def run(c, u_init, record=False, scheds=None):
         u = u_init.clone()
         us, rec = [u.clone()], []
-        ctx.reset_history()
+        c.reset_history()
         for k in range(ADJ_STEPS):
             if record or scheds is not None:
-                ctx.schedule_set(empty if record else scheds[k])
-                ctx.schedule_mode(X.RECORD if record else X.REPLAY)
-            ctx.step("exprb42", u, ADJ_DT)
+                c.schedule_set(empty if record else scheds[k])
+                c.schedule_mode(X.RECORD if record else X.REPLAY)
+            c.step("exprb42", u, ADJ_DT)
             if record or scheds is not None:
-                ctx.schedule_mode(X.FREE)
+                c.schedule_mode(X.FREE)
             if record:
-                rec.append(ctx.schedule_get())
+                rec.append(c.schedule_get())
             us.append(u.clone())
         return us, rec
 
     # truth and observations
-    tru, _ = run(torch.tensor(uth, dtype=torch.float64, device=dev))
+    tru, _ = run(ctx, torch.tensor(uth, dtype=torch.float64, device=dev))
     ys = [tru[k][cells[k]] + errs[k] for k in range(ADJ_STEPS + 1)]
 
     def loss(us):
@@ -285,48 +511,57 @@ def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
 
     u0 = torch.tensor(u0h, dtype=torch.float64, device=dev)
 
-    def gradient(us, scheds, stats=None):
+    def gradient(c, us, scheds, stats=None):
         g = torch.zeros(4 * n, dtype=torch.float64, device=dev)
         for k in range(ADJ_STEPS, 0, -1):
             g.index_add_(0, cells[k], us[k][cells[k]] - ys[k])
             if stats is None:
-                g = ctx.step_vjp("exprb42", us[k - 1], ADJ_DT, g, sched=scheds[k - 1])
+                g = c.step_vjp("exprb42", us[k - 1], ADJ_DT, g, sched=scheds[k - 1])
             else:
-                g, st = ctx.step_vjp("exprb42", us[k - 1], ADJ_DT, g, sched=scheds[k - 1],
-                                     return_stats=True)
+                g, st = c.step_vjp("exprb42", us[k - 1], ADJ_DT, g, sched=scheds[k - 1],
+                                   return_stats=True)
                 stats.append(st)
         return g
 
-    us, scheds = run(u0, record=True)            # warm-up: workspaces, substep store
-    gradient(us, scheds)
+    us, scheds = run(ctx, u0, record=True)       # warm-up: workspaces, substep store
+    gradient(ctx, us, scheds)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    us, scheds = run(u0, record=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    g = gradient(us, scheds)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    tf, tr = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        us, scheds = run(ctx, u0, record=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = gradient(ctx, us, scheds)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf.append(t1 - t0)
+        tr.append(t2 - t1)
     st = []
-    gradient(us, scheds, st)
+    gradient(ctx, us, scheds, st)
     L0 = loss(us)
-    fwd, bwd = t1 - t0, t2 - t1
-    # central differences of the replayed forward
-    # central differences of the replayed forward.  eps = 1e-5 (times the
-    # block RMS): at this size the replayed discrete map is not smooth below
-    # ~1e-9 relative (IOM2 near-breakdowns; the oracle shows the same), so
-    # smaller steps measure that roughness rather than the gradient.
+    fwd, bwd = float(np.median(tf)), float(np.median(tr))
     rng = np.random.default_rng(F.config_seed(4))
     scal = np.repeat([np.sqrt(np.mean(u0h[b * n:(b + 1) * n] ** 2)) for b in range(4)], n)
-    fd = []
-    eps = 1e-5
-    for _ in range(fd_dirs):
-        d = torch.tensor(rng.standard_normal(4 * n) * scal, device=dev)
-        lp = loss(run(u0 + eps * d, scheds=scheds)[0])
-        lm = loss(run(u0 - eps * d, scheds=scheds)[0])
-        f = (lp - lm) / (2 * eps)
-        a = float(g @ d)
-        fd.append(abs(f - a) / abs(a))
+    dirs = [torch.tensor(rng.standard_normal(4 * n) * scal, device=dev) for _ in range(fd_dirs)]
+
+    def central_differences(c, g, scheds, ndir):
+        out = []
+        for d in dirs[:ndir]:
+            lp = loss(run(c, u0 + fd_eps * d, scheds=scheds)[0])
+            lm = loss(run(c, u0 - fd_eps * d, scheds=scheds)[0])
+            f = (lp - lm) / (2 * fd_eps)
+            a = float(g @ d)
+            out.append(abs(f - a) / abs(a))
+        return out
+
+    fd_wl = central_differences(ctx, g, scheds, min(2, fd_dirs))
+    ctx_fd = X.Context(mesh, dev, gamma_h=4e-4, tol=FD_TOL, m_max=40)
+    ctx_fd.autotune(1)
+    us_fd, sch_fd = run(ctx_fd, u0, record=True)
+    g_fd = gradient(ctx_fd, us_fd, sch_fd)
+    fd = central_differences(ctx_fd, g_fd, sch_fd, fd_dirs)
+    ctx_fd.close()
     agg = {}
     for s2 in st:
         for c in s2:
@@ -335,8 +570,10 @@ def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
     out = {"workload": "exprb42, 12 steps of 1800 s, level-7 grid (N=163842, n=655368), "
                        "5000 depth observations (twin experiment), FP64, tol 1e-10, m_max 40",
            "loss": L0, "forward_ms": 1e3 * fwd, "reverse_ms": 1e3 * bwd,
-           "adjoint_over_forward": bwd / fwd, "fd_rel_err_max": max(fd) if fd else None,
-           "fd_directions": fd_dirs, "fd_eps": eps, "adjoint_krylov": agg,
+           "adjoint_over_forward": bwd / fwd, "timing": "median of %d runs" % reps,
+           "fd_rel_err_max": max(fd) if fd else None, "fd_rel_err": fd,
+           "fd_directions": fd_dirs, "fd_eps": fd_eps, "fd_krylov_tol": FD_TOL,
+           "fd_rel_err_at_tol_1e-10": fd_wl, "adjoint_krylov": agg,
            "lanes": tune["lanes"]}
     if cpu:
         s = O.SWE(mesh, gamma_h=4e-4)
@@ -351,181 +588,114 @@ def adjoint_leg(X, torch, fd_dirs=4, cpu=True):
     return out
 
 
-def cpu_baseline(mesh, u0_host, steps):
-    import oracle as O
-    s = O.SWE(mesh)
-    evals = 0
-    t0 = time.perf_counter()
-    for method in ("pexprb43", "exprb53"):
-        st = O.swe_stepper(s, method)
-        u = u0_host.copy()
-        for _ in range(steps):
-            u = st.step(u, DT)
-            evals += EVALS_PER_STEP[method]
-    t = time.perf_counter() - t0
-    return {"value": evals / t, "unit": "phi-combination evals/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d steps of pexprb43 and of exprb53 (%d of the 120 evaluations of "
-                      "one bench step), serial C oracle, %.1f s" % (steps, evals, t),
-            "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
-
-
-def _cpu_model():
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3,
+                    help="timed passes of the headline workload (6 exprb53 steps each)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
-    ap.add_argument("--no-c1", action="store_true", help="skip the level-4 single-step leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip every oracle timing")
     ap.add_argument("--lanes", type=int, default=0,
-                    help="lanes per cell for the level-6 workload (0: the library's choice)")
+                    help="lanes per cell of the headline context (0: the library's choice)")
     ap.add_argument("--autotune", action="store_true",
-                    help="tune the level-6 context's lanes before measuring")
+                    help="tune the headline context's lanes before measuring")
+    ap.add_argument("--event-every", type=int, default=JET_EVENT_EVERY,
+                    help="time every N-th launch of each headline kernel with HIP events")
+    ap.add_argument("--no-c1", action="store_true", help="skip the level-4 single-step leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the level-6 leg")
     ap.add_argument("--no-ensemble", action="store_true")
-    ap.add_argument("--no-jet", action="store_true")
-    ap.add_argument("--jet-only", action="store_true",
-                    help="run only the level-8 leg (for profiling it alone)")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--fd-dirs", type=int, default=8)
+    ap.add_argument("--fd-eps", type=float, default=1e-6)
+    ap.add_argument("--jet-only", action="store_true",
+                    help="run only the headline level-8 leg (for profiling it alone)")
+    ap.add_argument("--c1-only", action="store_true", help="run only the level-4 leg")
+    ap.add_argument("--c2-only", action="store_true", help="run only the level-6 leg")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the 64-member level-6 ensemble leg")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the level-7 adjoint leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 64 MiB device-to-device copies (the reference "
                          "kernel for scaling PMC byte counters)")
-    ap.add_argument("--adjoint-only", action="store_true",
-                    help="run only the level-7 adjoint leg")
-    ap.add_argument("--ensemble-only", action="store_true",
-                    help="run only the 64-member level-6 ensemble leg")
-    ap.add_argument("--event-every", type=int, default=64,
-                    help="time every N-th launch of each kernel of the level-6 workload with HIP "
-                         "events (each timed launch adds two event records; 16 costs the "
-                         "measured rate about 5 %%, 64 is within noise of none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1805_02144_amd as X
-    from synth import fields as F
-    from synth.mesh import get_mesh
 
-    if args.jet_only:
-        print(json.dumps({"level8_jet": jet_leg(X, torch, JET_EVENT_EVERY)}))
+    cpu = not args.no_cpu
+    only = None
+    for name in ("c1", "c2", "ensemble", "adjoint"):
+        if getattr(args, name + "_only"):
+            only = name
+    if only:
+        leg = {"c1": lambda: c1_leg(X, torch, cpu=cpu),
+               "c2": lambda: c2_leg(X, torch, cpu=cpu),
+               "ensemble": lambda: ensemble_leg(X, torch, cpu=cpu),
+               "adjoint": lambda: adjoint_leg(X, torch, fd_dirs=args.fd_dirs,
+                                              fd_eps=args.fd_eps, cpu=cpu)}[only]()
+        print(json.dumps({only: leg}))
         if args.copy_calibration:
             copy_calibration(torch)
         return
-    if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_leg(X, torch, cpu=not args.no_cpu)}))
+
+    log("headline: level-8 jet, %d timed passes" % args.steps)
+    jet = jet_leg(X, torch, args.steps, args.warmup, args.event_every, args.lanes, args.autotune)
+    if args.jet_only:
+        print(json.dumps({"level8_jet": jet}))
+        if args.copy_calibration:
+            copy_calibration(torch)
         return
-    if args.ensemble_only:
-        print(json.dumps({"ensemble": ensemble_leg(X, torch, get_mesh(6))}))
-        return
-
-    level = 6
-    mesh = get_mesh(level)
-    n = len(mesh["xyz"])
-    u0_host = F.initial_state("c2_l6_24x3600")
-    ctx = X.Context(mesh, "cuda:0", gamma_h=4e-4, tol=1e-10, m_max=40, lanes=args.lanes)
-    tune = ctx.autotune(1) if args.autotune else None
-    u0 = torch.tensor(u0_host, dtype=torch.float64, device="cuda:0")
-    u = torch.empty_like(u0)
-
-    for _ in range(args.warmup):
-        run_pass(ctx, u, u0, torch)
-    torch.cuda.synchronize()
-
-    ctx.profile(args.event_every)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    total_evals = 0
-    all_stats = []
-    for _ in range(args.steps):
-        e, st = run_pass(ctx, u, u0, torch)
-        total_evals += e
-        all_stats += st
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = ctx.profile_get()
-    ctx.profile(0)
-    elapsed = t1 - t0
-    value = total_evals / elapsed
-
-    # roofline of the fused Jacobian product + IOM2 dots
-    ms, timed_n, all_n = prof["jv_iom2"]
-    avg_s = ms * 1e-3 / max(timed_n, 1)
-    achieved = JV_IOM2_BYTES_PER_CELL * n / avg_s / 1e9 if timed_n else 0.0
-    traffic = measured_traffic()
-    roofline = {"bound": "hbm", "kernel": "k_jv<kEpiIom2>", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic,
-                "traffic_over_algorithmic": (traffic / (JV_IOM2_BYTES_PER_CELL * n)
-                                             if traffic else None),
-                "avg_us": avg_s * 1e6, "launches": all_n,
-                "timed_launches": timed_n, "bytes_per_cell": JV_IOM2_BYTES_PER_CELL, "cells": n}
-    avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
-    counts = {k: v[2] for k, v in prof.items()}
-    est = {k: avg[k] * counts[k] for k in prof}            # ms, all launches
-    tot_ms = sum(est.values())
-    kernels = {k: {"avg_us": 1e3 * avg[k], "launches": counts[k], "timed": prof[k][1],
-                   "est_ms": est[k], "share": est[k] / tot_ms if tot_ms else 0.0} for k in prof}
-    agg = {}
-    for st in all_stats:
-        for c in st:
-            for k, v in c.items():
-                if k in ("attempts", "rejected", "accepted", "matvecs", "expms", "sum_m"):
-                    agg[k] = agg.get(k, 0) + v
-    per_pass = {k: v / args.steps for k, v in agg.items()}
-
-    c1 = None if args.no_c1 else c1_leg(X, torch, cpu=not args.no_cpu)
-    ens = None if args.no_ensemble else ensemble_leg(X, torch, mesh)
-    jet = None if args.no_jet else jet_leg(X, torch, JET_EVENT_EVERY)
-    adj = None if args.no_adjoint else adjoint_leg(X, torch, cpu=not args.no_cpu)
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(mesh, u0_host, args.cpu_steps)
-
+    legs = {}
+    if not args.no_c2:
+        log("level-6 leg")
+        legs["level6_c2"] = c2_leg(X, torch, cpu=cpu)
+    if not args.no_c1:
+        log("level-4 leg")
+        legs["level4_c1"] = c1_leg(X, torch, cpu=cpu)
+    if not args.no_ensemble:
+        log("ensemble leg")
+        legs["ensemble"] = ensemble_leg(X, torch, cpu=cpu)
+    if not args.no_adjoint:
+        log("adjoint leg")
+        legs["adjoint"] = adjoint_leg(X, torch, fd_dirs=args.fd_dirs, fd_eps=args.fd_eps, cpu=cpu)
+    cpu_base = None
+    if cpu:
+        log("cpu baseline")
+        cpu_base = cpu_baseline_jet(host_threads())
+    steps = args.steps
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": jet["value"],
         "unit": "phi-combination evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * jet["elapsed_s"] / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
-        "data": "synthetic (seeded level-6 solid-body flow + Gaussian bump)",
-        "config": {"workload": "pexprb43 and exprb53, 24 steps of 3600 s each, level-6 "
-                               "icosahedral grid (N=40962, n=163848), FP64, tol 1e-10, m_max 40",
-                   "grid_level": level, "cells": n, "unknowns": 4 * n,
-                   "evals_per_step": sum(EVALS_PER_STEP.values()) * STEPS_PER_METHOD},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "kernels": kernels,
-        "krylov_per_step": per_pass,
-        "lanes": {"requested": args.lanes, "autotuned": tune},
-        "level4_c1": c1,
-        "ensemble": ens,
-        "level8_jet": jet,
-        "adjoint": adj,
-        "device_time_fraction": (tot_ms * 1e-3) / elapsed,
+        "data": "synthetic (seeded level-8 balanced zonal jet + Gaussian bump)",
+        "config": {"workload": "exprb53, 6 steps of 1800 s, level-8 icosahedral grid "
+                               "(N=655362, n=2621448), balanced zonal jet (80 m/s, 20N-70N) + "
+                               "120 m Gaussian bump, gamma_h 1.25e-2, FP64, tol 1e-10, m_max 40",
+                   "grid_level": 8, "cells": jet["n"], "unknowns": 4 * jet["n"],
+                   "evals_per_step": JET_STEPS * JET_EVALS_PER_STEP},
+        "roofline": jet["roofline"],
+        "cpu_baseline": cpu_base,
+        "kernels": jet["kernels"],
+        "event_overhead_us": jet["event_overhead_us"],
+        "device_time_fraction": jet["device_time_fraction"],
+        "lanes": {"requested": args.lanes, "autotuned": jet["autotuned"]},
     }
+    out.update(legs)
     print(json.dumps(out))
-    ctx.close()
     if args.copy_calibration:
         copy_calibration(torch)
 

@@ -25,7 +25,7 @@ EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", 
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
            "xrb_ktv", "xrb_step_vjp", "xrb_step_tableau", "xrb_mesh_info",
-           "xrb_schedule_set_member", "xrb_schedule_get_member"]
+           "xrb_schedule_set_member", "xrb_schedule_get_member", "xrb_profile_overhead"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
@@ -169,6 +169,7 @@ def lib():
         L.xrb_schedule_set_member.argtypes = [vp, C.c_int, _dp, C.c_int]
         L.xrb_schedule_get_member.argtypes = [vp, C.c_int, _dp, C.c_int, C.POINTER(C.c_int)]
         L.xrb_profile.argtypes = [vp, C.c_int]
+        L.xrb_profile_overhead.argtypes = [vp, C.c_int, _dp]
         L.xrb_profile_get.argtypes = [vp, C.c_int, _dp, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int64)]
         for f in EXPORTS:
@@ -433,6 +434,13 @@ class Context:
         """Time every `every`-th launch of each kernel with HIP events
         (counters zeroed); every = 0 disables."""
         self._check(lib().xrb_profile(self.h, int(every)))
+
+    def profile_overhead(self, reps=200):
+        """Microseconds one event pair adds to a timed launch (xrb_profile_overhead)."""
+        self._stream()
+        us = C.c_double()
+        self._check(lib().xrb_profile_overhead(self.h, int(reps), C.byref(us)))
+        return us.value
 
     def profile_get(self):
         """{kernel: (device ms over the timed launches, timed launches, all launches)}."""

@@ -344,3 +344,65 @@ def test_c5_reverse(X, k):
     if k == 1:
         ctx.close()
         _C5.clear()
+
+
+def test_c5_central_differences(X):
+    """Central differences of the replayed level-7 twin experiment along 8
+    seeded directions (eps = 1e-6 times each block's RMS) against the GPU
+    gradient, with the Krylov tolerance at 1e-14 for the forward and the
+    adjoint: at the workload's 1e-10 the replayed map carries the Krylov
+    approximation error, whose variation along a direction is of order
+    tol ||v|| / eps and swamps a 1e-6 comparison (the oracle shows the same
+    roughness, and it shrinks with the tolerance)."""
+    import torch
+    level, steps, dt, eps = 7, 12, 1800.0, 1e-6
+    mesh = get_mesh(level)
+    n = len(mesh["xyz"])
+    u0h, uth, ost, oce, oer = F.adjoint_twin(level, F.config_seed(4), steps, 5000)
+    ctx = X.Context(mesh, "cuda:0", tol=1e-14)
+    cells = [torch.tensor(3 * n + oce[ost == k], device="cuda:0") for k in range(steps + 1)]
+
+    def run(u_init, record=False, scheds=None):
+        u = torch.tensor(u_init, device="cuda:0") if isinstance(u_init, np.ndarray) \
+            else u_init.clone()
+        us, rec = [u.clone()], []
+        ctx.reset_history()
+        for k in range(steps):
+            if record or scheds is not None:
+                ctx.schedule_set(np.zeros((0, 3)) if record else scheds[k])
+                ctx.schedule_mode(X.RECORD if record else X.REPLAY)
+            try:
+                ctx.step("exprb42", u, dt)
+            finally:
+                ctx.schedule_mode(X.FREE)
+            if record:
+                rec.append(ctx.schedule_get())
+            us.append(u.clone())
+        return us, rec
+
+    tru, _ = run(uth)
+    ys = [tru[k][cells[k]] + torch.tensor(oer[ost == k], device="cuda:0")
+          for k in range(steps + 1)]
+
+    def loss(us):
+        return sum(0.5 * float(((us[k][cells[k]] - ys[k]) ** 2).sum())
+                   for k in range(1, steps + 1))
+
+    u0 = torch.tensor(u0h, device="cuda:0")
+    us, scheds = run(u0, record=True)
+    g = torch.zeros(4 * n, dtype=torch.float64, device="cuda:0")
+    for k in range(steps, 0, -1):
+        g.index_add_(0, cells[k], us[k][cells[k]] - ys[k])
+        g = ctx.step_vjp("exprb42", us[k - 1], dt, g, sched=scheds[k - 1])
+    rng = np.random.default_rng(F.config_seed(4))
+    scal = np.repeat([np.sqrt(np.mean(u0h[b * n:(b + 1) * n] ** 2)) for b in range(4)], n)
+    errs = []
+    for _ in range(8):
+        d = torch.tensor(rng.standard_normal(4 * n) * scal, device="cuda:0")
+        lp = loss(run(u0 + eps * d, scheds=scheds)[0])
+        lm = loss(run(u0 - eps * d, scheds=scheds)[0])
+        a = float(g @ d)
+        errs.append(abs((lp - lm) / (2 * eps) - a) / abs(a))
+    say("C5 central differences (tol 1e-14, eps 1e-6):", " ".join("%.1e" % e for e in errs))
+    ctx.close()
+    assert max(errs) <= 1e-6

@@ -25,7 +25,8 @@ EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", 
            "xrb_step_stats", "xrb_reset_history", "xrb_schedule_mode", "xrb_schedule_set",
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
            "xrb_ktv", "xrb_step_vjp", "xrb_step_tableau", "xrb_mesh_info",
-           "xrb_schedule_set_member", "xrb_schedule_get_member", "xrb_profile_overhead"]
+           "xrb_schedule_set_member", "xrb_schedule_get_member", "xrb_profile_overhead",
+           "xrb_jv_static"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
@@ -149,6 +150,7 @@ def lib():
         L.xrb_mesh_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(_dp), C.POINTER(_dp)]
         L.xrb_rhs.argtypes = [vp, vp, vp]
         L.xrb_jv.argtypes = [vp, vp, vp, vp]
+        L.xrb_jv_static.argtypes = [vp, vp, vp, vp]
         L.xrb_jtv.argtypes = [vp, vp, vp, vp]
         L.xrb_ktv.argtypes = [vp, vp, vp, vp]
         L.xrb_diagnostics.argtypes = [vp, vp, _dp]
@@ -282,6 +284,22 @@ class Context:
         u, v = self._vec(u), self._vec(v)
         out = self.empty()
         self._check(lib().xrb_jv(self.h, _ptr(u), _ptr(v), _ptr(out)))
+        return out
+
+    def jv_static(self, u, v, out=None):
+        """J(u) v through the entry point that allocates nothing (its
+        intermediates live in the library's static device scratch); `out`
+        may be given so that the caller allocates nothing either."""
+        self._stream()
+        u, v = self._vec(u), self._vec(v)
+        if out is None:
+            out = self.empty()
+        elif not (self.torch.is_tensor(out) and out.dtype == self.torch.float64
+                  and out.device == self.torch.device(self.device) and out.is_contiguous()
+                  and out.numel() == self.N):
+            raise ValueError("out: a contiguous float64 tensor of length %d on %s expected"
+                             % (self.N, self.device))
+        self._check(lib().xrb_jv_static(self.h, _ptr(u), _ptr(v), _ptr(out)))
         return out
 
     def jtv(self, u, w):

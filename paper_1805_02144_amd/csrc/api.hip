@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "reduce.h"
@@ -144,7 +145,47 @@ struct xrb_ctx {
     std::vector<double> h_xyz, h_area;
     // first device-side failure since the last xrb_sync (0 = none)
     int latched = 0;
+    int dev = 0;   // HIP device current at xrb_create
 };
+
+// Device scratch of the allocation-free Jacobian product (xrb_jv_static):
+// cell-major copies of u and v, the product before its relayout, L v and
+// eta -- kStaticPerCell doubles per cell, at most kStaticScratchDoubles in
+// all (96 MiB: up to 740 171 cells, so the level-8 grid of 655 362 cells
+// fits).  Every GPU that loads the library holds one copy until the process
+// ends.  Host code never passes the array's name to a kernel: it takes the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchDoubles = (size_t)96 << 17;
+constexpr size_t kStaticPerCell = 17;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+
+// Device addresses of `scratch`, one per device ordinal, resolved by
+// xrb_create with the context's device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Resolve the current device's copy of `scratch` (once per device).
+void resolve_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+        g_scratch_ptr[dev] = (double *)ptr;
+    else
+        (void)hipGetLastError();   // leave the table empty; xrb_jv_static reports it
+}
+
+double *scratch_of(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -1467,6 +1508,11 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     if (!ctx) return XRB_ENOMEM;
     ctx->prm = *params;
     ctx->stream = (hipStream_t)stream;
+    if (hipGetDevice(&ctx->dev) != hipSuccess) {
+        delete ctx;
+        return XRB_EDEVICE;
+    }
+    resolve_scratch(ctx->dev);
     HostGeometry geo;
     int rc = build_geometry(*mesh, *params, geo, ctx->err);
     if (rc) {
@@ -1591,6 +1637,34 @@ xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
     launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
     jv_plain(ctx, ctx->one, uc, vc, io_vec(ctx, kIoOutSlot), false);
     io_out(ctx, kIoOutSlot, jv);
+    HIPCHK(hipGetLastError());
+    return XRB_OK;
+}
+
+xrb_status xrb_jv_static(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
+    if (!ctx || !u || !v || !jv || jv == u || jv == v)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "jv_static: bad pointers");
+    if (kStaticPerCell * (size_t)ctx->n > kStaticScratchDoubles)
+        return (xrb_status)fail(ctx, XRB_EINVAL,
+                                "jv_static: the grid exceeds the static scratch (at most 740171 cells)");
+    double *s = scratch_of(ctx->dev);
+    if (!s) return (xrb_status)fail(ctx, XRB_EDEVICE, "jv_static: no device address for the scratch");
+    const size_t n4 = (size_t)ctx->n4;
+    double *uc = s, *vc = s + n4, *oc = s + 2 * n4, *lap = s + 3 * n4, *eta = s + 4 * n4;
+    Batch b;   // one state, no predicates, no step-size scaling
+    launch_relayout(ctx->n, 1, u, 0, uc, 0, true, ctx->stream);
+    launch_relayout(ctx->n, 1, v, 0, vc, 0, true, ctx->stream);
+    launch_linearize(ctx->M, uc, eta, b, ctx->stream);
+    if (!jv_fuses_lap(ctx->M, 1)) launch_lap4(ctx->M, vc, lap, b, ctx->stream);
+    JvArgs a;
+    a.u = uc;
+    a.eta = eta;
+    a.x = vc;
+    a.lx = lap;
+    a.dt = 1.0;
+    a.out = oc;
+    launch_jv(ctx->M, a, kEpiNone, b, ctx->stream);
+    launch_relayout(ctx->n, 1, oc, 0, jv, 0, false, ctx->stream);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }

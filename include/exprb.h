@@ -165,11 +165,12 @@ xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv);
 /* xrb_jv for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same kernels and the same bits as xrb_jv, with its intermediates (the
- * cell-major copies of u and v, eta, L v and the product before its relayout,
- * 136 bytes per cell) in a static device array of 96 MiB that the library
- * holds on every GPU it runs on until the process ends.  The call allocates
- * nothing; the context must exist (xrb_create allocates).  Grids of more than
- * 740 171 cells return XRB_EINVAL before any work.  Every call on one GPU
+ * cell-major copies of u and v, eta, the linearisation record, L v and the
+ * product before its relayout, 200 bytes per cell) in a static device array
+ * of 128 MiB that the library holds on every GPU it runs on until the
+ * process ends.  The call allocates nothing; the context must exist
+ * (xrb_create allocates).  Grids of more than 671 088 cells return
+ * XRB_EINVAL before any work.  Every call on one GPU
  * shares that array: calls that overlap on one GPU (two streams, two
  * contexts, two threads) race and must be serialised by the caller.
  * u, v, jv: device, length 4N; jv must not alias u or v. */

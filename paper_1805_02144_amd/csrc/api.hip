@@ -63,6 +63,7 @@ struct Work {
     double *y = nullptr;        // substep solution
     double *lap = nullptr;      // L x scratch
     double *eta = nullptr;      // V.u + f at the linearisation point
+    double *rec = nullptr;      // per-cell record (u, centre, eta) there, 8 doubles per cell
     double *stage = nullptr;    // S_COUNT stage vectors
     PhiCtl *ctl = nullptr;      // [nm]
     double *dot_parts = nullptr, *nrm_parts = nullptr, *v_parts = nullptr, *vnorm2 = nullptr;
@@ -149,14 +150,15 @@ struct xrb_ctx {
 };
 
 // Device scratch of the allocation-free Jacobian product (xrb_jv_static):
-// cell-major copies of u and v, the product before its relayout, L v and
-// eta -- kStaticPerCell doubles per cell, at most kStaticScratchDoubles in
-// all (96 MiB: up to 740 171 cells, so the level-8 grid of 655 362 cells
-// fits).  Every GPU that loads the library holds one copy until the process
-// ends.  Host code never passes the array's name to a kernel: it takes the
-// device address that hipGetSymbolAddress returns for the current device.
-constexpr size_t kStaticScratchDoubles = (size_t)96 << 17;
-constexpr size_t kStaticPerCell = 17;
+// cell-major copies of u and v, the product before its relayout, L v, eta
+// and the linearisation record -- kStaticPerCell doubles per cell, at most
+// kStaticScratchDoubles in all (128 MiB: up to 671 088 cells, so the
+// level-8 grid of 655 362 cells fits).  Every GPU that loads the library
+// holds one copy until the process ends.  Host code never passes the
+// array's name to a kernel: it takes the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchDoubles = (size_t)128 << 17;
+constexpr size_t kStaticPerCell = 25;
 static __device__ __align__(256) double scratch[kStaticScratchDoubles];
 
 namespace {
@@ -329,6 +331,7 @@ void jv_plain(xrb_ctx *ctx, const Work &W, const double *u, const double *x, dou
     JvArgs a;
     a.u = u;
     a.eta = W.eta;
+    a.rec = W.rec;
     a.x = x;
     a.lx = W.lap;
     a.dt = 1.0;
@@ -599,6 +602,7 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
                         timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, wptr[j - 1], W.lap, bp, s); });
                     a.u = u;
                     a.eta = W.eta;
+                    a.rec = W.rec;
                     a.x = wptr[j - 1];
                     a.lx = W.lap;
                     a.out = dst;
@@ -634,6 +638,7 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             JvArgs a;
             a.u = u;
             a.eta = W.eta;
+            a.rec = W.rec;
             a.x = rj;
             a.lx = W.lap;
             a.out = rn;
@@ -775,8 +780,8 @@ int free_work(Work &W) {
 int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
     const int64_t n4 = ctx->n4;
     const int mmax = ctx->prm.m_max;
-    // member block: basis, recurrence, y, lap, eta, stages
-    const int64_t nvec = (mmax + 1) + kPmax + 1 + 1 + 1 + S_COUNT;
+    // member block: basis, recurrence, y, lap, eta, record (two vectors), stages
+    const int64_t nvec = (mmax + 1) + kPmax + 1 + 1 + 1 + 2 + S_COUNT;
     W.nm = nm;
     W.ws = nm > 1 ? nvec * n4 : 0;
     const int64_t member_doubles = nvec * n4;
@@ -825,6 +830,8 @@ int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
     p += n4;
     W.eta = p;
     p += n4;
+    W.rec = p;
+    p += 2 * n4;
     W.stage = p;
     ck(hipMemset(W.base, 0, sizeof(double) * member_doubles * nm));
     ck(hipMemset(W.ctl, 0, sizeof(PhiCtl) * nm));
@@ -854,7 +861,7 @@ int scheme_step(xrb_ctx *ctx, Work &W, int method, double *u) {
     };
     rhs_plain(ctx, W, u, Fn);
     lincomb(ctx, W, v, {Fn}, {1.0}, 1u);                      // v = dt F(u_n)
-    launch_linearize(ctx->M, u, W.eta, batch_of(W), s);
+    launch_linearize(ctx->M, u, W.eta, W.rec, batch_of(W), s);
     // D = F(U) - Fn - J_n (U - u_n)
     auto nonlin = [&](const double *U, double *D) {
         lincomb(ctx, W, t1, {U, u}, {1.0, -1.0});
@@ -1030,7 +1037,7 @@ int tableau_step(xrb_ctx *ctx, Work &W, const xrb_tableau &T, double *u) {
     std::vector<xrb_phi_stats> tmp(nm);
     rhs_plain(ctx, W, u, Fn);
     lincomb(ctx, W, v, {Fn}, {1.0}, 1u);                      // v = dt F(u_n)
-    launch_linearize(ctx->M, u, W.eta, batch_of(W), s);
+    launch_linearize(ctx->M, u, W.eta, W.rec, batch_of(W), s);
     const Batch b = batch_of(W);
     // out = u_n + sum of the nonzero output terms
     auto combine = [&](double *out, const double (*w)[XRB_TAB_OUT]) {
@@ -1413,7 +1420,7 @@ int vjp_exprb42(xrb_ctx *ctx, const double *u, double dt, const double *ubar_np1
     // forward, keeping both calls' substeps
     rhs_plain(ctx, W, u, Fn);
     lincomb(ctx, W, v, {Fn}, {1.0}, 1u);
-    launch_linearize(ctx->M, u, W.eta, batch_of(W), s);
+    launch_linearize(ctx->M, u, W.eta, W.rec, batch_of(W), s);
     {
         const double r1[1] = {0.75};
         const double *vi[2] = {nullptr, v};
@@ -1525,9 +1532,16 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     const size_t nd = (size_t)n;
     ctx->h_xyz.assign(mesh->xyz, mesh->xyz + 3 * nd);
     ctx->h_area.swap(geo.area);
-    // geometry in one allocation: 2 x [n][6] edge scalars, [n][4] cell records, [n][6] int32
+    // chunk tables of the LDS-staged product on grids whose reducing products
+    // run several passes per block
+    if ((size_t)n > (size_t)kRedBlocks * 128) build_halo(geo);
+    const size_t nh = geo.hoff.size(), nhid = geo.hids.size();
+    // geometry in one allocation: 2 x [n][6] edge scalars, [n][4] cell
+    // records, [n][6] int32 neighbours, then the chunk tables (int32 offsets
+    // and halo ids, uint16 local ids)
     const size_t dbl = 2 * 6 * nd + 4 * nd;
-    const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t);
+    const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t) +
+                         (nh + nhid) * sizeof(int32_t) + geo.lnbr.size() * sizeof(uint16_t);
     if (hipMalloc(&ctx->geo_mem, bytes) != hipSuccess) {
         delete ctx;
         return XRB_ENOMEM;
@@ -1545,16 +1559,20 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
         }
     };
     double *g = (double *)ctx->geo_mem;
-    const std::vector<double> *srcs[2] = {&geo.alpha, &geo.cl};
-    double *dst[2];
-    for (int k = 0; k < 2; ++k) {
-        dst[k] = g + (size_t)k * 6 * nd;
-        ck(hipMemcpy(dst[k], srcs[k]->data(), sizeof(double) * 6 * nd, hipMemcpyHostToDevice));
-    }
+    double *alpha = g, *cl = g + 6 * nd;
+    ck(hipMemcpy(alpha, geo.alpha.data(), sizeof(double) * 6 * nd, hipMemcpyHostToDevice));
+    ck(hipMemcpy(cl, geo.cl.data(), sizeof(double) * 6 * nd, hipMemcpyHostToDevice));
     double *cen = g + 2 * 6 * nd;     // byte offset 96 n: 16-byte aligned
     ck(hipMemcpy(cen, geo.cen.data(), sizeof(double) * 4 * nd, hipMemcpyHostToDevice));
     int32_t *nb = (int32_t *)(g + dbl);
     ck(hipMemcpy(nb, geo.nbr.data(), sizeof(int32_t) * 6 * nd, hipMemcpyHostToDevice));
+    int32_t *hoff = nb + 6 * nd, *hids = hoff + nh;
+    uint16_t *lnbr = (uint16_t *)(hids + nhid);
+    if (nh) {
+        ck(hipMemcpy(hoff, geo.hoff.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice));
+        if (nhid) ck(hipMemcpy(hids, geo.hids.data(), sizeof(int32_t) * nhid, hipMemcpyHostToDevice));
+        ck(hipMemcpy(lnbr, geo.lnbr.data(), sizeof(uint16_t) * geo.lnbr.size(), hipMemcpyHostToDevice));
+    }
     if (rc) {
         free_work(ctx->one);
         (void)hipFree(ctx->geo_mem);
@@ -1564,9 +1582,16 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     DevMesh &M = ctx->M;
     M.n = n;
     M.nbr = nb;
-    M.alpha = dst[0];
-    M.cl = dst[1];
+    M.alpha = alpha;
+    M.cl = cl;
     M.cen = cen;
+    if (nh) {
+        M.halo.hoff = hoff;
+        M.halo.hids = hids;
+        M.halo.lnbr = lnbr;
+        M.halo.nchunks = (int)nh - 1;
+    }
+    M.half_r = 0.5 * params->radius;
     M.lanes = params->lanes ? params->lanes : stencil_lanes(n);
     // batches of small grids take two lanes per cell (same bits as eight)
     M.lanes_batch = (!params->lanes && M.lanes == 8 && n <= 65536) ? 2 : M.lanes;
@@ -1634,7 +1659,7 @@ xrb_status xrb_jv(xrb_ctx *ctx, const double *u, const double *v, double *jv) {
         return (xrb_status)fail(ctx, XRB_EINVAL, "jv: bad pointers");
     if (int rc = io_ensure(ctx)) return (xrb_status)rc;
     const double *uc = io_in(ctx, 0, u), *vc = io_in(ctx, 1, v);
-    launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    launch_linearize(ctx->M, uc, ctx->one.eta, ctx->one.rec, batch_of(ctx->one), ctx->stream);
     jv_plain(ctx, ctx->one, uc, vc, io_vec(ctx, kIoOutSlot), false);
     io_out(ctx, kIoOutSlot, jv);
     HIPCHK(hipGetLastError());
@@ -1646,19 +1671,21 @@ xrb_status xrb_jv_static(xrb_ctx *ctx, const double *u, const double *v, double 
         return (xrb_status)fail(ctx, XRB_EINVAL, "jv_static: bad pointers");
     if (kStaticPerCell * (size_t)ctx->n > kStaticScratchDoubles)
         return (xrb_status)fail(ctx, XRB_EINVAL,
-                                "jv_static: the grid exceeds the static scratch (at most 740171 cells)");
+                                "jv_static: the grid exceeds the static scratch (at most 671088 cells)");
     double *s = scratch_of(ctx->dev);
     if (!s) return (xrb_status)fail(ctx, XRB_EDEVICE, "jv_static: no device address for the scratch");
     const size_t n4 = (size_t)ctx->n4;
-    double *uc = s, *vc = s + n4, *oc = s + 2 * n4, *lap = s + 3 * n4, *eta = s + 4 * n4;
+    double *uc = s, *vc = s + n4, *oc = s + 2 * n4, *lap = s + 3 * n4, *rec = s + 4 * n4;
+    double *eta = s + 6 * n4;
     Batch b;   // one state, no predicates, no step-size scaling
     launch_relayout(ctx->n, 1, u, 0, uc, 0, true, ctx->stream);
     launch_relayout(ctx->n, 1, v, 0, vc, 0, true, ctx->stream);
-    launch_linearize(ctx->M, uc, eta, b, ctx->stream);
+    launch_linearize(ctx->M, uc, eta, rec, b, ctx->stream);
     if (!jv_fuses_lap(ctx->M, 1)) launch_lap4(ctx->M, vc, lap, b, ctx->stream);
     JvArgs a;
     a.u = uc;
     a.eta = eta;
+    a.rec = rec;
     a.x = vc;
     a.lx = lap;
     a.dt = 1.0;
@@ -1676,7 +1703,7 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out) 
     if (!rc) rc = io_ensure(ctx);
     if (rc) return (xrb_status)rc;
     const double *uc = io_in(ctx, 0, u), *wc = io_in(ctx, 1, w);
-    launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    launch_linearize(ctx->M, uc, ctx->one.eta, ctx->one.rec, batch_of(ctx->one), ctx->stream);
     jtv_plain(ctx, uc, ctx->one.eta, wc, io_vec(ctx, kIoOutSlot), 0, nullptr, nullptr);
     io_out(ctx, kIoOutSlot, out);
     HIPCHK(hipGetLastError());
@@ -1706,9 +1733,10 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
     const hipStream_t s = ctx->stream;
     HIPCHK(hipStreamSynchronize(s));
     const size_t n4 = (size_t)ctx->n4;
-    // per member: u, x, L x, out, R_{j-1}, eta; then the dot partials.  The
-    // data are zeros: the kernels' timing does not depend on the values.
-    const size_t ws = 6 * n4;
+    // per member: u, x, L x, out, R_{j-1}, eta, the linearisation record
+    // (two vectors); then the dot partials.  The data are zeros: the kernels'
+    // timing does not depend on the values.
+    const size_t ws = 8 * n4;
     const size_t total = ws * nm_batch + (size_t)kPartStride * nm_batch;
     double *buf = nullptr;
     if (hipMalloc((void **)&buf, sizeof(double) * total) != hipSuccess)
@@ -1725,6 +1753,7 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
     a.out = buf + 3 * n4;
     a.rjm1 = buf + 4 * n4;
     a.eta = buf + 5 * n4;
+    a.rec = buf + 6 * n4;
     a.dot_out = buf + ws * nm_batch;
     a.dt = 1.0;
     const DevMesh saved = ctx->M;
@@ -1897,7 +1926,7 @@ xrb_status xrb_phi_combo(xrb_ctx *ctx, double dt, const double *u, int p, const 
     double *wc[kIoOut];
     for (int l = 0; l <= p; ++l) vc[l] = v[l] ? io_in(ctx, 1 + l, v[l]) : nullptr;
     for (int i = 0; i < ns; ++i) wc[i] = io_vec(ctx, kIoOutSlot + i);
-    launch_linearize(ctx->M, uc, ctx->one.eta, batch_of(ctx->one), ctx->stream);
+    launch_linearize(ctx->M, uc, ctx->one.eta, ctx->one.rec, batch_of(ctx->one), ctx->stream);
     rc = phi_batch(ctx, ctx->one, uc, p, vc, ns, rho, wc, -1, stats);
     if (rc) return (xrb_status)rc;
     for (int i = 0; i < ns; ++i) io_out(ctx, kIoOutSlot + i, w_out[i]);

@@ -16,14 +16,23 @@
 // (|x_i + x_j| |x_j - x_i|): the kernels rebuild a_s and b_s from two
 // scalars per edge and the centres they already load,
 //   alpha_s = l_e / (2 A_i |x_j - x_i|),  beta_s = 2 alpha_s / |x_i + x_j|,
-// of which alpha_s is stored and beta_s formed in the kernels.
-// Pentagon slot 5 gets zero weights.
+// of which alpha_s is stored and beta_s formed in the kernels (the
+// LDS-staged product forms alpha_s as well, as c_s (a / 2) asin(y) / y with
+// the chord 2y = |x_j - x_i|, since d_e = 2 a asin(y)).  Pentagon slot 5
+// gets zero weights.
+//
+// For the LDS-staged product of large grids, build_halo cuts the cells into
+// chunks of kChunk consecutive cells and lists each chunk's one-ring halo.
+#include <algorithm>
 #include <cmath>
 
 #include "xrb_internal.h"
 
 namespace xrb {
 namespace {
+
+// the range of the kernels' asin series (kAsinY2Max in stencil_common.h)
+constexpr double kAsinY2MaxHost = 0.1;
 
 struct V3 {
     double x, y, z;
@@ -108,6 +117,53 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
     const double dxbar = std::sqrt(4.0 * M_PI * R * R / (double)n);
     geo.nu = prm.gamma_h * dxbar * dxbar * dxbar * dxbar / prm.dt_e;
     return XRB_OK;
+}
+
+void build_halo(HostGeometry &geo) {
+    geo.hoff.clear();
+    geo.hids.clear();
+    geo.lnbr.clear();
+    const int n = geo.n;
+    const int nch = (n + kChunk - 1) / kChunk;
+    std::vector<int32_t> hoff(nch + 1, 0), hids;
+    std::vector<uint16_t> lnbr(6 * (size_t)n, 0);
+    // the product's alpha series holds for half-chords y with y^2 <= kAsinY2MaxHost
+    for (int i = 0; i < n; ++i)
+        for (int s = 0; s < 6; ++s) {
+            const int j = geo.nbr[6 * (size_t)i + s];
+            double y2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double dx = geo.cen[4 * (size_t)j + c] - geo.cen[4 * (size_t)i + c];
+                y2 += 0.25 * dx * dx;
+            }
+            if (y2 > kAsinY2MaxHost) return;   // tables stay empty: the product keeps its gathers
+        }
+    std::vector<int32_t> ring;
+    for (int k = 0; k < nch; ++k) {
+        const int c0 = k * kChunk, c1 = std::min(n, c0 + kChunk);
+        ring.clear();
+        for (int i = c0; i < c1; ++i)
+            for (int s = 0; s < 6; ++s) {
+                const int j = geo.nbr[6 * (size_t)i + s];
+                if (j < c0 || j >= c1) ring.push_back(j);
+            }
+        std::sort(ring.begin(), ring.end());
+        ring.erase(std::unique(ring.begin(), ring.end()), ring.end());
+        if ((int)ring.size() > kHaloMax) return;   // tables stay empty: the product keeps its gathers
+        for (int i = c0; i < c1; ++i)
+            for (int s = 0; s < 6; ++s) {
+                const int j = geo.nbr[6 * (size_t)i + s];
+                const int lj = (j >= c0 && j < c1)
+                                   ? j - c0
+                                   : kChunk + (int)(std::lower_bound(ring.begin(), ring.end(), j) - ring.begin());
+                lnbr[6 * (size_t)i + s] = (uint16_t)lj;
+            }
+        hids.insert(hids.end(), ring.begin(), ring.end());
+        hoff[k + 1] = (int32_t)hids.size();
+    }
+    geo.hoff.swap(hoff);
+    geo.hids.swap(hids);
+    geo.lnbr.swap(lnbr);
 }
 
 }  // namespace xrb

@@ -88,12 +88,13 @@ __global__ void __launch_bounds__(kRedBlock) k_lincomb_dev(int n4, double *__res
 }
 
 // IOM2 update of column j (classical two-term Gram-Schmidt) and its norm.
-// Latency shape: the thread's first kUpdPre elements of w, R_j and R_{j-1}
-// are requested before the prologue (the column scale needs the previous
-// kernels' partials and H), and the prologue issues all its loads at once
-// and reduces the three sums and the column maximum behind one barrier --
-// in the same order as separate block reductions would.
-constexpr int kUpdPre = 8;
+// The body streams 16-byte pairs (n4 is even and every vector starts 16-byte
+// aligned).  Latency shape: the thread's first kUpdPre pairs of w, R_j and
+// R_{j-1} are requested before the prologue (the column scale needs the
+// previous kernels' partials and H), and the prologue issues all its loads
+// at once and reduces the three sums and the column maximum behind one
+// barrier -- in the same order as separate block reductions would.
+constexpr int kUpdPre = 4;
 
 __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double *__restrict__ w,
                                                            const double *__restrict__ rj,
@@ -105,19 +106,21 @@ __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double
     __shared__ double lds[16];
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
-    w = member_ptr(w, bt.ws, mk);
-    rj = member_ptr(rj, bt.ws, mk);
-    rjm1 = member_ptr(rjm1, bt.ws, mk);
+    double2 *w2 = reinterpret_cast<double2 *>(member_ptr(w, bt.ws, mk));
+    const double2 *r2 = reinterpret_cast<const double2 *>(member_ptr(rj, bt.ws, mk));
+    const double2 *m2 = reinterpret_cast<const double2 *>(member_ptr(rjm1, bt.ws, mk));
+    const int nv = n4 / 2;
     const int stride = gridDim.x * blockDim.x;
     const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-    double pw[kUpdPre], pr[kUpdPre], pm[kUpdPre];
+    const double2 z2 = make_double2(0.0, 0.0);
+    double2 pw[kUpdPre], pr[kUpdPre], pm[kUpdPre];
 #pragma unroll
     for (int u = 0; u < kUpdPre; ++u) {
         const int i = i0 + u * stride;
-        const bool in = i < n4;
-        pw[u] = in ? w[i] : 0.0;
-        pr[u] = in ? rj[i] : 0.0;
-        pm[u] = (in && j > 0) ? rjm1[i] : 0.0;
+        const bool in = i < nv;
+        pw[u] = in ? w2[i] : z2;
+        pr[u] = in ? r2[i] : z2;
+        pm[u] = (in && j > 0) ? m2[i] : z2;
     }
     PhiCtl *ctl = ctl_member(ctl0, mk);
     // a new basis (j = 0) starts fresh; later columns stop after a breakdown
@@ -172,22 +175,25 @@ __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double
     const double cj = hjj * sj;
     const double cm = hmj * sm;
     double r = 0.0;
+    auto upd = [&](double2 a, double2 b, double2 c) {
+        double2 x;
+        x.x = sj * a.x - cj * b.x;
+        x.y = sj * a.y - cj * b.y;
+        if (j > 0) {
+            x.x -= cm * c.x;
+            x.y -= cm * c.y;
+        }
+        r += x.x * x.x;
+        r += x.y * x.y;
+        return x;
+    };
 #pragma unroll
     for (int u = 0; u < kUpdPre; ++u) {
         const int i = i0 + u * stride;
-        if (i < n4) {
-            double x = sj * pw[u] - cj * pr[u];
-            if (j > 0) x -= cm * pm[u];
-            w[i] = x;
-            r += x * x;
-        }
+        if (i < nv) w2[i] = upd(pw[u], pr[u], pm[u]);
     }
-    for (int i = i0 + kUpdPre * stride; i < n4; i += stride) {
-        double x = sj * w[i] - cj * rj[i];
-        if (j > 0) x -= cm * rjm1[i];
-        w[i] = x;
-        r += x * x;
-    }
+    for (int i = i0 + kUpdPre * stride; i < nv; i += stride)
+        w2[i] = upd(w2[i], r2[i], j > 0 ? m2[i] : z2);
     double vv[1] = {r};
     block_sum_all<1>(vv, lds);
     put_partials<1>(vv, nrm_out + (size_t)mk * kPartStride);

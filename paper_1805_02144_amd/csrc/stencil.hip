@@ -90,11 +90,13 @@ __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restric
 
 template <int L>
 __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__restrict__ u,
-                                                   double *__restrict__ eta, Batch bt) {
+                                                   double *__restrict__ eta,
+                                                   double *__restrict__ rec, Batch bt) {
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
     u = member_ptr(u, bt.ws, mk);
     eta = member_ptr(eta, bt.ws, mk);
+    rec = member_ptr(rec, bt.ws, mk);
     const int n = M.n;
     const int q = threadIdx.x & (L - 1);
     for (CellRange r = block_cells<L>(n); r.i < r.end; r.i += r.step) {
@@ -116,7 +118,16 @@ __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__re
             z = acc_add(z, w.bx * (ui[0] + uj[0]) + w.by * (ui[1] + uj[1]) + w.bz * (ui[2] + uj[2]));
         }
         z = grp_sum<L>(z);
-        if (q == 0) eta[i] = z + M.two_omega * ci.z;
+        const double et = z + M.two_omega * ci.z;
+        if (q == 0) eta[i] = et;
+        if (rec) {
+            // record (u_x, u_y, u_z, h, x, y, z, eta): two 16-byte stores per lane
+            // pair position, spread over the group's lanes
+            const double v[8] = {ui[0], ui[1], ui[2], ui[3], ci.x, ci.y, ci.z, et};
+            double2 *r2 = reinterpret_cast<double2 *>(rec) + 4 * (size_t)i;
+#pragma unroll
+            for (int k = q; k < 4; k += L) r2[k] = make_double2(v[2 * k], v[2 * k + 1]);
+        }
     }
 }
 
@@ -419,6 +430,170 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
         for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
 }
 
+// The product of large grids with its neighbours staged in LDS.  Block b
+// takes chunks of kChunk consecutive cells (XCD-major: the blocks on XCD x
+// sweep the x-th eighth of the chunks together, window by window); for each
+// chunk the block copies x, L x and the linearisation record (u, centre,
+// eta) of the chunk's cells and of its one-ring halo into LDS with
+// coalesced 16-byte loads, and every edge term then reads the neighbour
+// from LDS through the chunk's 16-bit local ids instead of gathering it
+// through the vector caches.  Two lanes serve a cell (kJvLdsL), with the
+// per-cell arithmetic, lane placement and sums of k_jv<EPI, 2>: the output
+// vector has the same bits.  Reductions: per-lane partials over the block's
+// chunks, then one block sum (red_parts(n) blocks).
+constexpr int kJvLdsL = 2;
+constexpr int kJvLdsBlock = kChunk * kJvLdsL;
+
+template <int EPI>
+__global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, Batch bt) {
+    constexpr int L = kJvLdsL, C = kChunk, HM = kHaloMax;
+    __shared__ double2 sx[(C + HM) * 2];   // x
+    __shared__ double2 sl[(C + HM) * 2];   // L x
+    __shared__ double2 sr[(C + HM) * 4];   // record (u, centre, eta)
+    __shared__ double lds[64];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const int n = M.n;
+    const double g = M.g, nu = M.nu;
+    const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
+    double cax[kPmax];
+    const double *axv[kPmax];
+#pragma unroll
+    for (int k = 0; k < kPmax; ++k) {
+        cax[k] = (k < a.naxpy) ? *ctl_field(a.axc[k], mk) : 0.0;
+        axv[k] = (k < a.naxpy) ? member_ptr(a.axv[k], bt.ws, mk) : nullptr;
+    }
+    const double2 *x2 = reinterpret_cast<const double2 *>(member_ptr(a.x, bt.ws, mk));
+    const double2 *l2 = reinterpret_cast<const double2 *>(member_ptr(a.lx, bt.ws, mk));
+    const double2 *r2 = reinterpret_cast<const double2 *>(member_ptr(a.rec, bt.ws, mk));
+    double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
+    const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
+    const Halo &h = M.halo;
+    const int t = threadIdx.x;
+    const int q = t & (L - 1);
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;   // chunks per XCD
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    double r0 = 0.0, r1 = 0.0;
+    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C;
+        const int cnt = min(C, n - c0);
+        const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
+        __syncthreads();   // the previous chunk's readers are done
+        for (int k = t; k < 2 * cnt; k += kJvLdsBlock) {
+            sx[k] = x2[2 * (size_t)c0 + k];
+            sl[k] = l2[2 * (size_t)c0 + k];
+        }
+        for (int k = t; k < 4 * cnt; k += kJvLdsBlock) sr[k] = r2[4 * (size_t)c0 + k];
+        for (int k = t; k < 2 * hn; k += kJvLdsBlock) {
+            const int j = h.hids[h0 + (k >> 1)];
+            sx[2 * C + k] = x2[2 * (size_t)j + (k & 1)];
+            sl[2 * C + k] = l2[2 * (size_t)j + (k & 1)];
+        }
+        for (int k = t; k < 4 * hn; k += kJvLdsBlock) {
+            const int j = h.hids[h0 + (k >> 2)];
+            sr[4 * C + k] = r2[4 * (size_t)j + (k & 3)];
+        }
+        __syncthreads();
+        const int li = t / L;
+        if (li >= cnt) continue;
+        const int i = c0 + li;
+        const double2 p0 = sr[4 * li], p1 = sr[4 * li + 1], p2 = sr[4 * li + 2], p3 = sr[4 * li + 3];
+        const double ux = p0.x, uy = p0.y, uz = p1.x, uh = p1.y;
+        Cell ci;
+        ci.x = p2.x;
+        ci.y = p2.y;
+        ci.z = p3.x;
+        ci.ra = 0.0;
+        const double eta = p3.y;
+        const double2 q0 = sx[2 * li], q1 = sx[2 * li + 1];
+        const double2 s0 = sl[2 * li], s1 = sl[2 * li + 1];
+        const double xx = q0.x, xy = q0.y, xz = q1.x, xh = q1.y;
+        const double lxo[4] = {s0.x, s0.y, s1.x, s1.y};
+        const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
+        const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
+        double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int s = slot_of<L>(q, k);
+            const int e = 6 * i + s;
+            const int lj = h.lnbr[e];
+            const double c = M.cl[e];
+            const double2 a0 = sr[4 * lj], a1 = sr[4 * lj + 1], a2 = sr[4 * lj + 2], a3 = sr[4 * lj + 3];
+            const double2 b0 = sx[2 * lj], b1 = sx[2 * lj + 1];
+            const double2 e0 = sl[2 * lj], e1 = sl[2 * lj + 1];
+            Cell cj;
+            cj.x = a2.x;
+            cj.y = a2.y;
+            cj.z = a3.x;
+            cj.ra = 0.0;
+            const EdgeW w = edge_weights_c(ci, cj, c, M.half_r);
+            const double vx = b0.x, vy = b0.y, vz = b1.x, vh = b1.y;
+            const double wx = a0.x, wy = a0.y, wz = a1.x, wh = a1.y;
+            const double sj = wx * vx + wy * vy + wz * vz + g * vh;
+            const double ds = sj - si;
+            gx = acc_add(gx, w.ax * ds);
+            gy0 = acc_add(gy0, w.ay * ds);
+            gz0 = acc_add(gz0, w.az * ds);
+            dv = acc_add(dv, w.ax * (fx + (wh * vx + vh * wx)) + w.ay * (fy + (wh * vy + vh * wy)) +
+                                 w.az * (fz + (wh * vz + vh * wz)));
+            zt = acc_add(zt, w.bx * (xx + vx) + w.by * (xy + vy) + w.bz * (xz + vz));
+            const double lxj[4] = {e0.x, e0.y, e1.x, e1.y};
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) d[bb] = acc_add(d[bb], c * (lxj[bb] - lxo[bb]));
+        }
+        gx = grp_sum<L>(gx);
+        gy0 = grp_sum<L>(gy0);
+        gz0 = grp_sum<L>(gz0);
+        dv = grp_sum<L>(dv);
+        zt = grp_sum<L>(zt);
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) d[bb] = grp_sum<L>(d[bb]);
+        const double nx = ci.x, ny = ci.y, nz = ci.z;
+        const double gr = nx * gx + ny * gy0 + nz * gz0;
+        const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;
+        const double pux = ny * uz - nz * uy, puy = nz * ux - nx * uz, puz = nx * uy - ny * ux;
+        const double pxx = ny * xz - nz * xy, pxy = nz * xx - nx * xz, pxz = nx * xy - ny * xx;
+        double o[4];
+        o[0] = sc * (-zt * pux - eta * pxx - Gx - nu * d[0]);
+        o[1] = sc * (-zt * puy - eta * pxy - Gy - nu * d[1]);
+        o[2] = sc * (-zt * puz - eta * pxz - Gz - nu * d[2]);
+        o[3] = sc * (-dv - nu * d[3]);
+        const double xs[4] = {xx, xy, xz, xh};
+        double c0v = 0.0, c1v = 0.0;
+#pragma unroll
+        for (int kc = 0; kc < kCompIter<L>; ++kc) {
+            const int bb = comp_of<L>(q, kc);
+            const int oi = 4 * i + bb;
+            double ob = o[bb];
+            if constexpr (EPI != kEpiIom2) {   // IOM2 columns carry no sum terms
+#pragma unroll
+                for (int k = 0; k < kPmax; ++k)
+                    if (k < a.naxpy) ob += cax[k] * axv[k][oi];
+            }
+            outk[oi] = ob;
+            if (EPI == kEpiIom2) {
+                c0v = acc_add(c0v, ob * xs[bb]);
+                if (rjm1) c1v = acc_add(c1v, ob * rjm1[oi]);
+            } else if (EPI == kEpiNorm) {
+                c0v = acc_add(c0v, ob * ob);
+            }
+        }
+        r0 += c0v;
+        r1 += c1v;
+    }
+    if (EPI == kEpiNone) return;
+    double *parts = (EPI == kEpiIom2 ? a.dot_out : a.nrm_out) + (size_t)mk * kPartStride;
+    constexpr int NV = EPI == kEpiIom2 ? 2 : 1;
+    double v[2] = {r0, r1};
+    block_sum_all<2>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
+}
+
 // Conserved quantities monitored in Sec. 6: per block, in its cells'
 // order, the partial sums of A h (mass), A (h |u|^2 / 2 + g h^2 / 2 +
 // g h h_s) (total energy) and A (zeta + f)^2 / (2 h) (potential enstrophy);
@@ -473,8 +648,27 @@ __global__ void __launch_bounds__(256) k_diag_sum(const double *__restrict__ par
         for (int k = 0; k < 3; ++k) out[k] = t[k];
 }
 
+// Whether a product launch takes k_jv_lds: a grid with chunk tables whose
+// reducing products run several passes per block (above kCellRedMax cells
+// per block), two lanes per cell, a linearisation record to stage, and no
+// sum terms on an IOM2 column (none of the callers adds them there).
+bool jv_uses_lds(const DevMesh &M, const JvArgs &a, int epi, int L) {
+    return M.halo.nchunks > 0 && L == kJvLdsL && a.rec && red_cells(M.n) > kCellRedMax &&
+           red_parts(M.n) % kXcd == 0 && !(epi == kEpiIom2 && a.naxpy > 0);
+}
+
 template <int L, bool FL>
 void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+    if (jv_uses_lds(M, a, epi, L)) {
+        const dim3 grid(red_parts(M.n), b.nm), block(kJvLdsBlock);
+        if (epi == kEpiIom2)
+            hipLaunchKernelGGL(k_jv_lds<kEpiIom2>, grid, block, 0, s, M, a, b);
+        else if (epi == kEpiNorm)
+            hipLaunchKernelGGL(k_jv_lds<kEpiNorm>, grid, block, 0, s, M, a, b);
+        else
+            hipLaunchKernelGGL(k_jv_lds<kEpiNone>, grid, block, 0, s, M, a, b);
+        return;
+    }
     if (epi == kEpiNone) {
         hipLaunchKernelGGL((k_jv<kEpiNone, L, FL, false>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256),
                            0, s, M, a, b);
@@ -515,10 +709,10 @@ void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &
 #undef XRB_CALL
 }
 
-void launch_linearize(const DevMesh &M, const double *u, double *eta, const Batch &b,
+void launch_linearize(const DevMesh &M, const double *u, double *eta, double *rec, const Batch &b,
                       hipStream_t s) {
 #define XRB_CALL(L) \
-    hipLaunchKernelGGL(k_linearize<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, eta, b)
+    hipLaunchKernelGGL(k_linearize<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, u, eta, rec, b)
     XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
 }

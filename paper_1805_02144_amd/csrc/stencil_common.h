@@ -130,8 +130,39 @@ __device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]
     o[3] = b.y;
 }
 
-// Flux and circulation weights of the edge i -> j rebuilt from its stored
-// scalar alpha and the two unit centres: a = alpha (x_j - x_i) and
+// The flux weight alpha = l / (2 A_i |x_j - x_i|) of the edge i -> j rebuilt
+// from its Laplacian weight c = l / (d A_i) and the two unit centres: with
+// the chord 2y = |x_j - x_i| and the great-circle distance d = 2 a asin(y)
+// (a the sphere radius), alpha = c (a / 2) asin(y) / y.  asin(y) / y is the
+// series sum_k c_k y^(2k), c_0 = 1, c_(k+1) = c_k (2k+1)^2 / ((2k+2)(2k+3)),
+// summed by Horner in y^2 over kAsinTerms terms: for y^2 <= kAsinY2Max (a
+// neighbour angle up to about 37 degrees) the first omitted term is below
+// 1e-20, so this alpha and the stored one agree to rounding.  The
+// LDS-staged product uses it (one stream fewer); the host enables that
+// product only on grids inside the series' range.
+constexpr int kAsinTerms = 18;
+constexpr double kAsinY2Max = 0.1;
+struct AsinSeries {
+    double c[kAsinTerms];
+};
+constexpr AsinSeries asin_series() {
+    AsinSeries s{};
+    s.c[0] = 1.0;
+    for (int k = 0; k + 1 < kAsinTerms; ++k)
+        s.c[k + 1] = s.c[k] * (double)((2 * k + 1) * (2 * k + 1)) / (double)((2 * k + 2) * (2 * k + 3));
+    return s;
+}
+__device__ inline double edge_alpha(double dx, double dy, double dz, double c, double half_r) {
+    constexpr AsinSeries S = asin_series();
+    const double y2 = 0.25 * (dx * dx + dy * dy + dz * dz);
+    double f = S.c[kAsinTerms - 1];
+#pragma unroll
+    for (int k = kAsinTerms - 2; k >= 0; --k) f = f * y2 + S.c[k];
+    return c * half_r * f;
+}
+
+// Flux and circulation weights of the edge i -> j rebuilt from its scalar
+// alpha and the two unit centres: a = alpha (x_j - x_i) and
 // b = beta (x_i x x_j) with beta = 2 alpha / |x_i + x_j| (the edge's
 // circulation weight l t / (2 A_i)).  beta is evaluated without contraction,
 // so every kernel and lane count forms the same bits.
@@ -143,6 +174,11 @@ __device__ inline double edge_beta(const Cell &ci, const Cell &cj, double al) {
     const double sx = ci.x + cj.x, sy = ci.y + cj.y, sz = ci.z + cj.z;
     const double s2 = (sx * sx + sy * sy) + sz * sz;
     return (2.0 * al) * rsqrt(s2);
+}
+__device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al);
+// the same from the edge's Laplacian weight c (alpha formed by edge_alpha)
+__device__ inline EdgeW edge_weights_c(const Cell &ci, const Cell &cj, double c, double half_r) {
+    return edge_weights(ci, cj, edge_alpha(cj.x - ci.x, cj.y - ci.y, cj.z - ci.z, c, half_r));
 }
 __device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al) {
     const double be = edge_beta(ci, cj, al);

@@ -15,14 +15,30 @@ constexpr int kPmax = XRB_PMAX;
 constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix order
 
 // Geometry of the finite-volume operators, cell-major ([cell][slot], 6
-// slots): the eight lanes that share a cell in the edge-parallel kernels read
-// one contiguous 48-byte record per array.  For the edge from cell i to
-// neighbour j (unit centres x_i, x_j), x_j - x_i is exactly tangent at the
-// edge midpoint direction, so the flux and circulation weights are
+// slots): the lanes that share a cell in the edge-parallel kernels read one
+// contiguous record per array.  For the edge from cell i to neighbour j
+// (unit centres x_i, x_j), x_j - x_i is exactly tangent at the edge midpoint
+// direction, so the flux and circulation weights are
 //   a = l n_e / (2 A_i)  = alpha (x_j - x_i),  alpha = l / (2 A_i |x_j - x_i|)
 //   b = l t_e / (2 A_i)  = beta  (x_i x x_j),  beta  = 2 alpha / |x_i + x_j|
 // and the Laplacian weight is c = l / (d A_i).  alpha and c are stored per
-// edge slot; the kernels form beta from alpha and the two centres they load.
+// edge slot; the kernels form beta from alpha and the two centres they load
+// (the LDS-staged product forms alpha too, from c and the chord: see
+// edge_alpha).
+//
+// Large grids also carry the chunk tables of the LDS-staged product: the
+// cells are cut into chunks of kChunk consecutive cells; chunk k's one-ring
+// halo (the neighbours outside the chunk, ascending) is hids[hoff[k] ..
+// hoff[k+1]), and lnbr[6 i + s] is the position of slot s's neighbour in the
+// chunk's staging order (the chunk's cells, then its halo).
+constexpr int kChunk = 256;       // cells per chunk of the LDS-staged product
+constexpr int kHaloMax = 256;     // largest halo the product's LDS holds
+struct Halo {
+    const int32_t *hoff = nullptr;   // [nchunks + 1]
+    const int32_t *hids = nullptr;   // halo cell ids, chunk after chunk
+    const uint16_t *lnbr = nullptr;  // [n][6]
+    int nchunks = 0;                 // 0: no tables (small grid, or a halo above kHaloMax)
+};
 struct DevMesh {
     int n = 0;
     const int32_t *nbr = nullptr;                  // [n][6]
@@ -31,9 +47,11 @@ struct DevMesh {
     const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, 1 / cell area
     double nu = 0.0, g = 0.0;
     double two_omega = 0.0;                        // Coriolis f_i = two_omega * z_i
+    double half_r = 0.0;                           // sphere radius / 2 (edge_alpha)
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
     int lanes_batch = 8;                           // lanes of forward launches over many cells
     const double *hs = nullptr;                    // [n] surface topography h_s, null = flat
+    Halo halo;
 };
 
 // lanes per cell of the stencil kernels on an n-cell grid
@@ -169,8 +187,9 @@ struct Batch {
 
 // out = L psi (4 components), raw input
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s);
-// eta = V.u + f
-void launch_linearize(const DevMesh &M, const double *u, double *eta, const Batch &b,
+// eta = V.u + f; rec (nullable, 8 doubles per cell) receives the record
+// (u, centre, eta) of every cell
+void launch_linearize(const DevMesh &M, const double *u, double *eta, double *rec, const Batch &b,
                       hipStream_t s);
 // f = F(u), needs lu = L u (4 components)
 void launch_rhs(const DevMesh &M, const double *u, const double *lu, double *f, const Batch &b,
@@ -188,6 +207,10 @@ enum JvEpi { kEpiNone = 0, kEpiIom2 = 1, kEpiNorm = 2 };
 struct JvArgs {
     const double *u = nullptr;      // linearisation state
     const double *eta = nullptr;    // V.u + f
+    // per-cell record (u_x, u_y, u_z, h, x, y, z, eta) of the linearisation
+    // state, written by launch_linearize; nullable (then the products of
+    // large grids read u, eta and the centres from their own arrays)
+    const double *rec = nullptr;
     const double *x = nullptr;      // direction (raw)
     const double *lx = nullptr;     // L x (raw)
     double dt = 1.0;
@@ -343,8 +366,15 @@ struct HostGeometry {
     std::vector<double> cen;                               // [n][4] x, y, z, 1 / area
     std::vector<double> area;                              // [n] cell areas (m^2)
     double nu = 0.0;
+    // chunk tables of the LDS-staged product (see Halo); empty when unused
+    std::vector<int32_t> hoff, hids;
+    std::vector<uint16_t> lnbr;
 };
 int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,
                    std::string &err);
+// Chunk tables for grids whose products take the LDS-staged kernel; leaves
+// them empty when a chunk's halo exceeds kHaloMax or two neighbours lie
+// beyond the range of edge_alpha's series.
+void build_halo(HostGeometry &geo);
 
 }  // namespace xrb

@@ -141,11 +141,19 @@ def kernel_table(prof, overhead_us, n_cells):
     return out, tot
 
 
+def kernel_name(n_cells):
+    """The IOM2 product the library launches on an n-cell grid (two lanes per
+    cell): the LDS-staged kernel above 65536 cells, the gather kernel below."""
+    if n_cells > 65536:
+        return "k_jv_lds<kEpiIom2> (LDS-staged Jacobian product + IOM2 dots)"
+    return "k_jv<kEpiIom2> (fused Jacobian product + IOM2 dots)"
+
+
 def roofline_of(table, name, n_cells, kv):
     r = table[name]
     traffic = _float(kv, "traffic_bytes_per_launch")
     alg = KERNEL_BYTES[name] * n_cells
-    return {"bound": "hbm", "kernel": "k_jv<kEpiIom2> (fused Jacobian product + IOM2 dots)",
+    return {"bound": "hbm", "kernel": kernel_name(n_cells),
             "achieved": r.get("achieved_gbs", 0.0), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r.get("frac", 0.0), "traffic": traffic,
             "traffic_over_algorithmic": traffic / alg if traffic else None,

@@ -32,7 +32,7 @@ namespace xrb {
 namespace {
 
 // the range of the kernels' asin series (kAsinY2Max in stencil_common.h)
-constexpr double kAsinY2MaxHost = 0.1;
+constexpr double kAsinY2MaxHost = 0.01;
 
 struct V3 {
     double x, y, z;

@@ -88,6 +88,59 @@ __global__ void __launch_bounds__(256) k_lap4(DevMesh M, const double *__restric
     }
 }
 
+// L x of large grids with the chunk's cells and their one-ring halo staged
+// in LDS (the chunk tables of k_jv_lds): the per-cell arithmetic, lane
+// placement and sums of k_lap4<kJvLdsL>, so the same bits.  Any grid that
+// is a multiple of the XCD count.
+constexpr int kLapLdsL = 2;
+constexpr int kLapLdsBlock = kChunk * kLapLdsL;
+
+__global__ void __launch_bounds__(kLapLdsBlock) k_lap4_lds(DevMesh M, const double *__restrict__ psi,
+                                                           double *__restrict__ out, Batch bt) {
+    constexpr int L = kLapLdsL, C = kChunk, HM = kHaloMax;
+    __shared__ double2 sx[(C + HM) * 2];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const double2 *x2 = reinterpret_cast<const double2 *>(member_ptr(psi, bt.ws, mk));
+    out = member_ptr(out, bt.ws, mk);
+    const Halo &h = M.halo;
+    const int n = M.n;
+    const int t = threadIdx.x, q = t & (L - 1);
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
+        __syncthreads();   // the previous chunk's readers are done
+        for (int k = t; k < 2 * cnt; k += kLapLdsBlock) sx[k] = x2[2 * (size_t)c0 + k];
+        for (int k = t; k < 2 * hn; k += kLapLdsBlock)
+            sx[2 * C + k] = x2[2 * (size_t)h.hids[h0 + (k >> 1)] + (k & 1)];
+        __syncthreads();
+        const int li = t / L;
+        if (li >= cnt) continue;
+        const int i = c0 + li;
+        const double2 a0 = sx[2 * li], a1 = sx[2 * li + 1];
+        const double pi[4] = {a0.x, a0.y, a1.x, a1.y};
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int e = 6 * i + slot_of<L>(q, k);
+            const int lj = h.lnbr[e];
+            const double c = M.cl[e];
+            const double2 b0 = sx[2 * lj], b1 = sx[2 * lj + 1];
+            const double pj[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) acc[bb] = acc_add(acc[bb], c * (pj[bb] - pi[bb]));
+        }
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc[bb] = grp_sum<L>(acc[bb]);
+#pragma unroll
+        for (int k = 0; k < kCompIter<L>; ++k) out[4 * i + comp_of<L>(q, k)] = acc[comp_of<L>(q, k)];
+    }
+}
+
 template <int L>
 __global__ void __launch_bounds__(256) k_linearize(DevMesh M, const double *__restrict__ u,
                                                    double *__restrict__ eta,
@@ -467,7 +520,9 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
     const double2 *l2 = reinterpret_cast<const double2 *>(member_ptr(a.lx, bt.ws, mk));
     const double2 *r2 = reinterpret_cast<const double2 *>(member_ptr(a.rec, bt.ws, mk));
     double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
-    const double *__restrict__ rjm1 = member_ptr(a.rjm1, bt.ws, mk);
+    // column 0 has no R_{-1}: its second dot runs against x and is ignored by
+    // the update (h_{-1,0} is not formed), which saves a branch per cell
+    const double *__restrict__ rjm1 = member_ptr(a.rjm1 ? a.rjm1 : a.x, bt.ws, mk);
     const Halo &h = M.halo;
     const int t = threadIdx.x;
     const int q = t & (L - 1);
@@ -576,7 +631,7 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
             outk[oi] = ob;
             if (EPI == kEpiIom2) {
                 c0v = acc_add(c0v, ob * xs[bb]);
-                if (rjm1) c1v = acc_add(c1v, ob * rjm1[oi]);
+                c1v = acc_add(c1v, ob * rjm1[oi]);
             } else if (EPI == kEpiNorm) {
                 c0v = acc_add(c0v, ob * ob);
             }
@@ -703,6 +758,12 @@ void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipSt
 }  // namespace
 
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
+    const int L = launch_lanes(M, b.nm);
+    if (M.halo.nchunks > 0 && L == kLapLdsL && red_cells(M.n) > kCellRedMax) {
+        // four blocks per CU, XCD-major chunk sweep
+        hipLaunchKernelGGL(k_lap4_lds, dim3(4 * 256, b.nm), dim3(kLapLdsBlock), 0, s, M, psi, out, b);
+        return;
+    }
 #define XRB_CALL(L) \
     hipLaunchKernelGGL(k_lap4<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b)
     XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)

@@ -136,12 +136,13 @@ __device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]
 // (a the sphere radius), alpha = c (a / 2) asin(y) / y.  asin(y) / y is the
 // series sum_k c_k y^(2k), c_0 = 1, c_(k+1) = c_k (2k+1)^2 / ((2k+2)(2k+3)),
 // summed by Horner in y^2 over kAsinTerms terms: for y^2 <= kAsinY2Max (a
-// neighbour angle up to about 37 degrees) the first omitted term is below
-// 1e-20, so this alpha and the stored one agree to rounding.  The
+// neighbour angle up to 11.5 degrees; level 4 of the icosahedral grid has
+// 4.7) the first omitted term is about 1e-20, so this alpha and the stored
+// one agree to rounding.  The
 // LDS-staged product uses it (one stream fewer); the host enables that
 // product only on grids inside the series' range.
-constexpr int kAsinTerms = 18;
-constexpr double kAsinY2Max = 0.1;
+constexpr int kAsinTerms = 9;
+constexpr double kAsinY2Max = 0.01;
 struct AsinSeries {
     double c[kAsinTerms];
 };

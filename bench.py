@@ -359,14 +359,58 @@ def ensemble_leg(X, torch, reps=20, cpu=True):
         torch.cuda.synchronize()
         tl.append(time.perf_counter() - t0)
     same = bool(torch.equal(last, Ub[63]))
+    # A/B of the launch form on the same decisions: record the batched step's
+    # schedules, then time it replayed eagerly (host waits for every round's
+    # decisions) and as one captured HIP graph (no waits, no host turns)
+    Ub.copy_(Ub0)
+    ctx.reset_history()
+    ctx.schedule_mode(X.RECORD)
+    ctx.step_batch("exprb42", Ub, dts)
+    ctx.schedule_mode(X.FREE)
+    free_res = Ub.clone()
+    scheds = [ctx.schedule_get_member(k) for k in range(64)]
+
+    def replay_setup():
+        ctx.reset_history()
+        for k in range(64):
+            ctx.schedule_set_member(k, scheds[k])
+        ctx.schedule_mode(X.REPLAY)
+
+    tr = []
+    for _ in range(reps):
+        Ub.copy_(Ub0)
+        replay_setup()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.step_batch("exprb42", Ub, dts)
+        torch.cuda.synchronize()
+        tr.append(time.perf_counter() - t0)
+    replay_same = bool(torch.equal(Ub, free_res))
+    Ub.copy_(Ub0)
+    replay_setup()
+    ctx.step_batch_capture("exprb42", Ub, dts)
+    ctx.schedule_mode(X.FREE)
+    tg = []
+    for _ in range(reps):
+        Ub.copy_(Ub0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.graph_launch()
+        torch.cuda.synchronize()
+        tg.append(time.perf_counter() - t0)
+    graph_same = bool(torch.equal(Ub, free_res))
     ctx.close()
     mb, ml = float(np.median(tb)), float(np.median(tl))
+    mr, mg = float(np.median(tr)), float(np.median(tg))
     out = {"workload": "64 members, level-6 grid, exprb42, one step each, dt from "
                        "{600, 1200, 2400, 3600} s (seeded), FP64",
            "batched_member_steps_per_s": 64 / mb, "loop_member_steps_per_s": 64 / ml,
            "speedup": ml / mb, "batched_ms_median": 1e3 * mb, "loop_ms_median": 1e3 * ml,
            "batched_ms_min": 1e3 * min(tb), "loop_ms_min": 1e3 * min(tl), "runs": reps,
            "last_member_bitwise_equal": same,
+           "replayed_ms_median": 1e3 * mr, "graph_ms_median": 1e3 * mg,
+           "graph_member_steps_per_s": 64 / mg, "graph_speedup_vs_loop": ml / mg,
+           "replayed_bitwise_equal": replay_same, "graph_bitwise_equal": graph_same,
            "autotune": {"lanes": tune["lanes"], "lanes_batch": tune["lanes_batch"],
                         "single_us": tune["single_us"], "batch_us": tune["batch_us"]},
            "dt_mix": {str(int(d)): int((dts == d).sum()) for d in sorted(set(dts))}}
@@ -596,6 +640,99 @@ def adjoint_leg(X, torch, fd_dirs=8, fd_eps=1e-6, reps=3, cpu=True):
     return out
 
 
+# ---------------------------------------------------------------- Sec. 6 tables
+EFF_T = 86400.0
+EFF_METHODS = ("epi3", "exprb42", "pexprb43", "exprb53")
+EFF_THRESHOLDS = (1e-4, 1e-5, 1e-6, 1e-7)
+# step sizes that divide one day, from 6 h down to 2 min
+EFF_DTS = (21600, 17280, 14400, 10800, 8640, 7200, 5760, 4800, 4320, 3600, 2880, 2700, 2400,
+           2160, 1920, 1800, 1600, 1440, 1350, 1200, 1080, 960, 900, 864, 800, 720, 640, 600,
+           540, 480, 450, 400, 360, 320, 300, 270, 240, 200, 180, 160, 150, 120)
+
+
+def efficiency_tables(X, torch, reps=3):
+    """The kind of study Sec. 6 reports (Tables 2-7), on the level-6 C2 state
+    (solid-body flow + bump, gamma_h 4e-4) over one day: for each scheme and
+    step size dividing the day, the relative max-norm depth error against a
+    same-mesh reference (exprb53, 60 s steps, Krylov tolerance 1e-13); for
+    each threshold 1e-4 ... 1e-7 the largest step that meets it and its ratio
+    to epi3's; the largest local order between consecutive steps whose errors
+    lie in [1e-9, 1e-3]; and the GPU time of the one-day run at each chosen
+    step (median of `reps`), as the speed-up t_epi3 / t_method."""
+    import numpy as np
+    from synth import fields as F
+    from synth.mesh import get_mesh
+    mesh = get_mesh(6)
+    n = len(mesh["xyz"])
+    u0 = torch.tensor(F.initial_state("c2_l6_24x3600"), dtype=torch.float64, device="cuda:0")
+
+    def run(ctx, method, dt):
+        u = u0.clone()
+        ctx.reset_history()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(int(round(EFF_T / dt))):
+            ctx.step(method, u, float(dt))
+        torch.cuda.synchronize()
+        return u, time.perf_counter() - t0
+
+    ref_ctx = X.Context(mesh, "cuda:0", tol=1e-13, m_max=40)
+    log("efficiency: reference exprb53, 60 s steps")
+    ref, _ = run(ref_ctx, "exprb53", 60.0)
+    ref_ctx.close()
+    href = ref[3 * n:].cpu().numpy()
+    ctx = X.Context(mesh, "cuda:0", tol=1e-10, m_max=40)
+    out = {"workload": "level-6 grid (N=40962), solid-body flow 38.6 m/s + 120 m bump, "
+                       "gamma_h 4e-4, one day, Krylov tol 1e-10 (relative), m_max 40",
+           "reference": "exprb53, 60 s steps, Krylov tol 1e-13",
+           "error": "max|h - h_ref| / max|h_ref| after one day", "methods": {}}
+    for method in EFF_METHODS:
+        errs = {}
+        for dt in EFF_DTS:
+            try:
+                u, _ = run(ctx, method, dt)
+                h = u[3 * n:].cpu().numpy()
+                e = float(np.abs(h - href).max() / np.abs(href).max())
+                if not np.isfinite(e):
+                    e = float("inf")
+            except X.ExprbError:   # NaN or an attempt cap at a step the scheme cannot take
+                e = float("inf")
+            errs[dt] = e
+            log("  %-8s dt %6d  error %.3e" % (method, dt, e))
+            if e < 0.1 * EFF_THRESHOLDS[-1]:
+                break
+        chosen = {}
+        for thr in EFF_THRESHOLDS:
+            ok = [dt for dt, e in errs.items() if e <= thr]
+            chosen["%g" % thr] = max(ok) if ok else None
+        dts = sorted(errs, reverse=True)
+        orders = []
+        for a, b in zip(dts, dts[1:]):
+            ea, eb = errs[a], errs[b]
+            if 1e-9 <= eb <= 1e-3 and 1e-9 <= ea <= 1e-3 and ea > 0 and eb > 0:
+                orders.append(np.log(ea / eb) / np.log(a / b))
+        times = {}
+        for thr, dt in chosen.items():
+            if dt is None:
+                continue
+            ts = []
+            for _ in range(reps):
+                _, t = run(ctx, method, dt)
+                ts.append(t)
+            times[thr] = float(np.median(ts))
+        out["methods"][method] = {"errors": {str(k): v for k, v in errs.items()}, "dt": chosen,
+                                  "order_max": float(max(orders)) if orders else None,
+                                  "gpu_s": times}
+    ctx.close()
+    base = out["methods"]["epi3"]
+    for method, r in out["methods"].items():
+        r["dt_over_epi3"] = {thr: (dt / base["dt"][thr] if dt and base["dt"][thr] else None)
+                             for thr, dt in r["dt"].items()}
+        r["speedup_vs_epi3"] = {thr: (base["gpu_s"][thr] / t if thr in base["gpu_s"] else None)
+                                for thr, t in r["gpu_s"].items()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -623,6 +760,9 @@ def main():
                     help="run only the 64-member level-6 ensemble leg")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the level-7 adjoint leg")
+    ap.add_argument("--efficiency", action="store_true",
+                    help="run only the step-size / error / GPU-time study shaped like the "
+                         "paper's Sec. 6 tables (level 6, one day, four schemes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three 64 MiB device-to-device copies (the reference "
                          "kernel for scaling PMC byte counters)")
@@ -636,6 +776,9 @@ def main():
 
     import paper_1805_02144_amd as X
 
+    if args.efficiency:
+        print(json.dumps({"efficiency": efficiency_tables(X, torch)}))
+        return
     cpu = not args.no_cpu
     only = None
     for name in ("c1", "c2", "ensemble", "adjoint"):

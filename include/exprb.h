@@ -301,6 +301,28 @@ xrb_status xrb_step(xrb_ctx *ctx, xrb_method method, double *u, double dt);
 xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, const double *dt,
                           xrb_phi_stats *stats);
 
+/* The batched step above as one HIP graph (the ensemble's whole launch
+ * sequence, not in the paper): with the context in REPLAY mode, the host
+ * knows every substep decision of every member from its schedule
+ * (xrb_schedule_set_member), so it walks all attempt rounds without waiting
+ * for the device's decision records or synchronising, while the stream is
+ * captured; every host-to-device upload of the rounds (plans, controller
+ * arguments, step sizes) is staged in a pinned arena that the context keeps.
+ * xrb_step_batch_capture records that step for U and dt (it consumes the
+ * members' schedule entries as xrb_step_batch would, and runs nothing);
+ * xrb_graph_launch runs it, waits, and reports a device failure from the
+ * members' last decisions.  A launch gives the bits of the same replayed
+ * xrb_step_batch.  U, dt and the context's ensemble workspace are baked into
+ * the graph: relaunches step whatever U then holds with the same schedule,
+ * and a new capture, a batched call with another nm, or xrb_destroy drops
+ * the graph.  Every member's inputs are taken as nonzero (a member at rest
+ * needs the eager call).  Errors: EINVAL (not in REPLAY mode, event
+ * profiling on, the null stream, nothing captured), ESCHED (a schedule runs
+ * out), ENOMEM, EDEVICE. */
+xrb_status xrb_step_batch_capture(xrb_ctx *ctx, xrb_method method, int nm, double *U,
+                                  const double *dt);
+xrb_status xrb_graph_launch(xrb_ctx *ctx);
+
 /* A general exponential Rosenbrock scheme (eq. 3.10: internal stages U_ni
  * and weights built from phi_k functions of c_i dt J_n, whose stiff order
  * conditions Table 1 lists) written as the sequence of phi-combination

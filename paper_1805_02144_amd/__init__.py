@@ -26,7 +26,7 @@ EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", 
            "xrb_schedule_get", "xrb_profile", "xrb_profile_get", "xrb_step_batch", "xrb_jtv",
            "xrb_ktv", "xrb_step_vjp", "xrb_step_tableau", "xrb_mesh_info",
            "xrb_schedule_set_member", "xrb_schedule_get_member", "xrb_profile_overhead",
-           "xrb_jv_static"]
+           "xrb_jv_static", "xrb_step_batch_capture", "xrb_graph_launch"]
 
 KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
 
@@ -162,6 +162,8 @@ def lib():
                                     C.POINTER(vp), C.POINTER(PhiStats)]
         L.xrb_step.argtypes = [vp, C.c_int, vp, C.c_double]
         L.xrb_step_batch.argtypes = [vp, C.c_int, C.c_int, vp, _dp, C.POINTER(PhiStats)]
+        L.xrb_step_batch_capture.argtypes = [vp, C.c_int, C.c_int, vp, _dp]
+        L.xrb_graph_launch.argtypes = [vp]
         L.xrb_step_tableau.argtypes = [vp, C.POINTER(Tableau), vp, C.c_double]
         L.xrb_step_stats.argtypes = [vp, C.POINTER(PhiStats)]
         L.xrb_reset_history.argtypes = [vp]
@@ -418,6 +420,46 @@ class Context:
         if return_stats:
             return U, [[st[3 * k + c].asdict() for c in range(3)] for k in range(nm)]
         return U
+
+    _gstream = None
+
+    def step_batch_capture(self, method, U, dts):
+        """Capture one replayed batched step of U (float64 device tensor
+        [nm, 4N]) with step sizes dts as a HIP graph (xrb_step_batch_capture;
+        the context must be in REPLAY mode with per-member schedules).  The
+        capture runs on a side stream of this context (a graph cannot be
+        captured on the null stream); U and dts stay baked into the graph."""
+        if not (U.is_contiguous() and U.dtype == self.torch.float64 and U.dim() == 2
+                and U.shape[1] == self.N and U.device == self.device):
+            raise ValueError("U must be a contiguous float64 [nm, 4N] tensor on the device")
+        nm = U.shape[0]
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        if d.shape != (nm,):
+            raise ValueError("one step size per member expected")
+        mid = METHODS[method] if isinstance(method, str) else int(method)
+        if self._gstream is None:
+            self._gstream = self.torch.cuda.Stream(device=self.device)
+        self._gstream.wait_stream(self.torch.cuda.current_stream(self.device))
+        lib().xrb_set_stream(self.h, C.c_void_p(self._gstream.cuda_stream))
+        try:
+            self._check(lib().xrb_step_batch_capture(self.h, mid, nm, _ptr(U), d.ctypes.data_as(_dp)))
+        finally:
+            self._stream()
+        self._graph_keep = (U, d)
+        return U
+
+    def graph_launch(self):
+        """Run the captured batched step (xrb_graph_launch) and wait for it."""
+        if self._gstream is None:
+            raise ValueError("nothing captured")
+        cur = self.torch.cuda.current_stream(self.device)
+        self._gstream.wait_stream(cur)
+        lib().xrb_set_stream(self.h, C.c_void_p(self._gstream.cuda_stream))
+        try:
+            self._check(lib().xrb_graph_launch(self.h))
+        finally:
+            self._stream()
+        cur.wait_stream(self._gstream)
 
     def step_stats(self):
         st = (PhiStats * 3)()

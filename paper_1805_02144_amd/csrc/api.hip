@@ -147,6 +147,16 @@ struct xrb_ctx {
     // first device-side failure since the last xrb_sync (0 = none)
     int latched = 0;
     int dev = 0;   // HIP device current at xrb_create
+    // captured batched step (xrb_step_batch_capture, xrb_graph_launch): while
+    // capturing, the host walks the replay schedule without decision waits or
+    // stream synchronisations and stages every upload in a pinned arena that
+    // lives as long as the graph (a copy node reads its source at launch)
+    bool capturing = false;
+    char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_nm = 0;
 };
 
 // Device scratch of the allocation-free Jacobian product (xrb_jv_static):
@@ -236,6 +246,21 @@ double *io_in(xrb_ctx *ctx, int k, const double *src) {
 }
 void io_out(xrb_ctx *ctx, int k, double *dst) {
     launch_relayout(ctx->n, 1, io_vec(ctx, k), 0, dst, 0, false, ctx->stream);
+}
+
+// Host-to-device copy of `bytes` from pinned memory: while capturing,
+// through a region of the capture arena of its own (the graph's copy node
+// reads its source whenever the graph is launched), else directly.
+int h2d(xrb_ctx *ctx, void *dst, const void *src, size_t bytes) {
+    if (ctx->capturing) {
+        const size_t off = (ctx->arena_used + 255) & ~(size_t)255;
+        if (off + bytes > ctx->arena_cap) return fail(ctx, XRB_ENOMEM, "capture: upload arena exhausted");
+        std::memcpy(ctx->arena + off, src, bytes);
+        ctx->arena_used = off + bytes;
+        src = ctx->arena + off;
+    }
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    return XRB_OK;
 }
 
 hipEvent_t ev_get(xrb_ctx *ctx) {
@@ -362,6 +387,7 @@ void lincomb(xrb_ctx *ctx, const Work &W, double *out, std::initializer_list<con
 }
 
 struct MemberPhi {
+    SchedEntry rep{};         // the replay entry of the current attempt
     bool done = false;
     bool zero_input = false;
     bool ready = false;
@@ -383,9 +409,7 @@ int upload_plan(xrb_ctx *ctx, Work &W, int half) {
     if (W.nm <= 1) return XRB_OK;
     int32_t *stg = W.h_stage + (size_t)half * kPlanW * W.nm;
     std::memcpy(stg, W.h_plan.data(), sizeof(int32_t) * kPlanW * W.nm);
-    HIPCHK(hipMemcpyAsync(W.plan, stg, sizeof(int32_t) * kPlanW * W.nm, hipMemcpyHostToDevice,
-                          ctx->stream));
-    return XRB_OK;
+    return h2d(ctx, W.plan, stg, sizeof(int32_t) * kPlanW * W.nm);
 }
 
 // phipm_simul_iom2 for the nm members of W (lockstep rounds).  u, v, w_out
@@ -445,18 +469,22 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
         ms[k].m = std::min(std::max(m0, 1), P.m_max);
         W.h_m0[k] = ms[k].m;
     }
-    HIPCHK(hipMemcpyAsync(W.m0k, W.h_m0, sizeof(int32_t) * nm, hipMemcpyHostToDevice, s));
+    if (int rc = h2d(ctx, W.m0k, W.h_m0, sizeof(int32_t) * nm)) return rc;
     const Batch ball = batch_of(W);
     if (nv > 0) timed(ctx, XRB_K_VEC, [&] { launch_norms(n, nv, vl, W.v_parts, ball, s); });
     launch_phi_init(W.ctl, ms[0].m, W.m0k, rho[0], P.tol, W.v_parts, np, nv, W.vnorm2, ball, s);
-    HIPCHK(hipMemcpyAsync(W.h_vn, W.vnorm2, sizeof(double) * (kPmax + 1) * nm,
-                          hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    prof_drain(ctx);
+    // (a captured step treats every input as nonzero: the graph cannot read
+    // the norms back, and NaN inputs surface in the decisions instead)
+    if (!ctx->capturing) {
+        HIPCHK(hipMemcpyAsync(W.h_vn, W.vnorm2, sizeof(double) * (kPmax + 1) * nm,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        prof_drain(ctx);
+    }
     int live = 0;
     for (int k = 0; k < nm; ++k) {
-        double smax = 0.0;
-        for (int l = 0; l < nv; ++l) {
+        double smax = ctx->capturing ? 1.0 : 0.0;
+        for (int l = 0; l < nv && !ctx->capturing; ++l) {
             const double x = W.h_vn[k * (kPmax + 1) + l];
             if (x != x) return fail(ctx, XRB_ENAN, "phi_combo: NaN input");
             smax = std::max(smax, x);
@@ -546,6 +574,7 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
                     return fail(ctx, XRB_ESCHED, "phi_combo: replay schedule exhausted");
                 const SchedEntry &e = sv[pos++];
                 if (e.m < 1 || e.m > P.m_max) return fail(ctx, XRB_ESCHED, "phi_combo: bad replay m");
+                mm.rep = e;
                 rep.tau = e.tau;
                 rep.m = e.m;
                 rep.flags = e.flags;
@@ -578,8 +607,8 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
         }
         if (nm > 1) {
             int rc = upload_plan(ctx, W, 0);
+            if (!rc) rc = h2d(ctx, W.cargs, W.h_cargs, sizeof(CtlArgs) * nm);
             if (rc) return rc;
-            HIPCHK(hipMemcpyAsync(W.cargs, W.h_cargs, sizeof(CtlArgs) * nm, hipMemcpyHostToDevice, s));
         }
         if (any_rec) {
             for (int j = 1; j <= p; ++j) {
@@ -663,11 +692,11 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
                                   W.dec_seq, bc, s);
             });
         }
-        {
+        if (!ctx->capturing) {
             const int rc = wait_decisions(ctx, W, W.dec_seq);
             if (rc) return rc;
+            prof_drain(ctx, false);
         }
-        prof_drain(ctx, false);
         bool any_comb = false;
         int copy_slot = 0;
         for (int k = 0; k < nm; ++k) {
@@ -675,7 +704,25 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             W.h_plan[kPlanW * k + PF_COPY] = 0;
             MemberPhi &mm = ms[k];
             if (mm.done) continue;
-            const Decision d = W.h_dec[k];
+            // while capturing, the decision is the replay entry's: the device
+            // takes tau, accept and lands from it and forms t and the output
+            // test with the same arithmetic as below
+            Decision d{};
+            if (ctx->capturing) {
+                d.tau_u = mm.rep.tau;
+                d.accept = mm.rep.flags & 1;
+                d.lands = (mm.rep.flags >> 1) & 1;
+                d.m_eff = mm.wp_zero ? 0 : mm.m;
+                d.m_next = mm.m;
+                {
+#pragma clang fp contract(off)
+                    const double t_new = d.accept ? (d.lands ? rho[mm.io] : mm.t + d.tau_u) : mm.t;
+                    d.t = t_new;
+                    d.reached = (t_new >= rho[mm.io]) ? 1 : 0;
+                }
+            } else {
+                d = W.h_dec[k];
+            }
             if (d.status == XRB_ENAN) return fail(ctx, XRB_ENAN, "phi_combo: NaN in Krylov process");
             if (d.status != 0) return fail(ctx, d.status, "phi_combo: device error");
             if (!(d.tau_u >= 1e-12 * rho[ns - 1]))
@@ -975,6 +1022,7 @@ int scheme_step(xrb_ctx *ctx, Work &W, int method, double *u) {
         return fail(ctx, XRB_EINVAL, "step: unknown method");
     }
     HIPCHK(hipGetLastError());
+    if (ctx->capturing) return XRB_OK;
     HIPCHK(hipStreamSynchronize(s));
     prof_drain(ctx);
     return XRB_OK;
@@ -1103,14 +1151,22 @@ int tableau_step(xrb_ctx *ctx, Work &W, const xrb_tableau &T, double *u) {
     return XRB_OK;
 }
 
+// Drop a captured step (its nodes point into the ensemble workspace).
+void graph_reset(xrb_ctx *ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_nm = 0;
+}
+
 int set_dt(xrb_ctx *ctx, Work &W, const double *dt) {
     for (int k = 0; k < W.nm; ++k) {
         if (!(dt[k] > 0.0) && !(dt[k] < 0.0))
             return fail(ctx, XRB_EINVAL, "step: dt must be nonzero");
         W.h_dt[k] = dt[k];
     }
-    HIPCHK(hipMemcpyAsync(W.dtk, W.h_dt, sizeof(double) * W.nm, hipMemcpyHostToDevice, ctx->stream));
-    return XRB_OK;
+    return h2d(ctx, W.dtk, W.h_dt, sizeof(double) * W.nm);
 }
 
 // ------------------------------------------------------------------------
@@ -1607,6 +1663,8 @@ xrb_status xrb_destroy(xrb_ctx *ctx) {
     const hipError_t e = hipStreamSynchronize(ctx->stream);
     prof_drain(ctx);
     for (hipEvent_t ev : ctx->ev_free) (void)hipEventDestroy(ev);
+    graph_reset(ctx);
+    if (ctx->arena) (void)hipHostFree(ctx->arena);
     int rc = free_work(ctx->one);
     rc |= free_work(ctx->ens);
     adj_free(ctx->adj);
@@ -1968,6 +2026,7 @@ xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, co
     for (int k = 0; k < nm; ++k)
         if (!(dt[k] > 0.0)) return (xrb_status)fail(ctx, XRB_EINVAL, "step_batch: dt must be positive");
     if (ctx->ens.nm != nm) {
+        graph_reset(ctx);
         free_work(ctx->ens);
         int rc = alloc_work(ctx, ctx->ens, nm);
         if (rc) return (xrb_status)rc;
@@ -1985,6 +2044,77 @@ xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, co
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (stats)
         for (int k = 0; k < 3 * nm; ++k) stats[k] = W.stats[k];
+    return XRB_OK;
+}
+
+xrb_status xrb_step_batch_capture(xrb_ctx *ctx, xrb_method method, int nm, double *U,
+                                  const double *dt) {
+    if (!ctx || !U || !dt || nm < 1) return (xrb_status)fail(ctx, XRB_EINVAL, "capture: bad argument");
+    for (int k = 0; k < nm; ++k)
+        if (!(dt[k] > 0.0)) return (xrb_status)fail(ctx, XRB_EINVAL, "capture: dt must be positive");
+    if (ctx->mode != XRB_REPLAY)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "capture: the schedules must be replayed (mode REPLAY)");
+    if (ctx->prof_every)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "capture: event profiling is on");
+    if (!ctx->stream)
+        return (xrb_status)fail(ctx, XRB_EINVAL, "capture: the context needs a stream of its own");
+    const hipStream_t s = ctx->stream;
+    graph_reset(ctx);
+    if (ctx->ens.nm != nm) {
+        free_work(ctx->ens);
+        int rc = alloc_work(ctx, ctx->ens, nm);
+        if (rc) return (xrb_status)rc;
+    }
+    if (!ctx->arena) {
+        constexpr size_t kArenaBytes = (size_t)32 << 20;
+        if (hipHostMalloc((void **)&ctx->arena, kArenaBytes, hipHostMallocDefault) != hipSuccess) {
+            ctx->arena = nullptr;
+            return (xrb_status)fail(ctx, XRB_ENOMEM, "capture: no pinned host memory for the arena");
+        }
+        ctx->arena_cap = kArenaBytes;
+    }
+    ctx->arena_used = 0;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    ctx->capturing = true;
+    Work &W = ctx->ens;
+    double *ust = stage_vec(ctx, W, S_STATE);
+    int rc = set_dt(ctx, W, dt);
+    if (!rc) {
+        launch_relayout(ctx->n, nm, U, ctx->n4, ust, W.ws, true, s);
+        rc = scheme_step(ctx, W, (int)method, ust);
+        if (!rc) launch_relayout(ctx->n, nm, ust, W.ws, U, ctx->n4, false, s);
+    }
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return (xrb_status)(rc ? rc : fail(ctx, XRB_EDEVICE, "capture: stream capture failed"));
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess || !x) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return (xrb_status)fail(ctx, XRB_EDEVICE, "capture: graph instantiation failed");
+    }
+    ctx->graph = g;
+    ctx->graph_exec = x;
+    ctx->graph_nm = nm;
+    return XRB_OK;
+}
+
+xrb_status xrb_graph_launch(xrb_ctx *ctx) {
+    if (!ctx || !ctx->graph_exec) return (xrb_status)fail(ctx, XRB_EINVAL, "graph: nothing captured");
+    HIPCHK(hipGraphLaunch(ctx->graph_exec, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // device-side failures surface in the members' last decision records
+    for (int k = 0; k < ctx->graph_nm; ++k) {
+        const int st = __atomic_load_n(&ctx->ens.h_dec[k].status, __ATOMIC_ACQUIRE);
+        if (st) return (xrb_status)fail(ctx, st == XRB_ENAN ? XRB_ENAN : XRB_EDEVICE,
+                                        "graph: a member's decision reports a device failure");
+    }
     return XRB_OK;
 }
 

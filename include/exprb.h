@@ -404,10 +404,10 @@ xrb_status xrb_profile(xrb_ctx *ctx, int enable);
  * the number of all launches of that kernel. */
 xrb_status xrb_profile_get(const xrb_ctx *ctx, int kernel, double *timed_ms, int64_t *timed,
                            int64_t *launches);
-/* What one event pair adds to a timed launch: `reps` launches of an empty
- * kernel, each between its own pair of events on the context's stream, minus
- * the same launches back to back between one pair, per launch, in
- * microseconds (*us).  Subtracting it from xrb_profile's per-launch averages
+/* What one event pair adds to a timed launch: `reps` launches of a one-wave
+ * kernel that runs 20 us, each between its own pair of events on the
+ * context's stream, minus the same launches back to back between one pair,
+ * per launch, in microseconds (*us; reps of 200 take about 8 ms).  Subtracting it from xrb_profile's per-launch averages
  * leaves the kernel's own duration plus the gap between consecutive
  * launches.  Synchronises the stream; reps in 1..100000. */
 xrb_status xrb_profile_overhead(xrb_ctx *ctx, int reps, double *us);

@@ -323,19 +323,29 @@ __global__ void __launch_bounds__(kBlock) k_zgemm(int n4, ZArgs a) {
 }
 
 // ---------------------------------------------------------------------
-// Dense exponential of a K x K matrix (K <= kBigMax) by one block: the
-// degree-13 Pade approximant with scaling and squaring (the method whose
-// flop count the cost model eq. cost prices), products staged through LDS,
-// the solve (V - U) X = (V + U) by LU with partial pivoting in LDS.
+// Dense exponential of a K x K matrix (K <= kBigMax) by one block, with
+// products only, all on the FP64 matrix cores: scaling and squaring around
+// the degree-18 Taylor polynomial, evaluated by the Paterson-Stockmeyer
+// scheme (powers B^2..B^6, then two Horner steps in B^6: seven products).
+// B = A / 2^s with ||B||_1 <= 1.09, where the Taylor remainder
+// sum_{k>18} ||B||^k / k! is below 5e-17; then s squarings.  (The forward
+// controller keeps the Pade approximant that eq. cost prices; this
+// exponential is the adjoint's, which the paper does not have.)
 // ---------------------------------------------------------------------
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 struct BigLds {
     double a[kBigMax * kBigLd];
     double b[kBigMax * kBigLd];
     double red[64];
-    int ired[64];
 };
 
-// C = A B (global, row-major, ld K); C may alias A or B
+// C = A B (global, row-major, ld K); C may alias A or B.  Both factors are
+// staged in LDS first; the product is cut into 16 x 16 output tiles, one wave
+// per tile at a time, each K/4 rank-4 steps of v_mfma_f64_16x16x4: lane l
+// supplies A(i0 + l%16, k0 + l/16) and B(k0 + l/16, j0 + l%16) and holds
+// C(i0 + l/16 + 4 v, j0 + l%16), v < 4.  Entries at or past K enter as
+// zeros (read at clamped in-range addresses) and are never written.
 __device__ void big_matmul(int K, const double *A, const double *B, double *C, BigLds &L) {
     for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
         const int r = e / K, c = e % K;
@@ -343,11 +353,27 @@ __device__ void big_matmul(int K, const double *A, const double *B, double *C, B
         L.b[r * kBigLd + c] = B[e];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-        const int r = e / K, c = e % K;
-        double acc = 0.0;
-        for (int k = 0; k < K; ++k) acc += L.a[r * kBigLd + k] * L.b[k * kBigLd + c];
-        C[e] = acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int nt = (K + 15) >> 4;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int tile = wave; tile < nt * nt; tile += nw) {
+        const int i0 = (tile / nt) << 4, j0 = (tile % nt) << 4;
+        const int ar = i0 + li, col = j0 + li;
+        const int arc = ar < K ? ar : K - 1, colc = col < K ? col : K - 1;
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            const int k = k0 + lk;
+            const int kc = k < K ? k : K - 1;
+            const double av = L.a[arc * kBigLd + kc];
+            const double bv = L.b[kc * kBigLd + colc];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64((ar < K && k < K) ? av : 0.0,
+                                                       (k < K && col < K) ? bv : 0.0, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = i0 + lk + 4 * v;
+            if (row < K && col < K) C[row * K + col] = acc[v];
+        }
     }
     __syncthreads();
 }
@@ -356,8 +382,9 @@ __device__ void big_matmul(int K, const double *A, const double *B, double *C, B
 __device__ int big_expm(int K, const double *A, double *X, double *work, BigLds &L) {
     const int tid = threadIdx.x;
     const int KK = K * K;
-    double *B = work, *B2 = work + KK, *B4 = work + 2 * KK, *B6 = work + 3 * KK;
-    double *U = work + 4 * KK, *T = work + 5 * KK;
+    double *P[6];   // P[i] = B^i, i = 1..5 (P[0] unused: I), then B^6 in P[0]'s place
+    for (int i = 0; i < 6; ++i) P[i] = work + (size_t)i * KK;
+    double *B6 = P[0];
     // 1-norm and the scaling exponent (K <= kBigMax < blockDim: a column per thread)
     double cs = 0.0;
     if (tid < K)
@@ -370,109 +397,35 @@ __device__ int big_expm(int K, const double *A, double *X, double *work, BigLds 
     }
     int s = 0;
     double scale = 1.0;
-    while (nrm * scale > 5.371920351148152) {
+    while (nrm * scale > 1.09) {
         ++s;
-        scale /= 2.0;
+        scale *= 0.5;
     }
-    double bc[14];
-    bc[0] = 1.0;
-    for (int j = 0; j < 13; ++j) bc[j + 1] = bc[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
-    for (int e = tid; e < KK; e += blockDim.x) B[e] = A[e] * scale;
+    double ck[19];   // 1 / k!
+    ck[0] = 1.0;
+    for (int k = 1; k <= 18; ++k) ck[k] = ck[k - 1] / k;
+    for (int e = tid; e < KK; e += blockDim.x) P[1][e] = A[e] * scale;
     __syncthreads();
-    big_matmul(K, B, B, B2, L);
-    big_matmul(K, B2, B2, B4, L);
-    big_matmul(K, B4, B2, B6, L);
-    // U = B (B6 (b13 B6 + b11 B4 + b9 B2) + b7 B6 + b5 B4 + b3 B2 + b1 I)
-    for (int e = tid; e < KK; e += blockDim.x) T[e] = bc[13] * B6[e] + bc[11] * B4[e] + bc[9] * B2[e];
+    big_matmul(K, P[1], P[1], P[2], L);   // B^2
+    big_matmul(K, P[2], P[1], P[3], L);   // B^3
+    big_matmul(K, P[2], P[2], P[4], L);   // B^4
+    big_matmul(K, P[4], P[1], P[5], L);   // B^5
+    big_matmul(K, P[3], P[3], B6, L);     // B^6
+    // the degree-5 blocks of the polynomial: Q_j = sum_i ck[6j + i] B^i
+    auto q = [&](int j, int e) {
+        double v = (e / K == e % K) ? ck[6 * j] : 0.0;
+        for (int i = 1; i <= 5; ++i) v += ck[6 * j + i] * P[i][e];
+        return v;
+    };
+    // X = Q_2 + ck[18] B^6; X = Q_1 + B^6 X; X = Q_0 + B^6 X
+    for (int e = tid; e < KK; e += blockDim.x) X[e] = q(2, e) + ck[18] * B6[e];
     __syncthreads();
-    big_matmul(K, B6, T, U, L);
-    for (int e = tid; e < KK; e += blockDim.x) {
-        double v = U[e] + bc[7] * B6[e] + bc[5] * B4[e] + bc[3] * B2[e];
-        if (e / K == e % K) v += bc[1];
-        U[e] = v;
-    }
-    __syncthreads();
-    big_matmul(K, B, U, U, L);
-    // V = B6 (b12 B6 + b10 B4 + b8 B2) + b6 B6 + b4 B4 + b2 B2 + b0 I  (into X)
-    for (int e = tid; e < KK; e += blockDim.x) T[e] = bc[12] * B6[e] + bc[10] * B4[e] + bc[8] * B2[e];
-    __syncthreads();
-    big_matmul(K, B6, T, X, L);
-    for (int e = tid; e < KK; e += blockDim.x) {
-        double v = X[e] + bc[6] * B6[e] + bc[4] * B4[e] + bc[2] * B2[e];
-        if (e / K == e % K) v += bc[0];
-        X[e] = v;
-    }
-    __syncthreads();
-    // (V - U) X = (V + U) in LDS
-    for (int e = tid; e < KK; e += blockDim.x) {
-        const int r = e / K, c = e % K;
-        L.a[r * kBigLd + c] = X[e] - U[e];
-        L.b[r * kBigLd + c] = X[e] + U[e];
-    }
-    __syncthreads();
-    for (int c = 0; c < K; ++c) {
-        // pivot: first row of largest magnitude at or below the diagonal
-        if (tid < 64) {
-            double best = -1.0;
-            int bi = K;
-            for (int r = c + tid; r < K; r += 64) {
-                const double v = fabs(L.a[r * kBigLd + c]);
-                if (v > best) {
-                    best = v;
-                    bi = r;
-                }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_down(best, off, 64);
-                const int oi = __shfl_down(bi, off, 64);
-                if (ob > best || (ob == best && oi < bi)) {
-                    best = ob;
-                    bi = oi;
-                }
-            }
-            if (tid == 0) L.ired[0] = bi;
-        }
-        __syncthreads();
-        const int piv = L.ired[0];
-        if (piv != c) {
-            for (int k = tid; k < 2 * K; k += blockDim.x) {
-                double *m = k < K ? L.a : L.b;
-                const int kk = k < K ? k : k - K;
-                const double t = m[c * kBigLd + kk];
-                m[c * kBigLd + kk] = m[piv * kBigLd + kk];
-                m[piv * kBigLd + kk] = t;
-            }
-            __syncthreads();
-        }
-        const double dinv = L.a[c * kBigLd + c];
-        for (int r = c + 1 + tid; r < K; r += blockDim.x) L.a[r * kBigLd + c] /= dinv;
-        __syncthreads();
-        const int rows = K - c - 1, cols = (K - c - 1) + K;
-        for (int e = tid; e < rows * cols; e += blockDim.x) {
-            const int r = c + 1 + e / cols, k = e % cols;
-            const double l = L.a[r * kBigLd + c];
-            if (k < K - c - 1) {
-                const int kk = c + 1 + k;
-                L.a[r * kBigLd + kk] -= l * L.a[c * kBigLd + kk];
-            } else {
-                const int kk = k - (K - c - 1);
-                L.b[r * kBigLd + kk] -= l * L.b[c * kBigLd + kk];
-            }
-        }
+    for (int j = 1; j >= 0; --j) {
+        big_matmul(K, B6, X, X, L);
+        for (int e = tid; e < KK; e += blockDim.x) X[e] += q(j, e);
         __syncthreads();
     }
-    // back substitution, one right-hand side per thread
-    for (int r = K - 1; r >= 0; --r) {
-        for (int k = tid; k < K; k += blockDim.x) {
-            double acc = L.b[r * kBigLd + k];
-            for (int c = r + 1; c < K; ++c) acc -= L.a[r * kBigLd + c] * L.b[c * kBigLd + k];
-            L.b[r * kBigLd + k] = acc / L.a[r * kBigLd + r];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < KK; e += blockDim.x) X[e] = L.b[(e / K) * kBigLd + e % K];
-    __syncthreads();
-    for (int q = 0; q < s; ++q) big_matmul(K, X, X, X, L);
+    for (int r = 0; r < s; ++r) big_matmul(K, X, X, X, L);
     return s;
 }
 

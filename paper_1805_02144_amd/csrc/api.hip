@@ -2213,9 +2213,17 @@ xrb_status xrb_profile(xrb_ctx *ctx, int enable) {
 }  // extern "C"
 
 namespace {
-// An empty one-wave kernel: what the event pairs of xrb_profile add to a
-// launch's measured time is measured on it.
-__global__ void k_noop() {}
+// A one-wave kernel that runs for `ticks` periods of the constant 100 MHz
+// real-time counter (it always ends: the counter only advances).  What the
+// event pairs of xrb_profile add to a launch's measured time is measured on
+// it: a kernel that lasts like the timed ones, so the measurement includes
+// the part of the launch latency that a back-to-back sequence hides.
+__global__ void k_spin(uint64_t ticks) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__builtin_amdgcn_s_memrealtime() - t0 < ticks) {
+    }
+}
+constexpr uint64_t kSpinTicks = 2000;   // 20 us
 }  // namespace
 
 extern "C" {
@@ -2231,16 +2239,16 @@ xrb_status xrb_profile_overhead(xrb_ctx *ctx, int reps, double *us) {
         if (hipEventCreate(&e) != hipSuccess) rc = XRB_EDEVICE;
     double bracketed = 0.0, burst = 0.0;
     if (rc == XRB_OK) {
-        for (int w = 0; w < 3; ++w) hipLaunchKernelGGL(k_noop, dim3(1), dim3(64), 0, s);
+        for (int w = 0; w < 3; ++w) hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, s, kSpinTicks);
         // every launch between its own event pair, as xrb_profile times one
         for (int r = 0; r < reps; ++r) {
             (void)hipEventRecord(ev[2 * r], s);
-            hipLaunchKernelGGL(k_noop, dim3(1), dim3(64), 0, s);
+            hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, s, kSpinTicks);
             (void)hipEventRecord(ev[2 * r + 1], s);
         }
         // the same launches back to back inside one pair
         (void)hipEventRecord(ev[2 * reps], s);
-        for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_noop, dim3(1), dim3(64), 0, s);
+        for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, s, kSpinTicks);
         (void)hipEventRecord(ev[2 * reps + 1], s);
         if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess) rc = XRB_EDEVICE;
         for (int r = 0; r <= reps && rc == XRB_OK; ++r) {

@@ -411,8 +411,7 @@ def ensemble_leg(X, torch, reps=20, cpu=True):
            "replayed_ms_median": 1e3 * mr, "graph_ms_median": 1e3 * mg,
            "graph_member_steps_per_s": 64 / mg, "graph_speedup_vs_loop": ml / mg,
            "replayed_bitwise_equal": replay_same, "graph_bitwise_equal": graph_same,
-           "autotune": {"lanes": tune["lanes"], "lanes_batch": tune["lanes_batch"],
-                        "single_us": tune["single_us"], "batch_us": tune["batch_us"]},
+           "autotune": tune,
            "dt_mix": {str(int(d)): int((dts == d).sum()) for d in sorted(set(dts))}}
     if cpu:
         import threading

@@ -189,26 +189,42 @@ xrb_status xrb_jtv(xrb_ctx *ctx, const double *u, const double *w, double *out);
  * Device vectors of length 4N; out must not alias a or b. */
 xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
 
-/* Lanes-per-cell autotuner: the launch shape of the stencil kernels chosen
- * by measurement on this context's grid.  For each lane count 1, 2, 4, 8 it
- * times one IOM2 column's product (the Laplacian pass where that is
- * separate, then the product with its dot epilogue; 3 warm-up and 20 timed
- * launches on zero data, the fastest of 3 trials, HIP events) for a single
- * state and for a batch of nm_batch members (1..256), and sets the context's
- * lanes for single-state launches and for launches over many cells to the
- * pair that minimises the sum of the two times relative to each one's best,
- * among the pairs that keep batched members bitwise equal to single runs
- * (the same count, or two and eight on grids up to 65536 cells); the current
- * pair is kept unless that one is more than 3 % better.  Overrides
- * xrb_params.lanes.
- * Synchronises the stream; allocates 6 nm_batch vectors for its duration.
- * out (host): the timings in microseconds per launch and the choice. */
+/* Launch-shape autotuner: the launch shapes of the stencil kernels chosen
+ * by measurement on this context's grid, in two stages.
+ * 1. Lanes per cell: for each lane count 1, 2, 4, 8 it times one IOM2
+ *    column's product (the Laplacian pass where that is separate, then the
+ *    product with its dot epilogue; 3 warm-up and 20 timed launches on zero
+ *    data, the fastest of 3 trials, HIP events) for a single state and for a
+ *    batch of nm_batch members (1..256), and sets the context's lanes for
+ *    single-state launches and for launches over many cells to the pair that
+ *    minimises the sum of the two times relative to each one's best, among
+ *    the pairs that keep batched members bitwise equal to single runs (the
+ *    same count, or two and eight on grids up to 65536 cells); the current
+ *    pair is kept unless that one is more than 3 % better.  Overrides
+ *    xrb_params.lanes.
+ * 2. Block shapes, at the chosen lanes (none of them changes a result bit):
+ *    on grids up to 65536 cells, where the reducing products sum per-cell
+ *    terms in cell order, the threads per product block (the one-pass size,
+ *    half of it, 256 and 512), separately for single states and batches, and
+ *    the threads per Laplacian block (64, 128, 256); on larger grids with the
+ *    LDS-staged kernels, the blocks of the Laplacian launch (512, 1024, 2048).
+ *    The built-in rule is kept unless a candidate is more than 3 % faster.
+ * Every batched launch covers all members (the member-minor launch order was
+ * measured and lost).  Synchronises the stream; allocates 8 nm_batch vectors
+ * for its duration.  out (host): the timings in microseconds per launch and
+ * the choices (0 = the built-in rule). */
 typedef struct {
     double single_us[4];   /* lanes 1, 2, 4, 8: one state */
     double batch_us[4];    /* lanes 1, 2, 4, 8: nm_batch members in one launch */
     int32_t lanes;         /* chosen for single-state launches */
     int32_t lanes_batch;   /* chosen for launches over more than 200000 cells in all */
     int32_t nm_batch;
+    int32_t jv_cand[4];    /* product threads tried (0: unused slot) */
+    double jv_single_us[4], jv_batch_us[4];
+    int32_t jv_block, jv_block_batch;
+    int32_t lap_cand[3];   /* Laplacian threads (gather form) or blocks (LDS form) tried */
+    double lap_us[3];
+    int32_t lap_block, lap_grid;
 } xrb_tune_result;
 xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out);
 

@@ -111,7 +111,11 @@ class Params(C.Structure):
 
 class TuneResult(C.Structure):
     _fields_ = [("single_us", C.c_double * 4), ("batch_us", C.c_double * 4),
-                ("lanes", C.c_int32), ("lanes_batch", C.c_int32), ("nm_batch", C.c_int32)]
+                ("lanes", C.c_int32), ("lanes_batch", C.c_int32), ("nm_batch", C.c_int32),
+                ("jv_cand", C.c_int32 * 4), ("jv_single_us", C.c_double * 4),
+                ("jv_batch_us", C.c_double * 4), ("jv_block", C.c_int32),
+                ("jv_block_batch", C.c_int32), ("lap_cand", C.c_int32 * 3),
+                ("lap_us", C.c_double * 3), ("lap_block", C.c_int32), ("lap_grid", C.c_int32)]
 
 
 class PhiStats(C.Structure):
@@ -322,13 +326,20 @@ class Context:
 
     def autotune(self, nm_batch=16):
         """Time the stencil launch shapes on this grid and keep the fastest
-        bitwise-consistent lanes pair (see xrb_autotune)."""
+        bitwise-consistent lanes pair, then the fastest block shapes (see
+        xrb_autotune)."""
         self._stream()
         r = TuneResult()
         self._check(lib().xrb_autotune(self.h, int(nm_batch), C.byref(r)))
+        jv = [c for c in r.jv_cand if c > 0]
         return {"single_us": dict(zip((1, 2, 4, 8), r.single_us)),
                 "batch_us": dict(zip((1, 2, 4, 8), r.batch_us)),
-                "lanes": r.lanes, "lanes_batch": r.lanes_batch, "nm_batch": r.nm_batch}
+                "lanes": r.lanes, "lanes_batch": r.lanes_batch, "nm_batch": r.nm_batch,
+                "jv_threads_single_us": {c: r.jv_single_us[k] for k, c in enumerate(jv)},
+                "jv_threads_batch_us": {c: r.jv_batch_us[k] for k, c in enumerate(jv)},
+                "jv_block": r.jv_block, "jv_block_batch": r.jv_block_batch,
+                "lap_us": {c: r.lap_us[k] for k, c in enumerate(r.lap_cand) if c > 0},
+                "lap_block": r.lap_block, "lap_grid": r.lap_grid}
 
     def set_topography(self, hs):
         """Surface topography h_s (n values in metres, host; None: flat)."""

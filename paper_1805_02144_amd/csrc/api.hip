@@ -1818,14 +1818,16 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
     const int cand[4] = {1, 2, 4, 8};
     constexpr int kWarm = 3, kReps = 20, kTrials = 3;
     // one IOM2 column's product: the Laplacian pass (where separate) and the
-    // product with its dot epilogue
-    auto time_launch = [&](int nm) -> double {
+    // product with its dot epilogue (what = 0), the product alone (1), the
+    // Laplacian alone (2)
+    auto time_launch = [&](int nm, int what = 0) -> double {
         Batch b;
         b.nm = nm;
         b.ws = nm > 1 ? (int64_t)ws : 0;
         auto once = [&] {
-            if (!jv_fuses_lap(ctx->M, nm)) launch_lap4(ctx->M, a.x, (double *)a.lx, b, s);
-            launch_jv(ctx->M, a, kEpiIom2, b, s);
+            if (what != 1 && (what == 2 || !jv_fuses_lap(ctx->M, nm)))
+                launch_lap4(ctx->M, a.x, (double *)a.lx, b, s);
+            if (what != 2) launch_jv(ctx->M, a, kEpiIom2, b, s);
         };
         for (int w = 0; w < kWarm; ++w) once();
         double best = 1e300;   // the fastest of a few trials: least disturbed
@@ -1880,6 +1882,92 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
         out->lanes = la;
         out->lanes_batch = lb;
         out->nm_batch = nm_batch;
+    }
+    // stage 2: block shapes at the chosen lanes
+    for (int k = 0; k < 4; ++k) {
+        out->jv_cand[k] = 0;
+        out->jv_single_us[k] = out->jv_batch_us[k] = 0.0;
+    }
+    for (int k = 0; k < 3; ++k) {
+        out->lap_cand[k] = 0;
+        out->lap_us[k] = 0.0;
+    }
+    out->jv_block = ctx->M.jv_block;
+    out->jv_block_batch = ctx->M.jv_block_batch;
+    out->lap_block = ctx->M.lap_block;
+    out->lap_grid = ctx->M.lap_grid;
+    const bool cellred = red_parts(ctx->n) * 128 >= ctx->n;   // per-cell terms: red_cells <= 128
+    if (rc == XRB_OK && cellred) {
+        // product threads: the one-pass size at each launch's lanes, half of it, 256, 512
+        const int per = (ctx->n + red_parts(ctx->n) - 1) / red_parts(ctx->n);
+        auto cands = [&](int L, int *c) {
+            const int one = (per * L + 63) / 64 * 64;
+            const int half = ((one / 2) + 63) / 64 * 64;
+            const int raw[4] = {one, half, 256, 512};
+            int k = 0;
+            for (int r = 0; r < 4; ++r) {
+                bool dup = false;
+                for (int q = 0; q < k; ++q) dup |= c[q] == raw[r];
+                if (!dup && raw[r] >= 64 && raw[r] <= 1024) c[k++] = raw[r];
+            }
+            return k;
+        };
+        int cs[4] = {0, 0, 0, 0}, cb[4] = {0, 0, 0, 0};
+        const int ns_ = cands(ctx->M.lanes, cs), nb_ = cands(ctx->M.lanes_batch, cb);
+        const int js0 = ctx->M.jv_block, jb0 = ctx->M.jv_block_batch;
+        ctx->M.jv_block = ctx->M.jv_block_batch = 0;
+        const double auto_s = time_launch(1, 1), auto_b = time_launch(nm_batch, 1);
+        double best_s = auto_s, best_b = auto_b;
+        int pick_s = 0, pick_b = 0;
+        for (int k = 0; k < 4 && rc == XRB_OK; ++k) {
+            out->jv_cand[k] = k < ns_ ? cs[k] : 0;
+            if (k < ns_) {
+                ctx->M.jv_block = cs[k];
+                out->jv_single_us[k] = time_launch(1, 1);
+                if (out->jv_single_us[k] < 0.0) rc = fail(ctx, XRB_EDEVICE, "autotune: timing failed");
+                if (out->jv_single_us[k] < best_s / 1.03) {
+                    best_s = out->jv_single_us[k];
+                    pick_s = cs[k];
+                }
+            }
+            if (k < nb_) {
+                ctx->M.jv_block_batch = cb[k];
+                out->jv_batch_us[k] = time_launch(nm_batch, 1);
+                if (out->jv_batch_us[k] < 0.0) rc = fail(ctx, XRB_EDEVICE, "autotune: timing failed");
+                if (out->jv_batch_us[k] < best_b / 1.03) {
+                    best_b = out->jv_batch_us[k];
+                    pick_b = cb[k];
+                }
+            }
+        }
+        ctx->M.jv_block = rc == XRB_OK ? pick_s : js0;
+        ctx->M.jv_block_batch = rc == XRB_OK ? pick_b : jb0;
+        out->jv_block = ctx->M.jv_block;
+        out->jv_block_batch = ctx->M.jv_block_batch;
+    }
+    if (rc == XRB_OK) {
+        // the Laplacian: threads of the gather form, or blocks of the LDS form
+        const bool lds = ctx->M.halo.nchunks > 0 && ctx->M.lanes == 2 && !cellred;
+        const int cand3[3] = {lds ? 512 : 64, lds ? 1024 : 128, lds ? 2048 : 256};
+        const int l0 = lds ? ctx->M.lap_grid : ctx->M.lap_block;
+        int &knob = lds ? ctx->M.lap_grid : ctx->M.lap_block;
+        knob = 0;
+        const double base = time_launch(1, 2);
+        double best = base;
+        int pick = 0;
+        for (int k = 0; k < 3 && rc == XRB_OK; ++k) {
+            out->lap_cand[k] = cand3[k];
+            knob = cand3[k];
+            out->lap_us[k] = time_launch(1, 2);
+            if (out->lap_us[k] < 0.0) rc = fail(ctx, XRB_EDEVICE, "autotune: timing failed");
+            if (out->lap_us[k] < best / 1.03) {
+                best = out->lap_us[k];
+                pick = cand3[k];
+            }
+        }
+        knob = rc == XRB_OK ? pick : l0;
+        out->lap_block = ctx->M.lap_block;
+        out->lap_grid = ctx->M.lap_grid;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

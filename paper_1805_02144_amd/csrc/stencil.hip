@@ -729,7 +729,12 @@ void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hip
                            0, s, M, a, b);
         return;
     }
-    const int grid = red_parts(M.n), block = red_block(M.n, b.nm, L);
+    const int grid = red_parts(M.n);
+    int block = red_block(M.n, b.nm, L);
+    if (red_cells(M.n) <= kCellRedMax) {   // per-cell reduction: any block size gives the same bits
+        const int want = (long)b.nm * M.n > 200000L ? M.jv_block_batch : M.jv_block;
+        if (want > 0) block = want;
+    }
     if (epi == kEpiIom2) {
         if (red_cells(M.n) <= kCellRedMax)
             hipLaunchKernelGGL((k_jv<kEpiIom2, L, FL, true>), dim3(grid, b.nm), dim3(block), 0, s, M, a, b);
@@ -760,12 +765,14 @@ void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipSt
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
     const int L = launch_lanes(M, b.nm);
     if (M.halo.nchunks > 0 && L == kLapLdsL && red_cells(M.n) > kCellRedMax) {
-        // four blocks per CU, XCD-major chunk sweep
-        hipLaunchKernelGGL(k_lap4_lds, dim3(4 * 256, b.nm), dim3(kLapLdsBlock), 0, s, M, psi, out, b);
+        // four blocks per CU by default, XCD-major chunk sweep
+        const int grid = M.lap_grid > 0 ? M.lap_grid : 4 * 256;   // a multiple of the XCD count
+        hipLaunchKernelGGL(k_lap4_lds, dim3(grid, b.nm), dim3(kLapLdsBlock), 0, s, M, psi, out, b);
         return;
     }
+    const int lb = M.lap_block > 0 ? M.lap_block : 256;
 #define XRB_CALL(L) \
-    hipLaunchKernelGGL(k_lap4<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b)
+    hipLaunchKernelGGL(k_lap4<L>, dim3(cells_grid(M.n, lb, L), b.nm), dim3(lb), 0, s, M, psi, out, b)
     XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
 }

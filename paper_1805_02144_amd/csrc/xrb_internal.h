@@ -50,6 +50,12 @@ struct DevMesh {
     double half_r = 0.0;                           // sphere radius / 2 (edge_alpha)
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
     int lanes_batch = 8;                           // lanes of forward launches over many cells
+    // launch shapes the autotuner may set (0 = the built-in rule); none of
+    // them changes any result bit
+    int jv_block = 0, jv_block_batch = 0;          // threads of a product launch that reduces
+                                                   // per-cell terms (grids up to 65536 cells)
+    int lap_block = 0;                             // threads of a gather Laplacian launch
+    int lap_grid = 0;                              // blocks of an LDS-staged Laplacian launch
     const double *hs = nullptr;                    // [n] surface topography h_s, null = flat
     Halo halo;
 };

@@ -67,9 +67,10 @@ def test_binding_loads_torch_before_the_library():
     assert r.returncode == 0, r.stderr[-2000:]
 
 
-def test_tableau_layout_matches_the_header():
-    """The binding's Tableau has the size and field offsets of the C struct
-    xrb_tableau (compiled from include/exprb.h with the host C compiler)."""
+@pytest.mark.parametrize("cls,cname", [("Tableau", "xrb_tableau"), ("TuneResult", "xrb_tune_result")])
+def test_struct_layout_matches_the_header(cls, cname):
+    """The binding's ctypes structures have the size and field offsets of the
+    C structs (compiled from include/exprb.h with the host C compiler)."""
     import shutil
     import subprocess
     import tempfile
@@ -77,10 +78,11 @@ def test_tableau_layout_matches_the_header():
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    fields = [f[0] for f in X.Tableau._fields_]
+    T = getattr(X, cls)
+    fields = [f[0] for f in T._fields_]
     src = ('#include <stdio.h>\n#include <stddef.h>\n#include "exprb.h"\nint main(void){\n'
-           'printf("%zu", sizeof(xrb_tableau));\n' +
-           "".join('printf(" %%zu", offsetof(xrb_tableau, %s));\n' % f for f in fields) +
+           'printf("%%zu", sizeof(%s));\n' % cname +
+           "".join('printf(" %%zu", offsetof(%s, %s));\n' % (cname, f) for f in fields) +
            "return 0;}\n")
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
@@ -89,8 +91,8 @@ def test_tableau_layout_matches_the_header():
         subprocess.run([cc, "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
     got = [int(x) for x in out]
-    assert got[0] == ctypes.sizeof(X.Tableau)
-    assert got[1:] == [getattr(X.Tableau, f).offset for f in fields]
+    assert got[0] == ctypes.sizeof(T)
+    assert got[1:] == [getattr(T, f).offset for f in fields]
 
 
 def test_scheme_tableaus_follow_the_printed_coefficients():

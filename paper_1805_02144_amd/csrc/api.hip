@@ -143,7 +143,8 @@ struct xrb_ctx {
     double *io = nullptr;
     double *hs = nullptr;   // device copy of the surface topography (M.hs)
     // host copies of the cell centres (unit vectors) and areas, for xrb_mesh_info
-    std::vector<double> h_xyz, h_area;
+    std::vector<double> h_xyz, h_area;   // the caller's cell order
+    std::vector<int32_t> h_perm;         // internal cell p is the caller's cell h_perm[p]
     // first device-side failure since the last xrb_sync (0 = none)
     int latched = 0;
     int dev = 0;   // HIP device current at xrb_create
@@ -241,11 +242,11 @@ int io_ensure(xrb_ctx *ctx) {
 double *io_vec(const xrb_ctx *ctx, int k) { return ctx->io + (size_t)k * ctx->n4; }
 double *io_in(xrb_ctx *ctx, int k, const double *src) {
     double *d = io_vec(ctx, k);
-    launch_relayout(ctx->n, 1, src, 0, d, 0, true, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, 1, src, 0, d, 0, true, ctx->stream);
     return d;
 }
 void io_out(xrb_ctx *ctx, int k, double *dst) {
-    launch_relayout(ctx->n, 1, io_vec(ctx, k), 0, dst, 0, false, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, 1, io_vec(ctx, k), 0, dst, 0, false, ctx->stream);
 }
 
 // Host-to-device copy of `bytes` from pinned memory: while capturing,
@@ -1587,16 +1588,18 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ctx->n4 = 4 * n;
     const size_t nd = (size_t)n;
     ctx->h_xyz.assign(mesh->xyz, mesh->xyz + 3 * nd);
-    ctx->h_area.swap(geo.area);
+    ctx->h_area.resize(nd);   // in the caller's cell order
+    for (size_t p = 0; p < nd; ++p) ctx->h_area[(size_t)geo.perm[p]] = geo.area[p];
+    ctx->h_perm = geo.perm;
     // chunk tables of the LDS-staged product on grids whose reducing products
     // run several passes per block
     if ((size_t)n > (size_t)kRedBlocks * 128) build_halo(geo);
     const size_t nh = geo.hoff.size(), nhid = geo.hids.size();
     // geometry in one allocation: 2 x [n][6] edge scalars, [n][4] cell
-    // records, [n][6] int32 neighbours, then the chunk tables (int32 offsets
-    // and halo ids, uint16 local ids)
+    // records, [n][6] int32 neighbours, the [n] int32 cell order, then the
+    // chunk tables (int32 offsets and halo ids, uint16 local ids)
     const size_t dbl = 2 * 6 * nd + 4 * nd;
-    const size_t bytes = dbl * sizeof(double) + 6 * nd * sizeof(int32_t) +
+    const size_t bytes = dbl * sizeof(double) + 7 * nd * sizeof(int32_t) +
                          (nh + nhid) * sizeof(int32_t) + geo.lnbr.size() * sizeof(uint16_t);
     if (hipMalloc(&ctx->geo_mem, bytes) != hipSuccess) {
         delete ctx;
@@ -1622,7 +1625,9 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ck(hipMemcpy(cen, geo.cen.data(), sizeof(double) * 4 * nd, hipMemcpyHostToDevice));
     int32_t *nb = (int32_t *)(g + dbl);
     ck(hipMemcpy(nb, geo.nbr.data(), sizeof(int32_t) * 6 * nd, hipMemcpyHostToDevice));
-    int32_t *hoff = nb + 6 * nd, *hids = hoff + nh;
+    int32_t *perm = nb + 6 * nd;
+    ck(hipMemcpy(perm, geo.perm.data(), sizeof(int32_t) * nd, hipMemcpyHostToDevice));
+    int32_t *hoff = perm + nd, *hids = hoff + nh;
     uint16_t *lnbr = (uint16_t *)(hids + nhid);
     if (nh) {
         ck(hipMemcpy(hoff, geo.hoff.data(), sizeof(int32_t) * nh, hipMemcpyHostToDevice));
@@ -1638,6 +1643,7 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     DevMesh &M = ctx->M;
     M.n = n;
     M.nbr = nb;
+    M.perm = perm;
     M.alpha = alpha;
     M.cl = cl;
     M.cen = cen;
@@ -1736,8 +1742,8 @@ xrb_status xrb_jv_static(xrb_ctx *ctx, const double *u, const double *v, double 
     double *uc = s, *vc = s + n4, *oc = s + 2 * n4, *lap = s + 3 * n4, *rec = s + 4 * n4;
     double *eta = s + 6 * n4;
     Batch b;   // one state, no predicates, no step-size scaling
-    launch_relayout(ctx->n, 1, u, 0, uc, 0, true, ctx->stream);
-    launch_relayout(ctx->n, 1, v, 0, vc, 0, true, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, 1, u, 0, uc, 0, true, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, 1, v, 0, vc, 0, true, ctx->stream);
     launch_linearize(ctx->M, uc, eta, rec, b, ctx->stream);
     if (!jv_fuses_lap(ctx->M, 1)) launch_lap4(ctx->M, vc, lap, b, ctx->stream);
     JvArgs a;
@@ -1749,7 +1755,7 @@ xrb_status xrb_jv_static(xrb_ctx *ctx, const double *u, const double *v, double 
     a.dt = 1.0;
     a.out = oc;
     launch_jv(ctx->M, a, kEpiNone, b, ctx->stream);
-    launch_relayout(ctx->n, 1, oc, 0, jv, 0, false, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, 1, oc, 0, jv, 0, false, ctx->stream);
     HIPCHK(hipGetLastError());
     return XRB_OK;
 }
@@ -1989,7 +1995,9 @@ xrb_status xrb_set_topography(xrb_ctx *ctx, const double *hs) {
         ctx->hs = nullptr;
         return (xrb_status)fail(ctx, XRB_ENOMEM, "set_topography: out of device memory");
     }
-    HIPCHK(hipMemcpy(ctx->hs, hs, sizeof(double) * ctx->n, hipMemcpyHostToDevice));
+    std::vector<double> hp((size_t)ctx->n);   // in the kernels' cell order
+    for (int p = 0; p < ctx->n; ++p) hp[(size_t)p] = hs[ctx->h_perm[(size_t)p]];
+    HIPCHK(hipMemcpy(ctx->hs, hp.data(), sizeof(double) * ctx->n, hipMemcpyHostToDevice));
     ctx->M.hs = ctx->hs;
     return XRB_OK;
 }
@@ -2124,10 +2132,10 @@ xrb_status xrb_step_batch(xrb_ctx *ctx, xrb_method method, int nm, double *U, co
     if (rc) return (xrb_status)rc;
     // member states into the workspace, one step, and back
     double *ust = stage_vec(ctx, W, S_STATE);
-    launch_relayout(ctx->n, nm, U, ctx->n4, ust, W.ws, true, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, nm, U, ctx->n4, ust, W.ws, true, ctx->stream);
     rc = scheme_step(ctx, W, (int)method, ust);
     if (rc) return (xrb_status)rc;
-    launch_relayout(ctx->n, nm, ust, W.ws, U, ctx->n4, false, ctx->stream);
+    launch_relayout(ctx->n, ctx->M.perm, nm, ust, W.ws, U, ctx->n4, false, ctx->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (stats)
@@ -2169,9 +2177,9 @@ xrb_status xrb_step_batch_capture(xrb_ctx *ctx, xrb_method method, int nm, doubl
     double *ust = stage_vec(ctx, W, S_STATE);
     int rc = set_dt(ctx, W, dt);
     if (!rc) {
-        launch_relayout(ctx->n, nm, U, ctx->n4, ust, W.ws, true, s);
+        launch_relayout(ctx->n, ctx->M.perm, nm, U, ctx->n4, ust, W.ws, true, s);
         rc = scheme_step(ctx, W, (int)method, ust);
-        if (!rc) launch_relayout(ctx->n, nm, ust, W.ws, U, ctx->n4, false, s);
+        if (!rc) launch_relayout(ctx->n, ctx->M.perm, nm, ust, W.ws, U, ctx->n4, false, s);
     }
     ctx->capturing = false;
     hipGraph_t g = nullptr;

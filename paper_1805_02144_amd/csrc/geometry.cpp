@@ -17,13 +17,26 @@
 // scalars per edge and the centres they already load,
 //   alpha_s = l_e / (2 A_i |x_j - x_i|),  beta_s = 2 alpha_s / |x_i + x_j|,
 // of which alpha_s is stored and beta_s formed in the kernels (the
-// LDS-staged product forms alpha_s as well, as c_s (a / 2) asin(y) / y with
-// the chord 2y = |x_j - x_i|, since d_e = 2 a asin(y)).  Pentagon slot 5
-// gets zero weights.
+// LDS-staged product forms both from c_s and the chord 2y = |x_j - x_i|:
+// alpha_s = c_s (a / 2) asin(y) / y since d_e = 2 a asin(y), and
+// beta_s = alpha_s (1 - y^2)^(-1/2) since |x_i + x_j|^2 = 4 - 4 y^2).
+// Pentagon slot 5 gets zero weights.
+//
+// The kernels number the cells in an order of their own: the caller's cell
+// i sits at position inv(i) of every internal vector, with perm(p) = i.
+// The order is a recursive coordinate bisection of the centres: a set of
+// cells is split across the coordinate axis of its widest extent, the first
+// part holding a whole number of kChunk-cell chunks (the nearest to half),
+// until a part fits one chunk; each chunk keeps its cells in the caller's
+// order.  Consecutive chunks are then compact, neighbouring patches, so a
+// chunk's one-ring halo is close to a patch's perimeter (about 72 cells
+// per 256 on the icosahedral grids, against 120 for the subdivision's own
+// numbering), and the cells an XCD sweeps form one region of the sphere.
 //
 // For the LDS-staged product of large grids, build_halo cuts the cells into
 // chunks of kChunk consecutive cells and lists each chunk's one-ring halo.
 #include <algorithm>
+#include <numeric>
 #include <cmath>
 
 #include "xrb_internal.h"
@@ -31,8 +44,9 @@
 namespace xrb {
 namespace {
 
-// the range of the kernels' asin series (kAsinY2Max in stencil_common.h)
-constexpr double kAsinY2MaxHost = 0.01;
+// the range of the LDS-staged product's weight series (kShortY2Max in
+// stencil_common.h)
+constexpr double kShortY2MaxHost = 1e-4;
 
 struct V3 {
     double x, y, z;
@@ -52,6 +66,44 @@ inline double excess(V3 a, V3 b, V3 c) {
     return 2.0 * std::atan2(num, den);
 }
 
+// Recursive coordinate bisection of cells idx[0, cnt) into chunks (see the
+// top of this file); the explicit stack keeps the depth off the call stack.
+void bisect_cells(const double *xyz, int32_t *idx, int64_t cnt) {
+    struct Part {
+        int64_t lo, cnt;
+    };
+    std::vector<Part> todo{{0, cnt}};
+    while (!todo.empty()) {
+        const Part pt = todo.back();
+        todo.pop_back();
+        int32_t *a = idx + pt.lo;
+        if (pt.cnt <= kChunk) {
+            std::sort(a, a + pt.cnt);
+            continue;
+        }
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t k = 0; k < pt.cnt; ++k)
+            for (int c = 0; c < 3; ++c) {
+                const double v = xyz[3 * (int64_t)a[k] + c];
+                lo[c] = std::min(lo[c], v);
+                hi[c] = std::max(hi[c], v);
+            }
+        int ax = 0;
+        for (int c = 1; c < 3; ++c)
+            if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+        // first part: whole chunks, the nearest count to half (at least one)
+        int64_t nl = (pt.cnt / 2 + kChunk / 2) / kChunk * kChunk;
+        nl = std::max<int64_t>(kChunk, std::min(nl, pt.cnt - 1));
+        // split at the nl-th centre along the axis (ties by cell number)
+        std::nth_element(a, a + nl, a + pt.cnt, [&](int32_t p, int32_t q) {
+            const double vp = xyz[3 * (int64_t)p + ax], vq = xyz[3 * (int64_t)q + ax];
+            return vp < vq || (vp == vq && p < q);
+        });
+        todo.push_back({pt.lo + nl, pt.cnt - nl});
+        todo.push_back({pt.lo, nl});
+    }
+}
+
 }  // namespace
 
 int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,
@@ -65,8 +117,22 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
         err = "mesh: too many cells";
         return XRB_EINVAL;
     }
+    for (int64_t i = 0; i < n; ++i)
+        for (int s = 0; s < 6; ++s) {
+            const int32_t j = mesh.nbr[6 * i + s];
+            if (j < 0 || j >= n) {
+                err = "mesh: neighbour index out of range";
+                return XRB_EINVAL;
+            }
+        }
     const double R = prm.radius;
     geo.n = (int)n;
+    // the kernels' cell order: internal cell p is the caller's cell perm[p]
+    geo.perm.resize((size_t)n);
+    std::iota(geo.perm.begin(), geo.perm.end(), 0);
+    bisect_cells(mesh.xyz, geo.perm.data(), n);
+    std::vector<int32_t> inv((size_t)n);
+    for (int64_t p = 0; p < n; ++p) inv[(size_t)geo.perm[p]] = (int32_t)p;
     auto resize6 = [&](std::vector<double> &v) { v.assign(6 * (size_t)n, 0.0); };
     geo.nbr.assign(6 * (size_t)n, 0);
     resize6(geo.alpha); resize6(geo.cl);
@@ -79,7 +145,8 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
         return V3{c[0], c[1], c[2]};
     };
 
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t i = geo.perm[p];   // the caller's number of internal cell p
         const int d = mesh.deg[i];
         if (d != 5 && d != 6) {
             err = "mesh: degree must be 5 or 6";
@@ -91,17 +158,17 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
         for (int s = 0; s < d; ++s) ex += excess(xi, CRN(i, (s + d - 1) % d), CRN(i, s));
         const double area = R * R * ex;
         for (int s = 0; s < 6; ++s) {
-            const size_t k = 6 * (size_t)i + s;     // cell-major: the 6 slots of a cell are contiguous
+            const size_t k = 6 * (size_t)p + s;     // cell-major: the 6 slots of a cell are contiguous
             if (s >= d) {                      // pentagon padding: self, zero weights
-                geo.nbr[k] = (int32_t)i;
+                geo.nbr[k] = (int32_t)p;
                 continue;
             }
             const int32_t j = mesh.nbr[6 * i + s];
-            if (j < 0 || j >= n || j == i) {
+            if (j == i) {
                 err = "mesh: neighbour index out of range";
                 return XRB_EINVAL;
             }
-            geo.nbr[k] = j;
+            geo.nbr[k] = inv[(size_t)j];
             const V3 xj = X(j);
             const double le = R * angle(CRN(i, (s + d - 1) % d), CRN(i, s));
             const double de = R * angle(xi, xj);
@@ -109,10 +176,10 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
             geo.alpha[k] = le / (2.0 * area * chord);
             geo.cl[k] = le / (de * area);
         }
-        double *ce = &geo.cen[4 * (size_t)i];
+        double *ce = &geo.cen[4 * (size_t)p];
         ce[0] = xi.x; ce[1] = xi.y; ce[2] = xi.z;
         ce[3] = 1.0 / area;
-        geo.area[i] = area;
+        geo.area[p] = area;
     }
     const double dxbar = std::sqrt(4.0 * M_PI * R * R / (double)n);
     geo.nu = prm.gamma_h * dxbar * dxbar * dxbar * dxbar / prm.dt_e;
@@ -127,7 +194,7 @@ void build_halo(HostGeometry &geo) {
     const int nch = (n + kChunk - 1) / kChunk;
     std::vector<int32_t> hoff(nch + 1, 0), hids;
     std::vector<uint16_t> lnbr(6 * (size_t)n, 0);
-    // the product's alpha series holds for half-chords y with y^2 <= kAsinY2MaxHost
+    // the product's weight series hold for half-chords y with y^2 <= kShortY2MaxHost
     for (int i = 0; i < n; ++i)
         for (int s = 0; s < 6; ++s) {
             const int j = geo.nbr[6 * (size_t)i + s];
@@ -136,7 +203,7 @@ void build_halo(HostGeometry &geo) {
                 const double dx = geo.cen[4 * (size_t)j + c] - geo.cen[4 * (size_t)i + c];
                 y2 += 0.25 * dx * dx;
             }
-            if (y2 > kAsinY2MaxHost) return;   // tables stay empty: the product keeps its gathers
+            if (y2 > kShortY2MaxHost) return;   // tables stay empty: the product keeps its gathers
         }
     std::vector<int32_t> ring;
     for (int k = 0; k < nch; ++k) {

@@ -321,19 +321,21 @@ __global__ void __launch_bounds__(kBlock) k_phi_init(PhiCtl *ctl0, int m0, const
 }
 
 // Layout change between the caller's component-major vectors
-// [u_x | u_y | u_z | h] and the cell-major [cell][4] of the kernels; member k
-// at src + k ss and dst + k ds.  Element e of the cell-major side is
-// component e & 3 of cell e >> 2, so that side is accessed contiguously.
+// [u_x | u_y | u_z | h] and the cell-major [cell][4] of the kernels, whose
+// cell p is the caller's cell perm[p]; member k at src + k ss and dst + k ds.
+// Element e of the cell-major side is component e & 3 of cell e >> 2, so
+// that side is accessed contiguously (the other follows the cell order,
+// whose chunks are compact patches).
 template <bool TO_CELL>
-__global__ void __launch_bounds__(kBlock) k_relayout(int n, const double *__restrict__ src,
-                                                     int64_t ss, double *__restrict__ dst,
-                                                     int64_t ds) {
+__global__ void __launch_bounds__(kBlock) k_relayout(int n, const int32_t *__restrict__ perm,
+                                                     const double *__restrict__ src, int64_t ss,
+                                                     double *__restrict__ dst, int64_t ds) {
     const int mk = blockIdx.y;
     src += ss * mk;
     dst += ds * mk;
     const int n4 = 4 * n;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n4; e += gridDim.x * blockDim.x) {
-        const size_t c = (size_t)(e & 3) * n + (e >> 2);
+        const size_t c = (size_t)(e & 3) * n + perm[e >> 2];
         if (TO_CELL)
             dst[e] = src[c];
         else
@@ -343,13 +345,13 @@ __global__ void __launch_bounds__(kBlock) k_relayout(int n, const double *__rest
 
 }  // namespace
 
-void launch_relayout(int n, int nm, const double *src, int64_t ss, double *dst, int64_t ds,
-                     bool to_cell, hipStream_t s) {
+void launch_relayout(int n, const int32_t *perm, int nm, const double *src, int64_t ss, double *dst,
+                     int64_t ds, bool to_cell, hipStream_t s) {
     const dim3 grid(grid_elems(4 * n), nm);
     if (to_cell)
-        hipLaunchKernelGGL(k_relayout<true>, grid, dim3(kBlock), 0, s, n, src, ss, dst, ds);
+        hipLaunchKernelGGL(k_relayout<true>, grid, dim3(kBlock), 0, s, n, perm, src, ss, dst, ds);
     else
-        hipLaunchKernelGGL(k_relayout<false>, grid, dim3(kBlock), 0, s, n, src, ss, dst, ds);
+        hipLaunchKernelGGL(k_relayout<false>, grid, dim3(kBlock), 0, s, n, perm, src, ss, dst, ds);
 }
 
 void launch_lincomb(int n4, double *out, int k, const double *const *vec, const double *c,

@@ -485,24 +485,31 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
 
 // The product of large grids with its neighbours staged in LDS.  Block b
 // takes chunks of kChunk consecutive cells (XCD-major: the blocks on XCD x
-// sweep the x-th eighth of the chunks together, window by window); for each
-// chunk the block copies x, L x and the linearisation record (u, centre,
-// eta) of the chunk's cells and of its one-ring halo into LDS with
-// coalesced 16-byte loads, and every edge term then reads the neighbour
-// from LDS through the chunk's 16-bit local ids instead of gathering it
-// through the vector caches.  Two lanes serve a cell (kJvLdsL), with the
-// per-cell arithmetic, lane placement and sums of k_jv<EPI, 2>: the output
-// vector has the same bits.  Reductions: per-lane partials over the block's
-// chunks, then one block sum (red_parts(n) blocks).
+// sweep the x-th eighth of the chunks together, window by window).  For each
+// chunk, one thread per cell of the chunk and of its one-ring halo loads the
+// cell's x, L x and linearisation record (u, centre, eta) and stores in LDS
+// what its edges need: s = u . x_vel + g x_h and the flux F = h x_vel +
+// x_h u (both formed once per cell instead of once per edge), x_vel, the
+// centre and L x -- 14 doubles; the chunk's own cells also keep u, eta and
+// x_h.  Every edge term then reads its neighbour from LDS through the
+// chunk's 16-bit local ids, with the weights formed from c and the chord by
+// edge_weights_short.  Two lanes serve a cell (kJvLdsL), with the lane
+// placement and sums of k_jv<EPI, 2>; the rounding differs from the gather
+// kernels (weights from the series, no stored alpha), so a grid with chunk
+// tables keeps this kernel for all its two-lane products.  Reductions:
+// per-lane partials over the block's chunks, then one block sum
+// (red_parts(n) blocks).
 constexpr int kJvLdsL = 2;
 constexpr int kJvLdsBlock = kChunk * kJvLdsL;
 
 template <int EPI>
 __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, Batch bt) {
-    constexpr int L = kJvLdsL, C = kChunk, HM = kHaloMax;
-    __shared__ double2 sx[(C + HM) * 2];   // x
-    __shared__ double2 sl[(C + HM) * 2];   // L x
-    __shared__ double2 sr[(C + HM) * 4];   // record (u, centre, eta)
+    constexpr int L = kJvLdsL, C = kChunk, S = kChunk + kHaloMax;
+    // staged cells (chunk, then halo): (s, F_x) (F_y, F_z) (x_x, x_y) (x_z, centre_x)
+    // (centre_y, centre_z) (Lx_0, Lx_1) (Lx_2, Lx_3); the chunk's own cells:
+    // (u_x, u_y) (u_z, h) (eta, x_h)
+    __shared__ double2 nA[S], nB[S], nC[S], nD[S], nE[S], nL0[S], nL1[S];
+    __shared__ double2 oU0[C], oU1[C], oE[C];
     __shared__ double lds[64];
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
@@ -536,65 +543,63 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
         const int cnt = min(C, n - c0);
         const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
         __syncthreads();   // the previous chunk's readers are done
-        for (int k = t; k < 2 * cnt; k += kJvLdsBlock) {
-            sx[k] = x2[2 * (size_t)c0 + k];
-            sl[k] = l2[2 * (size_t)c0 + k];
-        }
-        for (int k = t; k < 4 * cnt; k += kJvLdsBlock) sr[k] = r2[4 * (size_t)c0 + k];
-        for (int k = t; k < 2 * hn; k += kJvLdsBlock) {
-            const int j = h.hids[h0 + (k >> 1)];
-            sx[2 * C + k] = x2[2 * (size_t)j + (k & 1)];
-            sl[2 * C + k] = l2[2 * (size_t)j + (k & 1)];
-        }
-        for (int k = t; k < 4 * hn; k += kJvLdsBlock) {
-            const int j = h.hids[h0 + (k >> 2)];
-            sr[4 * C + k] = r2[4 * (size_t)j + (k & 3)];
+        for (int m = t; m < cnt + hn; m += kJvLdsBlock) {
+            const bool own = m < cnt;
+            const int j = own ? c0 + m : h.hids[h0 + (m - cnt)];
+            const int sl = own ? m : C + (m - cnt);
+            const double2 v0 = x2[2 * (size_t)j], v1 = x2[2 * (size_t)j + 1];
+            const double2 w0 = r2[4 * (size_t)j], w1 = r2[4 * (size_t)j + 1];
+            const double2 w2 = r2[4 * (size_t)j + 2], w3 = r2[4 * (size_t)j + 3];
+            nL0[sl] = l2[2 * (size_t)j];
+            nL1[sl] = l2[2 * (size_t)j + 1];
+            const double vx = v0.x, vy = v0.y, vz = v1.x, vh = v1.y;
+            const double wx = w0.x, wy = w0.y, wz = w1.x, wh = w1.y;
+            nA[sl] = make_double2(wx * vx + wy * vy + wz * vz + g * vh, wh * vx + vh * wx);
+            nB[sl] = make_double2(wh * vy + vh * wy, wh * vz + vh * wz);
+            nC[sl] = v0;
+            nD[sl] = make_double2(vz, w2.x);
+            nE[sl] = make_double2(w2.y, w3.x);
+            if (own) {
+                oU0[m] = w0;
+                oU1[m] = w1;
+                oE[m] = make_double2(w3.y, vh);
+            }
         }
         __syncthreads();
         const int li = t / L;
         if (li >= cnt) continue;
         const int i = c0 + li;
-        const double2 p0 = sr[4 * li], p1 = sr[4 * li + 1], p2 = sr[4 * li + 2], p3 = sr[4 * li + 3];
-        const double ux = p0.x, uy = p0.y, uz = p1.x, uh = p1.y;
+        const double2 A0 = nA[li], B0 = nB[li], C0 = nC[li], D0 = nD[li], E0 = nE[li];
+        const double2 s0 = nL0[li], s1 = nL1[li];
         Cell ci;
-        ci.x = p2.x;
-        ci.y = p2.y;
-        ci.z = p3.x;
+        ci.x = D0.y;
+        ci.y = E0.x;
+        ci.z = E0.y;
         ci.ra = 0.0;
-        const double eta = p3.y;
-        const double2 q0 = sx[2 * li], q1 = sx[2 * li + 1];
-        const double2 s0 = sl[2 * li], s1 = sl[2 * li + 1];
-        const double xx = q0.x, xy = q0.y, xz = q1.x, xh = q1.y;
+        const double xx = C0.x, xy = C0.y, xz = D0.x;
         const double lxo[4] = {s0.x, s0.y, s1.x, s1.y};
-        const double si = ux * xx + uy * xy + uz * xz + g * xh;       // u.x_vel + g x_h
-        const double fx = uh * xx + xh * ux, fy = uh * xy + xh * uy, fz = uh * xz + xh * uz;
+        const double si = A0.x, fx = A0.y, fy = B0.x, fz = B0.y;
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
         double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < kSlotIter<L>; ++k) {
-            const int s = slot_of<L>(q, k);
-            const int e = 6 * i + s;
+            const int e = 6 * i + slot_of<L>(q, k);
             const int lj = h.lnbr[e];
             const double c = M.cl[e];
-            const double2 a0 = sr[4 * lj], a1 = sr[4 * lj + 1], a2 = sr[4 * lj + 2], a3 = sr[4 * lj + 3];
-            const double2 b0 = sx[2 * lj], b1 = sx[2 * lj + 1];
-            const double2 e0 = sl[2 * lj], e1 = sl[2 * lj + 1];
+            const double2 Aj = nA[lj], Bj = nB[lj], Cj = nC[lj], Dj = nD[lj], Ej = nE[lj];
+            const double2 e0 = nL0[lj], e1 = nL1[lj];
             Cell cj;
-            cj.x = a2.x;
-            cj.y = a2.y;
-            cj.z = a3.x;
+            cj.x = Dj.y;
+            cj.y = Ej.x;
+            cj.z = Ej.y;
             cj.ra = 0.0;
-            const EdgeW w = edge_weights_c(ci, cj, c, M.half_r);
-            const double vx = b0.x, vy = b0.y, vz = b1.x, vh = b1.y;
-            const double wx = a0.x, wy = a0.y, wz = a1.x, wh = a1.y;
-            const double sj = wx * vx + wy * vy + wz * vz + g * vh;
-            const double ds = sj - si;
+            const EdgeW w = edge_weights_short(ci, cj, c, M.half_r);
+            const double ds = Aj.x - si;
             gx = acc_add(gx, w.ax * ds);
             gy0 = acc_add(gy0, w.ay * ds);
             gz0 = acc_add(gz0, w.az * ds);
-            dv = acc_add(dv, w.ax * (fx + (wh * vx + vh * wx)) + w.ay * (fy + (wh * vy + vh * wy)) +
-                                 w.az * (fz + (wh * vz + vh * wz)));
-            zt = acc_add(zt, w.bx * (xx + vx) + w.by * (xy + vy) + w.bz * (xz + vz));
+            dv = acc_add(dv, w.ax * (fx + Aj.y) + w.ay * (fy + Bj.x) + w.az * (fz + Bj.y));
+            zt = acc_add(zt, w.bx * (xx + Cj.x) + w.by * (xy + Cj.y) + w.bz * (xz + Dj.x));
             const double lxj[4] = {e0.x, e0.y, e1.x, e1.y};
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) d[bb] = acc_add(d[bb], c * (lxj[bb] - lxo[bb]));
@@ -606,6 +611,9 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
         zt = grp_sum<L>(zt);
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) d[bb] = grp_sum<L>(d[bb]);
+        const double2 U0 = oU0[li], U1 = oU1[li], EE = oE[li];
+        const double ux = U0.x, uy = U0.y, uz = U1.x;
+        const double eta = EE.x, xh = EE.y;
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;
         const double Gx = gx - gr * nx, Gy = gy0 - gr * ny, Gz = gz0 - gr * nz;

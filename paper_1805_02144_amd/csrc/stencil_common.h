@@ -130,36 +130,35 @@ __device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]
     o[3] = b.y;
 }
 
-// The flux weight alpha = l / (2 A_i |x_j - x_i|) of the edge i -> j rebuilt
-// from its Laplacian weight c = l / (d A_i) and the two unit centres: with
-// the chord 2y = |x_j - x_i| and the great-circle distance d = 2 a asin(y)
-// (a the sphere radius), alpha = c (a / 2) asin(y) / y.  asin(y) / y is the
-// series sum_k c_k y^(2k), c_0 = 1, c_(k+1) = c_k (2k+1)^2 / ((2k+2)(2k+3)),
-// summed by Horner in y^2 over kAsinTerms terms: for y^2 <= kAsinY2Max (a
-// neighbour angle up to 11.5 degrees; level 4 of the icosahedral grid has
-// 4.7) the first omitted term is about 1e-20, so this alpha and the stored
-// one agree to rounding.  The
-// LDS-staged product uses it (one stream fewer); the host enables that
-// product only on grids inside the series' range.
-constexpr int kAsinTerms = 9;
-constexpr double kAsinY2Max = 0.01;
-struct AsinSeries {
-    double c[kAsinTerms];
+// The flux and circulation weights of the edge i -> j rebuilt from its
+// Laplacian weight c = l / (d A_i) and the two unit centres alone.  With the
+// chord 2y = |x_j - x_i| and the great-circle distance d = 2 a asin(y) (a the
+// sphere radius), alpha = l / (2 A_i |x_j - x_i|) = c (a / 2) asin(y) / y;
+// and since |x_i + x_j|^2 = 4 - |x_j - x_i|^2 on the unit sphere,
+// beta = 2 alpha / |x_i + x_j| = alpha (1 - y^2)^(-1/2).  Both factors are
+// series in y^2 summed by Horner over kShortTerms terms:
+//   asin(y) / y = sum_k a_k y^(2k),  a_0 = 1, a_(k+1) = a_k (2k+1)^2 / ((2k+2)(2k+3))
+//   (1 - y^2)^(-1/2) = sum_k b_k y^(2k),  b_0 = 1, b_(k+1) = b_k (2k+1) / (2k+2)
+// For y^2 <= kShortY2Max (neighbour angles up to 1.15 degrees; level 7 of the
+// icosahedral grid has 0.5) the first omitted terms are below 3e-17 of the
+// sums, so these weights agree with the stored alpha and the square-root
+// form of beta to rounding.  The LDS-staged product uses them (no alpha
+// stream, no square root); the host enables that product only on grids
+// inside the series' range.
+constexpr int kShortTerms = 4;
+constexpr double kShortY2Max = 1e-4;
+struct ShortSeries {
+    double a[kShortTerms], b[kShortTerms];
 };
-constexpr AsinSeries asin_series() {
-    AsinSeries s{};
-    s.c[0] = 1.0;
-    for (int k = 0; k + 1 < kAsinTerms; ++k)
-        s.c[k + 1] = s.c[k] * (double)((2 * k + 1) * (2 * k + 1)) / (double)((2 * k + 2) * (2 * k + 3));
+constexpr ShortSeries short_series() {
+    ShortSeries s{};
+    s.a[0] = 1.0;
+    s.b[0] = 1.0;
+    for (int k = 0; k + 1 < kShortTerms; ++k) {
+        s.a[k + 1] = s.a[k] * (double)((2 * k + 1) * (2 * k + 1)) / (double)((2 * k + 2) * (2 * k + 3));
+        s.b[k + 1] = s.b[k] * (double)(2 * k + 1) / (double)(2 * k + 2);
+    }
     return s;
-}
-__device__ inline double edge_alpha(double dx, double dy, double dz, double c, double half_r) {
-    constexpr AsinSeries S = asin_series();
-    const double y2 = 0.25 * (dx * dx + dy * dy + dz * dz);
-    double f = S.c[kAsinTerms - 1];
-#pragma unroll
-    for (int k = kAsinTerms - 2; k >= 0; --k) f = f * y2 + S.c[k];
-    return c * half_r * f;
 }
 
 // Flux and circulation weights of the edge i -> j rebuilt from its scalar
@@ -177,9 +176,28 @@ __device__ inline double edge_beta(const Cell &ci, const Cell &cj, double al) {
     return (2.0 * al) * rsqrt(s2);
 }
 __device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al);
-// the same from the edge's Laplacian weight c (alpha formed by edge_alpha)
-__device__ inline EdgeW edge_weights_c(const Cell &ci, const Cell &cj, double c, double half_r) {
-    return edge_weights(ci, cj, edge_alpha(cj.x - ci.x, cj.y - ci.y, cj.z - ci.z, c, half_r));
+// the same from the edge's Laplacian weight c by the short series above
+// (half_r = a / 2)
+__device__ inline EdgeW edge_weights_short(const Cell &ci, const Cell &cj, double c, double half_r) {
+    constexpr ShortSeries S = short_series();
+    const double dx = cj.x - ci.x, dy = cj.y - ci.y, dz = cj.z - ci.z;
+    const double y2 = 0.25 * (dx * dx + dy * dy + dz * dz);
+    double fa = S.a[kShortTerms - 1], fb = S.b[kShortTerms - 1];
+#pragma unroll
+    for (int k = kShortTerms - 2; k >= 0; --k) {
+        fa = fa * y2 + S.a[k];
+        fb = fb * y2 + S.b[k];
+    }
+    const double al = c * half_r * fa;
+    const double be = al * fb;
+    EdgeW w;
+    w.ax = al * dx;
+    w.ay = al * dy;
+    w.az = al * dz;
+    w.bx = be * (ci.y * cj.z - ci.z * cj.y);
+    w.by = be * (ci.z * cj.x - ci.x * cj.z);
+    w.bz = be * (ci.x * cj.y - ci.y * cj.x);
+    return w;
 }
 __device__ inline EdgeW edge_weights(const Cell &ci, const Cell &cj, double al) {
     const double be = edge_beta(ci, cj, al);

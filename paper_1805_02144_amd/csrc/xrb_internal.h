@@ -23,8 +23,8 @@ constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix or
 //   b = l t_e / (2 A_i)  = beta  (x_i x x_j),  beta  = 2 alpha / |x_i + x_j|
 // and the Laplacian weight is c = l / (d A_i).  alpha and c are stored per
 // edge slot; the kernels form beta from alpha and the two centres they load
-// (the LDS-staged product forms alpha too, from c and the chord: see
-// edge_alpha).
+// (the LDS-staged product forms alpha and beta from c and the chord: see
+// edge_weights_short).
 //
 // Large grids also carry the chunk tables of the LDS-staged product: the
 // cells are cut into chunks of kChunk consecutive cells; chunk k's one-ring
@@ -32,7 +32,7 @@ constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix or
 // hoff[k+1]), and lnbr[6 i + s] is the position of slot s's neighbour in the
 // chunk's staging order (the chunk's cells, then its halo).
 constexpr int kChunk = 256;       // cells per chunk of the LDS-staged product
-constexpr int kHaloMax = 256;     // largest halo the product's LDS holds
+constexpr int kHaloMax = 128;     // largest halo the product's LDS holds
 struct Halo {
     const int32_t *hoff = nullptr;   // [nchunks + 1]
     const int32_t *hids = nullptr;   // halo cell ids, chunk after chunk
@@ -47,7 +47,7 @@ struct DevMesh {
     const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, 1 / cell area
     double nu = 0.0, g = 0.0;
     double two_omega = 0.0;                        // Coriolis f_i = two_omega * z_i
-    double half_r = 0.0;                           // sphere radius / 2 (edge_alpha)
+    double half_r = 0.0;                           // sphere radius / 2 (edge_weights_short)
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
     int lanes_batch = 8;                           // lanes of forward launches over many cells
     // launch shapes the autotuner may set (0 = the built-in rule); none of
@@ -57,6 +57,7 @@ struct DevMesh {
     int lap_block = 0;                             // threads of a gather Laplacian launch
     int lap_grid = 0;                              // blocks of an LDS-staged Laplacian launch
     const double *hs = nullptr;                    // [n] surface topography h_s, null = flat
+    const int32_t *perm = nullptr;                 // [n] the caller's number of internal cell p
     Halo halo;
 };
 
@@ -245,11 +246,12 @@ int launch_lincomb_dev(int n, double *out, int k, const double *const *vec,
 // Mass, total energy and potential enstrophy of the cell-major state u into
 // out[0..2] (device); parts holds 3 red_parts(n) partials.
 void launch_diag(const DevMesh &M, const double *u, double *parts, double *out, hipStream_t s);
-// Caller layout [u_x | u_y | u_z | h] (component-major) to the kernels'
-// cell-major [cell][4] (to_cell) or back, for nm members at strides ss / ds
-// (doubles); src and dst must not overlap.
-void launch_relayout(int n, int nm, const double *src, int64_t ss, double *dst, int64_t ds,
-                     bool to_cell, hipStream_t s);
+// Caller layout [u_x | u_y | u_z | h] (component-major, the caller's cell
+// numbers) to the kernels' cell-major [cell][4] in their own cell order
+// (to_cell: internal cell p takes the caller's cell perm[p]) or back, for nm
+// members at strides ss / ds (doubles); src and dst must not overlap.
+void launch_relayout(int n, const int32_t *perm, int nm, const double *src, int64_t ss, double *dst,
+                     int64_t ds, bool to_cell, hipStream_t s);
 // out = sum_i c[i] * vec[i] (c[i] times dt_k when bit i of dtmask is set), length n4
 void launch_lincomb(int n4, double *out, int k, const double *const *vec, const double *c,
                     unsigned dtmask, const Batch &b, hipStream_t s);
@@ -371,16 +373,20 @@ struct HostGeometry {
     std::vector<double> alpha, cl;                         // [n][6]
     std::vector<double> cen;                               // [n][4] x, y, z, 1 / area
     std::vector<double> area;                              // [n] cell areas (m^2)
+    std::vector<int32_t> perm;                             // [n] caller's cell of internal cell p
     double nu = 0.0;
     // chunk tables of the LDS-staged product (see Halo); empty when unused
     std::vector<int32_t> hoff, hids;
     std::vector<uint16_t> lnbr;
 };
+// Validates the mesh, picks the kernels' cell order (geo.perm: recursive
+// coordinate bisection into kChunk-cell patches) and derives every per-cell
+// and per-edge array in that order.
 int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &geo,
                    std::string &err);
 // Chunk tables for grids whose products take the LDS-staged kernel; leaves
 // them empty when a chunk's halo exceeds kHaloMax or two neighbours lie
-// beyond the range of edge_alpha's series.
+// beyond the range of edge_weights_short's series.
 void build_halo(HostGeometry &geo);
 
 }  // namespace xrb

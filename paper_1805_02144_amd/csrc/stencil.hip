@@ -595,14 +595,16 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
             cj.ra = 0.0;
             const EdgeW w = edge_weights_short(ci, cj, c, M.half_r);
             const double ds = Aj.x - si;
-            gx = acc_add(gx, w.ax * ds);
-            gy0 = acc_add(gy0, w.ay * ds);
-            gz0 = acc_add(gz0, w.az * ds);
-            dv = acc_add(dv, w.ax * (fx + Aj.y) + w.ay * (fy + Bj.x) + w.az * (fz + Bj.y));
-            zt = acc_add(zt, w.bx * (xx + Cj.x) + w.by * (xy + Cj.y) + w.bz * (xz + Dj.x));
+            // fused multiply-adds throughout: this kernel's bits need only
+            // match themselves (batched and single launches)
+            gx = fma(w.ax, ds, gx);
+            gy0 = fma(w.ay, ds, gy0);
+            gz0 = fma(w.az, ds, gz0);
+            dv = fma(w.az, fz + Bj.y, fma(w.ay, fy + Bj.x, fma(w.ax, fx + Aj.y, dv)));
+            zt = fma(w.bz, xz + Dj.x, fma(w.by, xy + Cj.y, fma(w.bx, xx + Cj.x, zt)));
             const double lxj[4] = {e0.x, e0.y, e1.x, e1.y};
 #pragma unroll
-            for (int bb = 0; bb < 4; ++bb) d[bb] = acc_add(d[bb], c * (lxj[bb] - lxo[bb]));
+            for (int bb = 0; bb < 4; ++bb) d[bb] = fma(c, lxj[bb] - lxo[bb], d[bb]);
         }
         gx = grp_sum<L>(gx);
         gy0 = grp_sum<L>(gy0);
@@ -625,7 +627,6 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
         o[2] = sc * (-zt * puz - eta * pxz - Gz - nu * d[2]);
         o[3] = sc * (-dv - nu * d[3]);
         const double xs[4] = {xx, xy, xz, xh};
-        double c0v = 0.0, c1v = 0.0;
 #pragma unroll
         for (int kc = 0; kc < kCompIter<L>; ++kc) {
             const int bb = comp_of<L>(q, kc);
@@ -638,14 +639,12 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
             }
             outk[oi] = ob;
             if (EPI == kEpiIom2) {
-                c0v = acc_add(c0v, ob * xs[bb]);
-                c1v = acc_add(c1v, ob * rjm1[oi]);
+                r0 = fma(ob, xs[bb], r0);
+                r1 = fma(ob, rjm1[oi], r1);
             } else if (EPI == kEpiNorm) {
-                c0v = acc_add(c0v, ob * ob);
+                r0 = fma(ob, ob, r0);
             }
         }
-        r0 += c0v;
-        r1 += c1v;
     }
     if (EPI == kEpiNone) return;
     double *parts = (EPI == kEpiIom2 ? a.dot_out : a.nrm_out) + (size_t)mk * kPartStride;

@@ -99,11 +99,13 @@ typedef struct {
  *   lanes                        tuning: lanes per cell in the stencil kernels,
  *                                1, 2, 4 or 8, or 0 to choose from the grid size
  *                                (8 up to 16384 cells, else 2; with 0, batched
- *                                steps on grids up to 65536 cells use 2).  Two
- *                                and eight lanes give the same bits; 1 and 4
- *                                differ from them at the rounding level (the
- *                                order of the edge sums).  Results never depend
- *                                on the batch size. */
+ *                                steps on grids up to 16384 cells use 2).  On
+ *                                grids up to 16384 cells two and eight lanes
+ *                                give the same bits; on larger ones two lanes
+ *                                take the LDS-staged product, whose rounding
+ *                                differs; 1 and 4 differ at the rounding level
+ *                                (the order of the edge sums).  Results never
+ *                                depend on the batch size. */
 typedef struct {
     double radius, omega, gravity, gamma_h, dt_e;
     double tol;

@@ -676,10 +676,11 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             a.rjm1 = rm;
             a.ctl = W.ctl;
             a.dot_out = W.dot_parts;
-            timed(ctx, XRB_K_JV_IOM2, [&] { launch_jv(ctx->M, a, kEpiIom2, bj, s); });
+            int np_dot = np;   // the product's partial count (its LDS form may take fewer blocks)
+            timed(ctx, XRB_K_JV_IOM2, [&] { np_dot = launch_jv(ctx->M, a, kEpiIom2, bj, s); });
             timed(ctx, XRB_K_IOM2_UPD, [&] {
                 launch_iom2_update(n, j, rn, rj, rm, W.ctl, nrm_buf(j), j == 0 ? np : upd_parts(n),
-                                   W.dot_parts, np,
+                                   W.dot_parts, np_dot,
                                    nrm_buf(j + 1), bj, s);
             });
         }
@@ -1591,9 +1592,9 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     ctx->h_area.resize(nd);   // in the caller's cell order
     for (size_t p = 0; p < nd; ++p) ctx->h_area[(size_t)geo.perm[p]] = geo.area[p];
     ctx->h_perm = geo.perm;
-    // chunk tables of the LDS-staged product on grids whose reducing products
-    // run several passes per block
-    if ((size_t)n > (size_t)kRedBlocks * 128) build_halo(geo);
+    // chunk tables of the LDS-staged product and Laplacian: every grid whose
+    // stencils default to two lanes per cell
+    if (stencil_lanes(n) == 2) build_halo(geo);
     const size_t nh = geo.hoff.size(), nhid = geo.hids.size();
     // geometry in one allocation: 2 x [n][6] edge scalars, [n][4] cell
     // records, [n][6] int32 neighbours, the [n] int32 cell order, then the
@@ -1903,7 +1904,10 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
     out->lap_block = ctx->M.lap_block;
     out->lap_grid = ctx->M.lap_grid;
     const bool cellred = red_parts(ctx->n) * 128 >= ctx->n;   // per-cell terms: red_cells <= 128
-    if (rc == XRB_OK && cellred) {
+    // (two-lane products of grids with chunk tables are the LDS-staged kernel,
+    // whose block shape is fixed)
+    const bool lds2 = ctx->M.halo.nchunks > 0 && ctx->M.lanes == 2 && ctx->M.lanes_batch == 2;
+    if (rc == XRB_OK && cellred && !lds2) {
         // product threads: the one-pass size at each launch's lanes, half of it, 256, 512
         const int per = (ctx->n + red_parts(ctx->n) - 1) / red_parts(ctx->n);
         auto cands = [&](int L, int *c) {
@@ -1953,7 +1957,7 @@ xrb_status xrb_autotune(xrb_ctx *ctx, int nm_batch, xrb_tune_result *out) {
     }
     if (rc == XRB_OK) {
         // the Laplacian: threads of the gather form, or blocks of the LDS form
-        const bool lds = ctx->M.halo.nchunks > 0 && ctx->M.lanes == 2 && !cellred;
+        const bool lds = ctx->M.halo.nchunks > 0 && ctx->M.lanes == 2;
         const int cand3[3] = {lds ? 512 : 64, lds ? 1024 : 128, lds ? 2048 : 256};
         const int l0 = lds ? ctx->M.lap_grid : ctx->M.lap_block;
         int &knob = lds ? ctx->M.lap_grid : ctx->M.lap_block;

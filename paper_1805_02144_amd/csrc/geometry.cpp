@@ -46,7 +46,7 @@ namespace {
 
 // the range of the LDS-staged product's weight series (kShortY2Max in
 // stencil_common.h)
-constexpr double kShortY2MaxHost = 1e-4;
+constexpr double kShortY2MaxHost = 4e-4;
 
 struct V3 {
     double x, y, z;

@@ -35,11 +35,13 @@ int launch_lanes(const DevMesh &M, int nm) {
 
 // Whether single-state launches with a lanes and batched ones with b give
 // the same bits: the same count, or two and eight on grids whose reducing
-// products reduce per-cell terms in fixed order.
+// products reduce per-cell terms in fixed order and have no chunk tables.
 bool lanes_pair_bitwise(const DevMesh &M, int a, int b) {
     if (a == b) return true;
     const bool two_eight = (a == 2 || a == 8) && (b == 2 || b == 8);
-    return two_eight && stc::red_cells(M.n) <= stc::kCellRedMax;
+    // with chunk tables two lanes take the LDS-staged product, whose rounding
+    // is its own
+    return two_eight && stc::red_cells(M.n) <= stc::kCellRedMax && M.halo.nchunks == 0;
 }
 
 namespace {
@@ -710,31 +712,42 @@ __global__ void __launch_bounds__(256) k_diag_sum(const double *__restrict__ par
         for (int k = 0; k < 3; ++k) out[k] = t[k];
 }
 
-// Whether a product launch takes k_jv_lds: a grid with chunk tables whose
-// reducing products run several passes per block (above kCellRedMax cells
-// per block), two lanes per cell, a linearisation record to stage, and no
-// sum terms on an IOM2 column (none of the callers adds them there).
+// Blocks that cover every chunk once: the chunk count rounded up to whole
+// XCDs (the LDS kernels sweep chunk x * ceil(nchunks / 8) + k on XCD x).
+int lds_grid_cap(const DevMesh &M) { return (M.halo.nchunks + kXcd - 1) / kXcd * kXcd; }
+
+// Whether a product launch takes k_jv_lds: a grid with chunk tables, two
+// lanes per cell, a linearisation record to stage (every forward product of
+// the library passes one), and no sum terms on an IOM2 column (none of the
+// callers adds them there).
 bool jv_uses_lds(const DevMesh &M, const JvArgs &a, int epi, int L) {
-    return M.halo.nchunks > 0 && L == kJvLdsL && a.rec && red_cells(M.n) > kCellRedMax &&
-           red_parts(M.n) % kXcd == 0 && !(epi == kEpiIom2 && a.naxpy > 0);
+    return M.halo.nchunks > 0 && L == kJvLdsL && a.rec && red_parts(M.n) % kXcd == 0 &&
+           !(epi == kEpiIom2 && a.naxpy > 0);
 }
 
+// Returns the number of partials the launch writes per member (0 without an
+// epilogue).
 template <int L, bool FL>
-void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+int jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
     if (jv_uses_lds(M, a, epi, L)) {
-        const dim3 grid(red_parts(M.n), b.nm), block(kJvLdsBlock);
+        // no more blocks than chunks (rounded to whole XCDs): a batched launch
+        // would otherwise dispatch every member's empty blocks; norm partials
+        // keep red_parts(n) blocks, the count their consumers sum
+        const int cap = lds_grid_cap(M);
+        const int np = epi == kEpiNorm ? red_parts(M.n) : (cap < red_parts(M.n) ? cap : red_parts(M.n));
+        const dim3 grid(np, b.nm), block(kJvLdsBlock);
         if (epi == kEpiIom2)
             hipLaunchKernelGGL(k_jv_lds<kEpiIom2>, grid, block, 0, s, M, a, b);
         else if (epi == kEpiNorm)
             hipLaunchKernelGGL(k_jv_lds<kEpiNorm>, grid, block, 0, s, M, a, b);
         else
             hipLaunchKernelGGL(k_jv_lds<kEpiNone>, grid, block, 0, s, M, a, b);
-        return;
+        return epi == kEpiNone ? 0 : np;
     }
     if (epi == kEpiNone) {
         hipLaunchKernelGGL((k_jv<kEpiNone, L, FL, false>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256),
                            0, s, M, a, b);
-        return;
+        return 0;
     }
     const int grid = red_parts(M.n);
     int block = red_block(M.n, b.nm, L);
@@ -754,26 +767,27 @@ void jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hip
         else
             hipLaunchKernelGGL((k_jv<kEpiNorm, L, FL, false>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
     }
+    return grid;
 }
 
 template <int L>
-void jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+int jv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
     if constexpr (L == 8) {
-        if (jv_fuses_lap(M, b.nm)) {
-            jv_launch_t<8, true>(M, a, epi, b, s);
-            return;
-        }
+        if (jv_fuses_lap(M, b.nm)) return jv_launch_t<8, true>(M, a, epi, b, s);
     }
-    jv_launch_t<L, false>(M, a, epi, b, s);
+    return jv_launch_t<L, false>(M, a, epi, b, s);
 }
 
 }  // namespace
 
 void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
     const int L = launch_lanes(M, b.nm);
-    if (M.halo.nchunks > 0 && L == kLapLdsL && red_cells(M.n) > kCellRedMax) {
-        // four blocks per CU by default, XCD-major chunk sweep
-        const int grid = M.lap_grid > 0 ? M.lap_grid : 4 * 256;   // a multiple of the XCD count
+    if (M.halo.nchunks > 0 && L == kLapLdsL) {
+        // four blocks per CU by default, XCD-major chunk sweep, and no more
+        // blocks than chunks (both multiples of the XCD count)
+        const int want = M.lap_grid > 0 ? M.lap_grid : 4 * 256;
+        const int cap = lds_grid_cap(M);
+        const int grid = want < cap ? want : cap;
         hipLaunchKernelGGL(k_lap4_lds, dim3(grid, b.nm), dim3(kLapLdsBlock), 0, s, M, psi, out, b);
         return;
     }
@@ -809,10 +823,11 @@ void launch_diag(const DevMesh &M, const double *u, double *parts, double *out, 
 }
 
 int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
-#define XRB_CALL(L) jv_launch<L>(M, a, epi, b, s)
+    int np = 0;
+#define XRB_CALL(L) np = jv_launch<L>(M, a, epi, b, s)
     XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
-    return epi == kEpiNone ? 0 : red_parts(M.n);
+    return np;
 }
 
 }  // namespace xrb

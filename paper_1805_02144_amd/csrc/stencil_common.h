@@ -139,14 +139,14 @@ __device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]
 // series in y^2 summed by Horner over kShortTerms terms:
 //   asin(y) / y = sum_k a_k y^(2k),  a_0 = 1, a_(k+1) = a_k (2k+1)^2 / ((2k+2)(2k+3))
 //   (1 - y^2)^(-1/2) = sum_k b_k y^(2k),  b_0 = 1, b_(k+1) = b_k (2k+1) / (2k+2)
-// For y^2 <= kShortY2Max (neighbour angles up to 1.15 degrees; level 7 of the
-// icosahedral grid has 0.5) the first omitted terms are below 3e-17 of the
+// For y^2 <= kShortY2Max (neighbour angles up to 2.3 degrees; level 6 of the
+// icosahedral grid has 1.2) the first omitted terms are below 3e-18 of the
 // sums, so these weights agree with the stored alpha and the square-root
 // form of beta to rounding.  The LDS-staged product uses them (no alpha
 // stream, no square root); the host enables that product only on grids
 // inside the series' range.
-constexpr int kShortTerms = 4;
-constexpr double kShortY2Max = 1e-4;
+constexpr int kShortTerms = 5;
+constexpr double kShortY2Max = 4e-4;
 struct ShortSeries {
     double a[kShortTerms], b[kShortTerms];
 };

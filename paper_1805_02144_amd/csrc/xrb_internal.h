@@ -26,7 +26,8 @@ constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix or
 // (the LDS-staged product forms alpha and beta from c and the chord: see
 // edge_weights_short).
 //
-// Large grids also carry the chunk tables of the LDS-staged product: the
+// Grids above 16384 cells (where the stencils default to two lanes per cell)
+// also carry the chunk tables of the LDS-staged product and Laplacian: the
 // cells are cut into chunks of kChunk consecutive cells; chunk k's one-ring
 // halo (the neighbours outside the chunk, ascending) is hids[hoff[k] ..
 // hoff[k+1]), and lnbr[6 i + s] is the position of slot s's neighbour in the

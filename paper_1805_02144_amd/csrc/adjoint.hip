@@ -8,6 +8,7 @@
 //   k_lapT    L^T psi on four fields (prepass of the two-ring (L^T)^2)
 //   k_jtv     dt J(u)^T x (+ axpys) with the IOM2 / norm epilogues of k_jv,
 //             so the IOM2 driver builds a Krylov space of A^T unchanged
+//             (k_jtv_lds: its form on grids with chunk tables)
 //   k_kpairs  acc += sum_r c_r K(a_r, b_r)
 //   k_lincomb_multi  several combinations of one contiguous basis at once
 //   k_zgemm   Z_r = sum_c z_rc What_c (the forward substep's solution basis)
@@ -191,6 +192,175 @@ __global__ void __launch_bounds__(kJtvMaxBlock<EPI>) k_jtv(DevMesh M, JvArgs a, 
         block_sum_all<1>(v, lds);
         put_partials<1>(v, a.nrm_out + (size_t)mk * kPartStride);
     }
+}
+
+// k_jtv on grids with chunk tables, its neighbours staged in LDS like the
+// forward k_jv_lds: for each chunk, one thread per cell of the chunk and of
+// its one-ring halo loads the cell's x, u, L^T x and centre record and stores
+// the area-scaled quantities its edges take -- s ra, (P x) ra, x_h ra and
+// (L^T x) ra (s = x . (n x u), P x the tangential part of x_vel, ra = 1/A) --
+// with the centre, 12 doubles; the chunk's own cells also keep u, x, eta and
+// A.  Edge weights come from c and the chord (edge_weights_short), two lanes
+// serve a cell, accumulations fuse.  Reductions as in k_jtv: per-lane
+// partials, one block sum, the returned number of blocks.
+constexpr int kJtvLdsL = 2;
+constexpr int kJtvLdsBlock = kChunk * kJtvLdsL;
+
+template <int EPI>
+__global__ void __launch_bounds__(kJtvLdsBlock, 4) k_jtv_lds(DevMesh M, JvArgs a, Batch bt) {
+    constexpr int L = kJtvLdsL, C = kChunk, S = kChunk + kHaloMax;
+    // staged cells: (s ra, p_x ra) (p_y ra, p_z ra) (x_h ra, centre_x)
+    // (centre_y, centre_z) ((L^T x)_0 ra, (L^T x)_1 ra) ((L^T x)_2 ra, (L^T x)_3 ra);
+    // own cells: (u_x, u_y) (u_z, h) (x_x, x_y) (x_z, x_h) (eta, A)
+    __shared__ double2 nA[S], nB[S], nC[S], nD[S], nE[S], nF[S];
+    __shared__ double2 oU0[C], oU1[C], oX0[C], oX1[C], oE[C];
+    __shared__ double lds[64];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const int n = M.n;
+    const double g = M.g, nu = M.nu;
+    const double sc = bt.dtk ? bt.dtk[mk] : a.dt;
+    double cax[kPmax];
+    const double *axv[kPmax];
+#pragma unroll
+    for (int k = 0; k < kPmax; ++k) {
+        cax[k] = (k < a.naxpy) ? *ctl_field(a.axc[k], mk) : 0.0;
+        axv[k] = (k < a.naxpy) ? member_ptr(a.axv[k], bt.ws, mk) : nullptr;
+    }
+    const double2 *x2 = reinterpret_cast<const double2 *>(member_ptr(a.x, bt.ws, mk));
+    const double2 *u2 = reinterpret_cast<const double2 *>(member_ptr(a.u, bt.ws, mk));
+    const double2 *l2 = reinterpret_cast<const double2 *>(member_ptr(a.lx, bt.ws, mk));
+    const double2 *c2 = reinterpret_cast<const double2 *>(M.cen);
+    const double *__restrict__ etak = member_ptr(a.eta, bt.ws, mk);
+    double *__restrict__ outk = member_ptr(a.out, bt.ws, mk);
+    // column 0 has no R_{-1}: its second dot runs against x and is not used
+    const double *__restrict__ rjm1 = member_ptr(a.rjm1 ? a.rjm1 : a.x, bt.ws, mk);
+    const Halo &h = M.halo;
+    const int t = threadIdx.x;
+    const int q = t & (L - 1);
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    double r0 = 0.0, r1 = 0.0;
+    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C;
+        const int cnt = min(C, n - c0);
+        const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
+        __syncthreads();   // the previous chunk's readers are done
+        for (int m = t; m < cnt + hn; m += kJtvLdsBlock) {
+            const bool own = m < cnt;
+            const int j = own ? c0 + m : h.hids[h0 + (m - cnt)];
+            const int sl = own ? m : C + (m - cnt);
+            const double2 v0 = x2[2 * (size_t)j], v1 = x2[2 * (size_t)j + 1];
+            const double2 w0 = u2[2 * (size_t)j], w1 = u2[2 * (size_t)j + 1];
+            const double2 e0 = c2[2 * (size_t)j], e1 = c2[2 * (size_t)j + 1];
+            const double2 l0 = l2[2 * (size_t)j], l1 = l2[2 * (size_t)j + 1];
+            const double vx = v0.x, vy = v0.y, vz = v1.x, vh = v1.y;
+            const double wx = w0.x, wy = w0.y, wz = w1.x;
+            const double cx = e0.x, cy = e0.y, cz = e1.x, ra = e1.y;
+            const double sj = vx * (cy * wz - cz * wy) + vy * (cz * wx - cx * wz) + vz * (cx * wy - cy * wx);
+            const double vn = cx * vx + cy * vy + cz * vz;
+            nA[sl] = make_double2(sj * ra, (vx - vn * cx) * ra);
+            nB[sl] = make_double2((vy - vn * cy) * ra, (vz - vn * cz) * ra);
+            nC[sl] = make_double2(vh * ra, cx);
+            nD[sl] = make_double2(cy, cz);
+            nE[sl] = make_double2(l0.x * ra, l0.y * ra);
+            nF[sl] = make_double2(l1.x * ra, l1.y * ra);
+            if (own) {
+                oU0[m] = w0;
+                oU1[m] = w1;
+                oX0[m] = v0;
+                oX1[m] = v1;
+                oE[m] = make_double2(etak[j], 1.0 / ra);
+            }
+        }
+        __syncthreads();
+        const int li = t / L;
+        if (li >= cnt) continue;
+        const int i = c0 + li;
+        const double2 A0 = nA[li], B0 = nB[li], C0 = nC[li], D0 = nD[li], E0 = nE[li], F0 = nF[li];
+        Cell ci;
+        ci.x = C0.y;
+        ci.y = D0.x;
+        ci.z = D0.y;
+        ci.ra = 0.0;
+        const double Si = A0.x, tx = A0.y, ty = B0.x, tz = B0.y, Hi = C0.x;
+        const double lxi[4] = {E0.x, E0.y, F0.x, F0.y};
+        double vsx = 0.0, vsy = 0.0, vsz = 0.0, gq = 0.0, drx = 0.0, dry = 0.0, drz = 0.0;
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int e = 6 * i + slot_of<L>(q, k);
+            const int lj = h.lnbr[e];
+            const double c = M.cl[e];
+            const double2 Aj = nA[lj], Bj = nB[lj], Cj = nC[lj], Dj = nD[lj], Ej = nE[lj], Fj = nF[lj];
+            Cell cj;
+            cj.x = Cj.y;
+            cj.y = Dj.x;
+            cj.z = Dj.y;
+            cj.ra = 0.0;
+            const EdgeW w = edge_weights_short(ci, cj, c, M.half_r);
+            const double ds = Si - Aj.x;
+            vsx = fma(w.bx, ds, vsx);
+            vsy = fma(w.by, ds, vsy);
+            vsz = fma(w.bz, ds, vsz);
+            gq = fma(w.az, tz + Bj.y, fma(w.ay, ty + Bj.x, fma(w.ax, tx + Aj.y, gq)));
+            const double dh = Hi - Cj.x;
+            drx = fma(w.ax, dh, drx);
+            dry = fma(w.ay, dh, dry);
+            drz = fma(w.az, dh, drz);
+            const double lxj[4] = {Ej.x, Ej.y, Fj.x, Fj.y};
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) d[bb] = fma(c, lxj[bb] - lxi[bb], d[bb]);
+        }
+        vsx = grp_sum<L>(vsx);
+        vsy = grp_sum<L>(vsy);
+        vsz = grp_sum<L>(vsz);
+        gq = grp_sum<L>(gq);
+        drx = grp_sum<L>(drx);
+        dry = grp_sum<L>(dry);
+        drz = grp_sum<L>(drz);
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) d[bb] = grp_sum<L>(d[bb]);
+        const double2 U0 = oU0[li], U1 = oU1[li], X0 = oX0[li], X1 = oX1[li], EE = oE[li];
+        const double ux = U0.x, uy = U0.y, uz = U1.x, uh = U1.y;
+        const double xx = X0.x, xy = X0.y, xz = X1.x, xh = X1.y;
+        const double eta = EE.x, Ai = EE.y;
+        const double nx = ci.x, ny = ci.y, nz = ci.z;
+        const double qq = -Ai * gq;                              // (G^T x_vel)_i
+        const double rx = Ai * drx, ry = Ai * dry, rz = Ai * drz;  // (D^T x_h)_i
+        double o[4];
+        o[0] = sc * (-Ai * vsx + eta * (ny * xz - nz * xy) - qq * ux - uh * rx - nu * Ai * d[0]);
+        o[1] = sc * (-Ai * vsy + eta * (nz * xx - nx * xz) - qq * uy - uh * ry - nu * Ai * d[1]);
+        o[2] = sc * (-Ai * vsz + eta * (nx * xy - ny * xx) - qq * uz - uh * rz - nu * Ai * d[2]);
+        o[3] = sc * (-g * qq - (rx * ux + ry * uy + rz * uz) - nu * Ai * d[3]);
+        const double xs[4] = {xx, xy, xz, xh};
+#pragma unroll
+        for (int kc = 0; kc < kCompIter<L>; ++kc) {
+            const int bb = comp_of<L>(q, kc);
+            const int oi = 4 * i + bb;
+            double ob = o[bb];
+#pragma unroll
+            for (int k = 0; k < kPmax; ++k)
+                if (k < a.naxpy) ob += cax[k] * axv[k][oi];
+            outk[oi] = ob;
+            if (EPI == kEpiIom2) {
+                r0 = fma(ob, xs[bb], r0);
+                r1 = fma(ob, rjm1[oi], r1);
+            } else if (EPI == kEpiNorm) {
+                r0 = fma(ob, ob, r0);
+            }
+        }
+    }
+    if (EPI == kEpiNone) return;
+    double *parts = (EPI == kEpiIom2 ? a.dot_out : a.nrm_out) + (size_t)mk * kPartStride;
+    constexpr int NV = EPI == kEpiIom2 ? 2 : 1;
+    double v[2] = {r0, r1};
+    block_sum_all<2>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) parts[blockIdx.x * NV + k] = v[k];
 }
 
 // out (= or +=) scale * sum_{r < R} coef_r K(a_r, b_r), a_r = a0 + r sa,
@@ -565,12 +735,28 @@ void lapT_launch(const DevMesh &M, const double *psi, double *out, const Batch &
     hipLaunchKernelGGL(k_lapT<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b);
 }
 
+// Returns the number of partials the launch writes per member (0 without an
+// epilogue).
 template <int L>
-void jtv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+int jtv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
+    if (M.halo.nchunks > 0 && L == kJtvLdsL && red_parts(M.n) % kXcd == 0) {
+        // as the forward LDS product: no more blocks than chunks, except for
+        // norm partials, whose consumers sum red_parts(n)
+        const int cap = (M.halo.nchunks + kXcd - 1) / kXcd * kXcd;
+        const int np = epi == kEpiNorm ? red_parts(M.n) : (cap < red_parts(M.n) ? cap : red_parts(M.n));
+        const dim3 grid(np, b.nm), block(kJtvLdsBlock);
+        if (epi == kEpiIom2)
+            hipLaunchKernelGGL(k_jtv_lds<kEpiIom2>, grid, block, 0, s, M, a, b);
+        else if (epi == kEpiNorm)
+            hipLaunchKernelGGL(k_jtv_lds<kEpiNorm>, grid, block, 0, s, M, a, b);
+        else
+            hipLaunchKernelGGL(k_jtv_lds<kEpiNone>, grid, block, 0, s, M, a, b);
+        return epi == kEpiNone ? 0 : np;
+    }
     if (epi == kEpiNone) {
         hipLaunchKernelGGL((k_jtv<kEpiNone, L>), dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0,
                            s, M, a, b);
-        return;
+        return 0;
     }
     const int grid = red_parts(M.n), block = red_block(M.n);
     if (epi == kEpiIom2) {
@@ -579,6 +765,7 @@ void jtv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipS
         const int nb = block < kJtvMaxBlock<kEpiNorm> ? block : kJtvMaxBlock<kEpiNorm>;
         hipLaunchKernelGGL((k_jtv<kEpiNorm, L>), dim3(grid, b.nm), dim3(nb), 0, s, M, a, b);
     }
+    return grid;
 }
 
 template <int L>
@@ -601,10 +788,11 @@ void launch_lapT(const DevMesh &M, const double *psi, double *out, const Batch &
 }
 
 int launch_jtv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s) {
-#define XRB_CALL(L) jtv_launch<L>(M, a, epi, b, s)
+    int np = 0;
+#define XRB_CALL(L) np = jtv_launch<L>(M, a, epi, b, s)
     XRB_LANES_DISPATCH(XRB_CALL)
 #undef XRB_CALL
-    return epi == kEpiNone ? 0 : red_parts(M.n);
+    return np;
 }
 
 void launch_kpairs(const DevMesh &M, const KPairArgs &k, const Batch &b, hipStream_t s) {

@@ -1320,10 +1320,11 @@ int adj_phi(xrb_ctx *ctx, const PhiTape &tape, const double *u, const double *et
                 a.rjm1 = rm;
                 a.ctl = A.actl;
                 a.dot_out = A.dot_parts;
-                timed(ctx, XRB_K_JV_IOM2, [&] { launch_jtv(ctx->M, a, kEpiIom2, b1, s); });
+                int np_dot = np;   // the product's partial count (its LDS form may take fewer blocks)
+                timed(ctx, XRB_K_JV_IOM2, [&] { np_dot = launch_jtv(ctx->M, a, kEpiIom2, b1, s); });
                 timed(ctx, XRB_K_IOM2_UPD, [&] {
                     launch_iom2_update(n, j, rn, rj, rm, A.actl, nrm_buf(j),
-                                       j == 0 ? np : upd_parts(n), A.dot_parts, np,
+                                       j == 0 ? np : upd_parts(n), A.dot_parts, np_dot,
                                        nrm_buf(j + 1), b1, s);
                 });
                 st->matvecs++;

@@ -5,11 +5,13 @@
 //   int mu t^(j-1)/(j-1)! dt, and the A-term int K(mu, y) dt, where
 //   K(a, b) = grad_u <a, J(u) b>.
 //
-//   k_lapT    L^T psi on four fields (prepass of the two-ring (L^T)^2)
+//   k_lapT    L^T psi on four fields (prepass of the two-ring (L^T)^2;
+//             k_lapT_lds on grids with chunk tables)
 //   k_jtv     dt J(u)^T x (+ axpys) with the IOM2 / norm epilogues of k_jv,
 //             so the IOM2 driver builds a Krylov space of A^T unchanged
 //             (k_jtv_lds: its form on grids with chunk tables)
-//   k_kpairs  acc += sum_r c_r K(a_r, b_r)
+//   k_kpairs  acc += sum_r c_r K(a_r, b_r) (k_kpairs_lds on grids with
+//             chunk tables)
 //   k_lincomb_multi  several combinations of one contiguous basis at once
 //   k_zgemm   Z_r = sum_c z_rc What_c (the forward substep's solution basis)
 //   k_adj_gexp    finishes the last IOM2 column, exp(tau G) of the adjoint
@@ -65,6 +67,64 @@ __global__ void __launch_bounds__(256) k_lapT(DevMesh M, const double *__restric
         for (int b = 0; b < 4; ++b) a[b] = grp_sum<L>(a[b]);
 #pragma unroll
         for (int b = q; b < 4; b += L) out[4 * i + b] = Ai * a[b];
+    }
+}
+
+// k_lapT on grids with chunk tables: the chunk's cells and their one-ring
+// halo staged in LDS as psi ra (ra = 1/A), then
+// (L^T psi)_i = A_i sum_s c_s ((psi ra)_j - (psi ra)_i) with two lanes per
+// cell.  Any grid that is a multiple of the XCD count.
+constexpr int kLapTLdsL = 2;
+constexpr int kLapTLdsBlock = kChunk * kLapTLdsL;
+
+__global__ void __launch_bounds__(kLapTLdsBlock) k_lapT_lds(DevMesh M, const double *__restrict__ psi,
+                                                             double *__restrict__ out, Batch bt) {
+    constexpr int L = kLapTLdsL, C = kChunk, HM = kHaloMax;
+    __shared__ double2 sx[(C + HM) * 2];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const double2 *x2 = reinterpret_cast<const double2 *>(member_ptr(psi, bt.ws, mk));
+    out = member_ptr(out, bt.ws, mk);
+    const Halo &h = M.halo;
+    const int n = M.n;
+    const int t = threadIdx.x, q = t & (L - 1);
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
+        __syncthreads();   // the previous chunk's readers are done
+        for (int k = t; k < 2 * (cnt + hn); k += kLapTLdsBlock) {
+            const int m = k >> 1;
+            const int j = m < cnt ? c0 + m : h.hids[h0 + (m - cnt)];
+            const double ra = M.cen[4 * (size_t)j + 3];
+            const double2 v = x2[2 * (size_t)j + (k & 1)];
+            sx[(m < cnt ? 2 * m : 2 * (C + m - cnt)) + (k & 1)] = make_double2(v.x * ra, v.y * ra);
+        }
+        __syncthreads();
+        const int li = t / L;
+        if (li >= cnt) continue;
+        const int i = c0 + li;
+        const double2 a0 = sx[2 * li], a1 = sx[2 * li + 1];
+        const double pi[4] = {a0.x, a0.y, a1.x, a1.y};
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < kSlotIter<L>; ++k) {
+            const int e = 6 * i + slot_of<L>(q, k);
+            const int lj = h.lnbr[e];
+            const double c = M.cl[e];
+            const double2 b0 = sx[2 * lj], b1 = sx[2 * lj + 1];
+            const double pj[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) acc[bb] = fma(c, pj[bb] - pi[bb], acc[bb]);
+        }
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc[bb] = grp_sum<L>(acc[bb]);
+        const double Ai = 1.0 / M.cen[4 * (size_t)i + 3];
+#pragma unroll
+        for (int k = 0; k < kCompIter<L>; ++k) out[4 * i + comp_of<L>(q, k)] = Ai * acc[comp_of<L>(q, k)];
     }
 }
 
@@ -449,6 +509,147 @@ __global__ void __launch_bounds__(256) k_kpairs(DevMesh M, KPairArgs k, Batch bt
     }
 }
 
+// k_kpairs on grids with chunk tables.  Per chunk, the centres and areas of
+// the chunk's cells and their halo are staged once, and each lane forms the
+// weights of its edge slots once (edge_weights_short) and keeps them in
+// registers over all pairs; per pair, one thread per staged cell loads a_r
+// and b_r and stores what the edges take -- c ra, (P a) ra, a_h ra (c =
+// a . (b x n), ra = 1/A) and b_vel -- and the chunk's own cells keep a and b.
+// Two lanes serve a cell; the pair sums accumulate in registers and the
+// chunk's outputs are written once.
+constexpr int kKpLdsL = 2;
+constexpr int kKpLdsBlock = kChunk * kKpLdsL;
+
+__global__ void __launch_bounds__(kKpLdsBlock, 4) k_kpairs_lds(DevMesh M, KPairArgs k, Batch bt) {
+    constexpr int L = kKpLdsL, C = kChunk, S = kChunk + kHaloMax;
+    __shared__ double2 gC0[S], gC1[S];                 // centre x, y; centre z, ra
+    __shared__ double2 pA[S], pB[S], pC[S], pD[S];     // (c ra, (Pa)_x ra) ((Pa)_y ra, (Pa)_z ra) (a_h ra, b_x) (b_y, b_z)
+    __shared__ double2 oA0[C], oA1[C], oB1[C];         // own (a_x, a_y) (a_z, -) (b_z, b_h)
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const int n = M.n;
+    const int t = threadIdx.x, q = t & (L - 1);
+    double *__restrict__ out = member_ptr(k.out, bt.ws, mk);
+    const double2 *c2 = reinterpret_cast<const double2 *>(M.cen);
+    const Halo &h = M.halo;
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
+        const int li = t / L;
+        const bool act = li < cnt;
+        const int i = c0 + (act ? li : 0);
+        __syncthreads();   // the previous chunk's readers are done
+        for (int m = t; m < cnt + hn; m += kKpLdsBlock) {
+            const int j = m < cnt ? c0 + m : h.hids[h0 + (m - cnt)];
+            const int sl = m < cnt ? m : C + (m - cnt);
+            gC0[sl] = c2[2 * (size_t)j];
+            gC1[sl] = c2[2 * (size_t)j + 1];
+        }
+        __syncthreads();
+        // this lane's edge weights, kept over the pairs
+        EdgeW w[kSlotIter<L>];
+        int lj[kSlotIter<L>];
+        const double2 I0 = gC0[act ? li : 0], I1 = gC1[act ? li : 0];
+        Cell ci;
+        ci.x = I0.x;
+        ci.y = I0.y;
+        ci.z = I1.x;
+        ci.ra = I1.y;
+#pragma unroll
+        for (int s = 0; s < kSlotIter<L>; ++s) {
+            const int e = 6 * i + slot_of<L>(q, s);
+            lj[s] = h.lnbr[e];
+            const double2 J0 = gC0[lj[s]], J1 = gC1[lj[s]];
+            Cell cj;
+            cj.x = J0.x;
+            cj.y = J0.y;
+            cj.z = J1.x;
+            cj.ra = 0.0;
+            w[s] = edge_weights_short(ci, cj, M.cl[e], M.half_r);
+        }
+        const double nx = ci.x, ny = ci.y, nz = ci.z;
+        const double Ai = 1.0 / ci.ra;
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int pr = 0; pr < k.R; ++pr) {
+            const double cr = k.scale * (k.coef ? k.coef[pr] : 1.0);
+            if (cr == 0.0) continue;   // the same for every thread of the launch
+            const double2 *a2 = reinterpret_cast<const double2 *>(member_ptr(k.a0, bt.ws, mk) + (size_t)pr * k.sa);
+            const double2 *b2 = reinterpret_cast<const double2 *>(member_ptr(k.b0, bt.ws, mk) + (size_t)pr * k.sb);
+            __syncthreads();   // the previous pair's readers are done
+            for (int m = t; m < cnt + hn; m += kKpLdsBlock) {
+                const int j = m < cnt ? c0 + m : h.hids[h0 + (m - cnt)];
+                const int sl = m < cnt ? m : C + (m - cnt);
+                const double2 A0 = a2[2 * (size_t)j], A1 = a2[2 * (size_t)j + 1];
+                const double2 B0 = b2[2 * (size_t)j], B1 = b2[2 * (size_t)j + 1];
+                const double2 J0 = gC0[sl], J1 = gC1[sl];
+                const double cx = J0.x, cy = J0.y, cz = J1.x, ra = J1.y;
+                const double ax = A0.x, ay = A0.y, az = A1.x, ah = A1.y;
+                const double bx = B0.x, by = B0.y, bz = B1.x;
+                const double cc = ax * (by * cz - bz * cy) + ay * (bz * cx - bx * cz) + az * (bx * cy - by * cx);
+                const double an = cx * ax + cy * ay + cz * az;
+                pA[sl] = make_double2(cc * ra, (ax - an * cx) * ra);
+                pB[sl] = make_double2((ay - an * cy) * ra, (az - an * cz) * ra);
+                pC[sl] = make_double2(ah * ra, bx);
+                pD[sl] = make_double2(by, bz);
+                if (m < cnt) {
+                    oA0[m] = A0;
+                    oA1[m] = A1;
+                    oB1[m] = B1;
+                }
+            }
+            __syncthreads();
+            if (!act) continue;
+            const double2 PA = pA[li], PB = pB[li], PC = pC[li], PD = pD[li];
+            const double ci_c = PA.x, tx = PA.y, ty = PB.x, tz = PB.y, hi = PC.x;
+            const double bx = PC.y, by = PD.x, bz = PD.y;
+            double zb = 0.0, vcx = 0.0, vcy = 0.0, vcz = 0.0, gq = 0.0, drx = 0.0, dry = 0.0, drz = 0.0;
+#pragma unroll
+            for (int s = 0; s < kSlotIter<L>; ++s) {
+                const double2 QA = pA[lj[s]], QB = pB[lj[s]], QC = pC[lj[s]], QD = pD[lj[s]];
+                const EdgeW &ww = w[s];
+                zb = fma(ww.bz, bz + QD.y, fma(ww.by, by + QD.x, fma(ww.bx, bx + QC.y, zb)));
+                const double dc = ci_c - QA.x;
+                vcx = fma(ww.bx, dc, vcx);
+                vcy = fma(ww.by, dc, vcy);
+                vcz = fma(ww.bz, dc, vcz);
+                gq = fma(ww.az, tz + QB.y, fma(ww.ay, ty + QB.x, fma(ww.ax, tx + QA.y, gq)));
+                const double dh = hi - QC.x;
+                drx = fma(ww.ax, dh, drx);
+                dry = fma(ww.ay, dh, dry);
+                drz = fma(ww.az, dh, drz);
+            }
+            zb = grp_sum<L>(zb);
+            vcx = grp_sum<L>(vcx);
+            vcy = grp_sum<L>(vcy);
+            vcz = grp_sum<L>(vcz);
+            gq = grp_sum<L>(gq);
+            drx = grp_sum<L>(drx);
+            dry = grp_sum<L>(dry);
+            drz = grp_sum<L>(drz);
+            const double2 OA0 = oA0[li], OA1 = oA1[li], OB1 = oB1[li];
+            const double ax = OA0.x, ay = OA0.y, az = OA1.x, bh = OB1.y;
+            const double qq = -Ai * gq;
+            const double rx = Ai * drx, ry = Ai * dry, rz = Ai * drz;
+            const double anx = ay * nz - az * ny, any = az * nx - ax * nz, anz = ax * ny - ay * nx;
+            o[0] += cr * (-zb * anx + Ai * vcx - qq * bx - bh * rx);
+            o[1] += cr * (-zb * any + Ai * vcy - qq * by - bh * ry);
+            o[2] += cr * (-zb * anz + Ai * vcz - qq * bz - bh * rz);
+            o[3] += cr * (-(rx * bx + ry * by + rz * bz));
+        }
+        if (!act) continue;
+#pragma unroll
+        for (int kc = 0; kc < kCompIter<L>; ++kc) {
+            const int bb = comp_of<L>(q, kc);
+            const int oi = 4 * i + bb;
+            out[oi] = k.accumulate ? out[oi] + o[bb] : o[bb];
+        }
+    }
+}
+
 // outs[k] (= or +=, bit k of accmask) sum_{r < nv} C[k * ldc + r] v_r,
 // v_r = vbase + r * vstride; k < nout <= kMultiOut
 __global__ void __launch_bounds__(kBlock) k_lincomb_multi(int n4, MultiArgs a, Batch bt) {
@@ -732,6 +933,14 @@ __global__ void __launch_bounds__(1024) k_adj_vanloan(const PhiCtl *c, const Phi
 
 template <int L>
 void lapT_launch(const DevMesh &M, const double *psi, double *out, const Batch &b, hipStream_t s) {
+    if (M.halo.nchunks > 0 && L == kLapTLdsL) {
+        // the forward LDS Laplacian's grid: at most the chunk count (whole XCDs)
+        const int want = M.lap_grid > 0 ? M.lap_grid : 4 * 256;
+        const int cap = (M.halo.nchunks + kXcd - 1) / kXcd * kXcd;
+        const int grid = want < cap ? want : cap;
+        hipLaunchKernelGGL(k_lapT_lds, dim3(grid, b.nm), dim3(kLapTLdsBlock), 0, s, M, psi, out, b);
+        return;
+    }
     hipLaunchKernelGGL(k_lapT<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, psi, out, b);
 }
 
@@ -770,6 +979,12 @@ int jtv_launch(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipSt
 
 template <int L>
 void kpairs_launch(const DevMesh &M, const KPairArgs &k, const Batch &b, hipStream_t s) {
+    if (M.halo.nchunks > 0 && L == kKpLdsL) {
+        // every chunk once: the chunk count rounded up to whole XCDs
+        const int grid = (M.halo.nchunks + kXcd - 1) / kXcd * kXcd;
+        hipLaunchKernelGGL(k_kpairs_lds, dim3(grid, b.nm), dim3(kKpLdsBlock), 0, s, M, k, b);
+        return;
+    }
     hipLaunchKernelGGL(k_kpairs<L>, dim3(cells_grid(M.n, 256, L), b.nm), dim3(256), 0, s, M, k, b);
 }
 

@@ -76,8 +76,10 @@ def test_jtv_parity_and_dot(X, level):
     assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(w) * np.linalg.norm(to_np(ctx.jv(u, v)))
 
 
-@pytest.mark.parametrize("level", [2, 5])
+@pytest.mark.parametrize("level", [2, 5, 6])
 def test_ktv_parity(X, level):
+    """Levels 2 and 5 take the gather kernel, level 6 (chunk tables) the
+    LDS-staged one."""
     ctx, s = setup(X, level)
     a = rand_dir(s.n, 7 + level)
     b = rand_dir(s.n, 8 + level)

@@ -223,13 +223,42 @@ __global__ void __launch_bounds__(kBlock) k_combine(int n4, double *__restrict__
     for (int j = 0; j < kPmax; ++j)
         w[j] = (j < a.p && !((zmask >> j) & 1)) ? member_ptr(a.w[j], bt.ws, mk) : nullptr;
     const double *V = member_ptr(a.V, bt.ws, mk);
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += gridDim.x * blockDim.x) {
-        double acc = 0.0;
+    // 16-byte pairs (n4 is even, vectors start 16-byte aligned); the basis
+    // is read four vectors at a time so that four independent loads are in
+    // flight per thread, and each element still sums its terms in order
+    const int n2 = n4 / 2;
+    const size_t s2 = (size_t)n4 / 2;   // one basis vector, in pairs
+    const double2 *V2 = reinterpret_cast<const double2 *>(V);
+    double2 *y2 = reinterpret_cast<double2 *>(y);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += gridDim.x * blockDim.x) {
+        double ax = 0.0, ay = 0.0;
         for (int j = 0; j < a.p; ++j)
-            if (w[j]) acc += cf[j] * w[j][i];
-        const double *vb = V + i;
-        for (int k = 0; k < nb; ++k) acc += cf[a.p + k] * vb[(size_t)k * n4];
-        y[i] = acc;
+            if (w[j]) {
+                const double2 v = reinterpret_cast<const double2 *>(w[j])[i];
+                ax += cf[j] * v.x;
+                ay += cf[j] * v.y;
+            }
+        const double2 *vb = V2 + i;
+        int k = 0;
+        for (; k + 4 <= nb; k += 4) {
+            const double2 v0 = vb[(size_t)k * s2], v1 = vb[(size_t)(k + 1) * s2];
+            const double2 v2 = vb[(size_t)(k + 2) * s2], v3 = vb[(size_t)(k + 3) * s2];
+            const double c0 = cf[a.p + k], c1 = cf[a.p + k + 1], c2 = cf[a.p + k + 2], c3 = cf[a.p + k + 3];
+            ax += c0 * v0.x;
+            ay += c0 * v0.y;
+            ax += c1 * v1.x;
+            ay += c1 * v1.y;
+            ax += c2 * v2.x;
+            ay += c2 * v2.y;
+            ax += c3 * v3.x;
+            ay += c3 * v3.y;
+        }
+        for (; k < nb; ++k) {
+            const double2 v = vb[(size_t)k * s2];
+            ax += cf[a.p + k] * v.x;
+            ay += cf[a.p + k] * v.y;
+        }
+        y2[i] = make_double2(ax, ay);
     }
 }
 
@@ -403,7 +432,7 @@ void launch_combine(int n4, double *y, int p, const double *const *w, const int 
     a.p = p;
     for (int j = 0; j < p; ++j) a.w[j] = wzero[j] ? nullptr : w[j];
     a.V = V;
-    hipLaunchKernelGGL(k_combine, dim3(grid_elems(n4), b.nm), dim3(kBlock), 0, s, n4, y, a, ctl, b);
+    hipLaunchKernelGGL(k_combine, dim3(grid_elems(n4 / 2), b.nm), dim3(kBlock), 0, s, n4, y, a, ctl, b);
 }
 
 int launch_norms(int n, int nv, const double *const *vec, double *parts, const Batch &b,

@@ -46,8 +46,11 @@ JV_IOM2_BYTES_PER_CELL = 192.0
 IOM2_BYTES_PER_CELL = 128.0
 # one-ring Laplacian pass: x 32 + out 32 + neighbour ids 24 + Laplacian weights 48
 LAP_BYTES_PER_CELL = 136.0
+# IOM2 update fused with the next column's Laplacian: read w, v_j, v_{j-1},
+# write v_{j+1} and L v_{j+1}, neighbour ids 24 + Laplacian weights 48
+UPD_LAP_BYTES_PER_CELL = 232.0
 KERNEL_BYTES = {"jv_iom2": JV_IOM2_BYTES_PER_CELL, "iom2_update": IOM2_BYTES_PER_CELL,
-                "lap": LAP_BYTES_PER_CELL}
+                "lap": LAP_BYTES_PER_CELL, "upd_lap": UPD_LAP_BYTES_PER_CELL}
 
 # headline: level-8 jet, exprb53
 JET_STEPS, JET_DT, JET_EVALS_PER_STEP = 6, 1800.0, 3

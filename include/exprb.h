@@ -414,7 +414,9 @@ enum {
     XRB_K_JV_OTHER = 5,  /* Jacobian products of the w_j recurrence/stages */
     XRB_K_RHS = 6,       /* right-hand side F(u)                        */
     XRB_K_VEC = 7,       /* linear combinations, norms                  */
-    XRB_K_COUNT = 8
+    XRB_K_UPD_LAP = 8,   /* IOM2 update fused with the next column's L x
+                            (grids above 16384 cells)                   */
+    XRB_K_COUNT = 9
 };
 xrb_status xrb_profile(xrb_ctx *ctx, int enable);
 /* Since the last xrb_profile(ctx, N >= 1): device milliseconds summed over

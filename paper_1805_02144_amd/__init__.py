@@ -28,7 +28,7 @@ EXPORTS = ["xrb_default_params", "xrb_create", "xrb_destroy", "xrb_set_stream", 
            "xrb_schedule_set_member", "xrb_schedule_get_member", "xrb_profile_overhead",
            "xrb_jv_static", "xrb_step_batch_capture", "xrb_graph_launch"]
 
-KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec"]
+KERNELS = ["jv_iom2", "lap", "iom2_update", "controller", "combine", "jv_other", "rhs", "vec", "upd_lap"]
 
 _dp = C.POINTER(C.c_double)
 

@@ -62,6 +62,8 @@ struct Work {
     double *Wr = nullptr;       // w_1 .. w_{p-1} of the recurrence
     double *y = nullptr;        // substep solution
     double *lap = nullptr;      // L x scratch
+    double *lapn = nullptr;     // L R_{j+1} from the fused update (next column's input)
+    double *wraw = nullptr;     // the IOM2 product's raw output when the update is fused
     double *eta = nullptr;      // V.u + f at the linearisation point
     double *rec = nullptr;      // per-cell record (u, centre, eta) there, 8 doubles per cell
     double *stage = nullptr;    // S_COUNT stage vectors
@@ -524,7 +526,7 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
     const double *wptr[kPmax + 1];
     wptr[0] = W.y;
     for (int j = 1; j <= p; ++j) wptr[j] = (j == p) ? W.V : W.Wr + (size_t)(j - 1) * n4;
-    auto nrm_buf = [&](int col) { return W.nrm_parts + (size_t)(col & 1) * kRedBlocks; };
+    auto nrm_buf = [&](int col) { return W.nrm_parts + (size_t)(col & 1) * kNrmRegion; };
 
     while (true) {
         bool any_live = false;
@@ -599,7 +601,8 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             ca.wp_zero = mm.wp_zero;
             ca.built = mm.built;
             ca.nrm_buf = mm.built & 1;
-            ca.n_nrm_in = upd_parts(n);   // the last column's norm comes from an IOM2 update
+            // the last column's norm comes from an IOM2 update
+            ca.n_nrm_in = iom2_chunked(ctx->M, nm) ? chunked_norm_parts(ctx->M) : upd_parts(n);
             ca.t_out = rho[mm.io];
             ca.n4 = (double)n4;
             ca.delta = P.delta;
@@ -657,32 +660,50 @@ int phi_batch(xrb_ctx *ctx, Work &W, const double *u, int p, const double *const
             for (auto &mm : ms)
                 if (!mm.done) mm.ready = true;
         }
-        // ---- step 2(i): IOM2 columns
+        // ---- step 2(i): IOM2 columns.  With the fused update (single states
+        // on grids with chunk tables) column j's update also forms L R_{j+1}
+        // for column j+1, in this attempt or, after a rejection that grows m,
+        // the next one (nothing else writes W.lapn, and the basis is kept);
+        // only a basis's first column takes a Laplacian pass of its own.
+        const bool chunked = iom2_chunked(ctx->M, nm), fused = upd_lap_fused(ctx->M, nm);
+        const int np_col = chunked ? chunked_norm_parts(ctx->M) : upd_parts(n);   // column norm partials
         for (int j = jlo; j < jhi; ++j) {
             const Batch bj = batch_of(W, W.plan, PF_IOM2_LO, j);
             double *rj = W.V + (size_t)j * n4;
             double *rn = W.V + (size_t)(j + 1) * n4;
             const double *rm = j > 0 ? W.V + (size_t)(j - 1) * n4 : nullptr;
-            if (!jv_fuses_lap(ctx->M, bj.nm))
-                timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, W.lap, bj, s); });
+            const bool own_lap = !jv_fuses_lap(ctx->M, bj.nm) && !(fused && j > 0);
+            if (own_lap) timed(ctx, XRB_K_LAP, [&] { launch_lap4(ctx->M, rj, W.lap, bj, s); });
             JvArgs a;
             a.u = u;
             a.eta = W.eta;
             a.rec = W.rec;
             a.x = rj;
-            a.lx = W.lap;
-            a.out = rn;
+            a.lx = (fused && j > 0) ? W.lapn : W.lap;
+            a.out = fused ? W.wraw : rn;
             a.j = j;
             a.rjm1 = rm;
             a.ctl = W.ctl;
             a.dot_out = W.dot_parts;
             int np_dot = np;   // the product's partial count (its LDS form may take fewer blocks)
             timed(ctx, XRB_K_JV_IOM2, [&] { np_dot = launch_jv(ctx->M, a, kEpiIom2, bj, s); });
-            timed(ctx, XRB_K_IOM2_UPD, [&] {
-                launch_iom2_update(n, j, rn, rj, rm, W.ctl, nrm_buf(j), j == 0 ? np : upd_parts(n),
-                                   W.dot_parts, np_dot,
-                                   nrm_buf(j + 1), bj, s);
-            });
+            const int np_nrm = j == 0 ? np : np_col;
+            if (fused) {
+                timed(ctx, XRB_K_UPD_LAP, [&] {
+                    launch_upd_lap(ctx->M, j, W.wraw, rj, rm, rn, W.lapn, W.ctl, nrm_buf(j), np_nrm,
+                                   W.dot_parts, np_dot, nrm_buf(j + 1), bj, s);
+                });
+            } else if (chunked) {
+                timed(ctx, XRB_K_IOM2_UPD, [&] {
+                    launch_iom2_update_lds(ctx->M, j, rn, rj, rm, W.ctl, nrm_buf(j), np_nrm, W.dot_parts,
+                                           np_dot, nrm_buf(j + 1), bj, s);
+                });
+            } else {
+                timed(ctx, XRB_K_IOM2_UPD, [&] {
+                    launch_iom2_update(n, j, rn, rj, rm, W.ctl, nrm_buf(j), np_nrm, W.dot_parts, np_dot,
+                                       nrm_buf(j + 1), bj, s);
+                });
+            }
         }
         // ---- steps 2(ii)-6 on the device
         {
@@ -829,8 +850,9 @@ int free_work(Work &W) {
 int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
     const int64_t n4 = ctx->n4;
     const int mmax = ctx->prm.m_max;
-    // member block: basis, recurrence, y, lap, eta, record (two vectors), stages
-    const int64_t nvec = (mmax + 1) + kPmax + 1 + 1 + 1 + 2 + S_COUNT;
+    // member block: basis, recurrence, y, lap, lapn, wraw, eta, record (two
+    // vectors), stages
+    const int64_t nvec = (mmax + 1) + kPmax + 1 + 1 + 2 + 1 + 2 + S_COUNT;
     W.nm = nm;
     W.ws = nm > 1 ? nvec * n4 : 0;
     const int64_t member_doubles = nvec * n4;
@@ -876,6 +898,10 @@ int alloc_work(xrb_ctx *ctx, Work &W, int nm) {
     W.y = p;
     p += n4;
     W.lap = p;
+    p += n4;
+    W.lapn = p;
+    p += n4;
+    W.wraw = p;
     p += n4;
     W.eta = p;
     p += n4;
@@ -1254,7 +1280,7 @@ int adj_phi(xrb_ctx *ctx, const PhiTape &tape, const double *u, const double *et
     Batch b1;
     b1.nm = 1;
     const int np = red_parts(n);
-    auto nrm_buf = [&](int col) { return A.nrm_parts + (size_t)(col & 1) * kRedBlocks; };
+    auto nrm_buf = [&](int col) { return A.nrm_parts + (size_t)(col & 1) * kNrmRegion; };
     const double *none[1] = {nullptr};
     const double zc0[1] = {0.0};
     for (int l = 0; l <= p; ++l)

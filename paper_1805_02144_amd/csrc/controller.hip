@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
     if (!member_active(bt.pred, mk)) return;
     PhiCtl *c = ctl0 + mk;
     const CtlArgs a = dargs ? dargs[mk] : a0;
-    const double *nrm_in = nrm_parts + (size_t)mk * kPartStride + (size_t)a.nrm_buf * kRedBlocks;
+    const double *nrm_in = nrm_parts + (size_t)mk * kPartStride + (size_t)a.nrm_buf * kNrmRegion;
     __shared__ double Bm[kMat], B2[kMat], B4[kMat], B6[kMat], Ue[kMat], Uo[kMat], Vm[kMat];
     __shared__ int piv_of[kLd];
     __shared__ double dinv_of[kLd];

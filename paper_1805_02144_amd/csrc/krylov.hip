@@ -125,64 +125,12 @@ __global__ void __launch_bounds__(kRedBlock) k_iom2_update(int n4, int j, double
     PhiCtl *ctl = ctl_member(ctl0, mk);
     // a new basis (j = 0) starts fresh; later columns stop after a breakdown
     if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
-    // prologue: ||R_j||^2, <w, R_j>, <w, R_{j-1}> and max column sum of H
-    double v[3] = {0.0, 0.0, 0.0};
-    const double *nk = nrm_in + (size_t)mk * kPartStride;
-    const double *dk = dot_in + (size_t)mk * kPartStride;
-    for (int b = threadIdx.x; b < np_nrm; b += blockDim.x) v[0] += nk[b];
-    for (int b = threadIdx.x; b < np_dot; b += blockDim.x) {
-        v[1] += dk[2 * b];
-        v[2] += dk[2 * b + 1];
-    }
-    double cm_ = j > 0 ? column_abs_sum(ctl, j) : 0.0;
-    {
-        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-        const int nw = blockDim.x >> 6;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v[k] = wave_sum(v[k]);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double o = __shfl_down(cm_, off, 64);
-            cm_ = o > cm_ ? o : cm_;
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) pro[wid * 4 + k] = v[k];
-            pro[wid * 4 + 3] = cm_;
-        }
-        __syncthreads();
-        double t[3] = {0.0, 0.0, 0.0}, bn = 0.0;
-        for (int q = 0; q < nw; ++q) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) t[k] += pro[q * 4 + k];
-            bn = pro[q * 4 + 3] > bn ? pro[q * 4 + 3] : bn;
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v[k] = t[k];
-        cm_ = bn;
-    }
-    const bool writer = blockIdx.x == 0 && threadIdx.x == 0;
-    const ColumnScale cs = finalize_column_bn(ctl, j, v[0], cm_, writer);
-    if (cs.stop) return;
-    const double sj = cs.sigma;
-    const double sm = j > 0 ? ctl->sigma[j - 1] : 0.0;
-    const double hjj = sj * sj * v[1];
-    const double hmj = j > 0 ? sj * sm * v[2] : 0.0;
-    if (writer) {
-        ctl->H[j * kMmax + j] = hjj;
-        if (j > 0) ctl->H[(j - 1) * kMmax + j] = hmj;
-    }
-    const double cj = hjj * sj;
-    const double cm = hmj * sm;
+    // prologue: ||R_j||^2, <w, R_j>, <w, R_{j-1}>, max column sum of H, scale
+    const IomCoef kc = iom2_coefficients(ctl, j, mk, nrm_in, np_nrm, dot_in, np_dot, pro);
+    if (kc.stop) return;
     double r = 0.0;
     auto upd = [&](double2 a, double2 b, double2 c) {
-        double2 x;
-        x.x = sj * a.x - cj * b.x;
-        x.y = sj * a.y - cj * b.y;
-        if (j > 0) {
-            x.x -= cm * c.x;
-            x.y -= cm * c.y;
-        }
+        const double2 x = iom2_pair(kc, j, a, b, c);
         r += x.x * x.x;
         r += x.y * x.y;
         return x;

@@ -11,6 +11,7 @@
 // identical in all L).  The two-ring dissipation stencil L(L x) takes L x
 // from a preceding one-ring pass (launch_lap4), or, in small eight-lane
 // launches, forms it in the product kernel with the same rounding.
+#include "column.h"
 #include "reduce.h"
 #include "stencil_common.h"
 #include "xrb_internal.h"
@@ -140,6 +141,196 @@ __global__ void __launch_bounds__(kLapLdsBlock) k_lap4_lds(DevMesh M, const doub
         for (int bb = 0; bb < 4; ++bb) acc[bb] = grp_sum<L>(acc[bb]);
 #pragma unroll
         for (int k = 0; k < kCompIter<L>; ++k) out[4 * i + comp_of<L>(q, k)] = acc[comp_of<L>(q, k)];
+    }
+}
+
+// The chunked IOM2 update of column j on grids with chunk tables (512
+// threads per block, chunks XCD-major).  Every block first takes the update's
+// prologue (the column's dots and norm from the partials, its scale and H
+// entries: iom2_coefficients).  Per chunk, thread t forms pair t of the
+// chunk's cells, t < 2 cnt, of R_{j+1} = sj w - cj R_j - cm R_{j-1}
+// (iom2_pair) and adds x.x^2 + x.y^2 to its share of ||R_{j+1}||^2.  With
+// per_chunk the shares are summed by block_sum_all after every chunk and
+// stored at the chunk's index (any grid gives the same bits); without, once
+// per block at the block's index (the grid must be the same).  The two
+// kernels below do exactly that, so they give the same bits.
+constexpr int kUpdLapL = 2;
+constexpr int kUpdLapBlock = kChunk * kUpdLapL;
+
+// R_{j+1} over w in place, with the column-norm partials.
+__global__ void __launch_bounds__(kUpdLapBlock) k_iom2_update_lds(DevMesh M, int j, double *w,
+                                                                 const double *rj, const double *rjm1,
+                                                                 PhiCtl *ctl0, const double *nrm_in,
+                                                                 int np_nrm, const double *dot_in,
+                                                                 int np_dot, double *nrm_out,
+                                                                 int per_chunk, Batch bt) {
+    constexpr int C = kChunk;
+    __shared__ double pro[16 * 4];
+    __shared__ double lds[16];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    double2 *w2 = reinterpret_cast<double2 *>(member_ptr(w, bt.ws, mk));
+    const double2 *r2 = reinterpret_cast<const double2 *>(member_ptr(rj, bt.ws, mk));
+    const double2 *m2 = reinterpret_cast<const double2 *>(member_ptr(j > 0 ? rjm1 : rj, bt.ws, mk));
+    double *parts = nrm_out + (size_t)mk * kPartStride;
+    const Halo &h = M.halo;
+    const int n = M.n;
+    const int t = threadIdx.x;
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    const double2 z2 = make_double2(0.0, 0.0);
+    double2 pw = z2, pr = z2, pm = z2;
+    auto fetch = [&](int ck) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        const bool in = t < 2 * cnt;
+        const size_t e = 2 * (size_t)c0 + (in ? t : 0);
+        pw = in ? w2[e] : z2;
+        pr = in ? r2[e] : z2;
+        pm = (in && j > 0) ? m2[e] : z2;
+    };
+    const int ck0 = xcd * cpx + kk;
+    if (ck0 < ck_end) fetch(ck0);
+    PhiCtl *ctl = ctl_member(ctl0, mk);
+    // a new basis (j = 0) starts fresh; later columns stop after a breakdown
+    if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
+    const IomCoef kc = iom2_coefficients(ctl, j, mk, nrm_in, np_nrm, dot_in, np_dot, pro);
+    if (kc.stop) return;
+    double r = 0.0;
+    for (int ck = ck0; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        if (ck != ck0) fetch(ck);
+        if (t < 2 * cnt) {
+            const double2 x = iom2_pair(kc, j, pw, pr, pm);
+            w2[2 * (size_t)c0 + t] = x;
+            r += fma(x.y, x.y, x.x * x.x);
+        }
+        if (per_chunk) {
+            double vv[1] = {r};
+            block_sum_all<1>(vv, lds);
+            if (t == 0) parts[ck] = vv[0];
+            r = 0.0;
+        }
+    }
+    if (!per_chunk) {
+        double vv[1] = {r};
+        block_sum_all<1>(vv, lds);
+        if (t == 0) parts[blockIdx.x] = vv[0];
+    }
+}
+
+// The same update fused with the Laplacian pass of column j+1: per chunk, the
+// pairs of R_{j+1} are formed for the chunk's cells and its one-ring halo into
+// LDS (the same instructions for both, so a halo copy has the bits its owner
+// writes; the own pairs are pair t of k_iom2_update_lds), the own ones go to
+// rn with the chunk's norm partial, and L R_{j+1} of the chunk's cells goes
+// to lapn with the arithmetic of k_lap4_lds.  w is the product's output in a
+// buffer of its own (rn is written while other blocks still read w).
+__global__ void __launch_bounds__(kUpdLapBlock) k_upd_lap_lds(DevMesh M, int j, const double *w,
+                                                             const double *rj, const double *rjm1,
+                                                             double *rn, double *lapn, PhiCtl *ctl0,
+                                                             const double *nrm_in, int np_nrm,
+                                                             const double *dot_in, int np_dot,
+                                                             double *nrm_out, int per_chunk, Batch bt) {
+    constexpr int L = kUpdLapL, C = kChunk, HM = kHaloMax;
+    // a chunk and its halo hold at most 2 (C + HM) pairs: two per thread, and
+    // the own pairs (2 C) all come first
+    static_assert(2 * (C + HM) <= 2 * kUpdLapBlock && 2 * C <= kUpdLapBlock, "staged pairs per thread");
+    __shared__ double2 sx[(C + HM) * 2];
+    __shared__ double pro[16 * 4];
+    __shared__ double lds[16];
+    const int mk = blockIdx.y;
+    if (!member_active(bt.pred, mk)) return;
+    const double2 *w2 = reinterpret_cast<const double2 *>(member_ptr(w, bt.ws, mk));
+    const double2 *r2 = reinterpret_cast<const double2 *>(member_ptr(rj, bt.ws, mk));
+    const double2 *m2 = reinterpret_cast<const double2 *>(member_ptr(j > 0 ? rjm1 : rj, bt.ws, mk));
+    double2 *n2 = reinterpret_cast<double2 *>(member_ptr(rn, bt.ws, mk));
+    double *__restrict__ lout = member_ptr(lapn, bt.ws, mk);
+    double *parts = nrm_out + (size_t)mk * kPartStride;
+    const Halo &h = M.halo;
+    const int n = M.n;
+    const int t = threadIdx.x, q = t & (L - 1);
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
+    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
+    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    const double2 z2 = make_double2(0.0, 0.0);
+    // the thread's staged pairs of a chunk: pair k = t + u kUpdLapBlock, u < 2
+    double2 pw[2], pr[2], pm[2];
+    auto fetch = [&](int ck) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = t + u * kUpdLapBlock;
+            const int m = k >> 1;
+            const bool in = k < 2 * (cnt + hn);
+            const int cell = !in ? 0 : (m < cnt ? c0 + m : h.hids[h0 + (m - cnt)]);
+            const size_t e = 2 * (size_t)cell + (k & 1);
+            pw[u] = in ? w2[e] : z2;
+            pr[u] = in ? r2[e] : z2;
+            pm[u] = (in && j > 0) ? m2[e] : z2;
+        }
+    };
+    // (requesting the first chunk before the prologue, as the batched update
+    // does, measured slower here: more registers, no gain in latency)
+    PhiCtl *ctl = ctl_member(ctl0, mk);
+    // a new basis (j = 0) starts fresh; later columns stop after a breakdown
+    if (j > 0 && (ctl->brk != 0 || ctl->beta_zero)) return;
+    const IomCoef kc = iom2_coefficients(ctl, j, mk, nrm_in, np_nrm, dot_in, np_dot, pro);
+    if (kc.stop) return;
+    double r = 0.0;
+    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+        const int c0 = ck * C, cnt = min(C, n - c0);
+        const int hn = h.hoff[ck + 1] - h.hoff[ck];
+        fetch(ck);
+        __syncthreads();   // the previous chunk's readers are done
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int k = t + u * kUpdLapBlock;
+            if (k >= 2 * (cnt + hn)) continue;
+            const int m = k >> 1;
+            const bool own = m < cnt;
+            const double2 x = iom2_pair(kc, j, pw[u], pr[u], pm[u]);
+            sx[(own ? 2 * m : 2 * (C + m - cnt)) + (k & 1)] = x;
+            if (own) {   // only u = 0: one pair per chunk, as in k_iom2_update_lds
+                n2[2 * (size_t)c0 + k] = x;
+                r += fma(x.y, x.y, x.x * x.x);
+            }
+        }
+        if (per_chunk) {
+            double vv[1] = {r};
+            block_sum_all<1>(vv, lds);
+            if (t == 0) parts[ck] = vv[0];
+            r = 0.0;
+        }
+        __syncthreads();   // publishes sx
+        const int li = t / L;
+        if (li >= cnt) continue;
+        const int i = c0 + li;
+        const double2 a0 = sx[2 * li], a1 = sx[2 * li + 1];
+        const double pi[4] = {a0.x, a0.y, a1.x, a1.y};
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < kSlotIter<L>; ++s) {
+            const int e = 6 * i + slot_of<L>(q, s);
+            const int lj = h.lnbr[e];
+            const double c = M.cl[e];
+            const double2 b0 = sx[2 * lj], b1 = sx[2 * lj + 1];
+            const double pj[4] = {b0.x, b0.y, b1.x, b1.y};
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) acc[bb] = acc_add(acc[bb], c * (pj[bb] - pi[bb]));
+        }
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) acc[bb] = grp_sum<L>(acc[bb]);
+#pragma unroll
+        for (int s = 0; s < kCompIter<L>; ++s) lout[4 * i + comp_of<L>(q, s)] = acc[comp_of<L>(q, s)];
+    }
+    if (!per_chunk) {
+        double vv[1] = {r};
+        block_sum_all<1>(vv, lds);
+        if (t == 0) parts[blockIdx.x] = vv[0];
     }
 }
 
@@ -796,6 +987,49 @@ void launch_lap4(const DevMesh &M, const double *psi, double *out, const Batch &
     hipLaunchKernelGGL(k_lap4<L>, dim3(cells_grid(M.n, lb, L), b.nm), dim3(lb), 0, s, M, psi, out, b)
     XRB_LANES_DISPATCH_N(launch_lanes(M, b.nm), XRB_CALL)
 #undef XRB_CALL
+}
+
+bool iom2_chunked(const DevMesh &M, int nm) {
+    return M.halo.nchunks > 0 && launch_lanes(M, nm) == kUpdLapL && !jv_fuses_lap(M, nm);
+}
+
+bool upd_lap_fused(const DevMesh &M, int nm) { return nm == 1 && iom2_chunked(M, nm); }
+
+namespace {
+bool norm_per_chunk(const DevMesh &M) { return M.halo.nchunks <= kNrmRegion; }
+// the grid both chunked forms take when their partials are per block: every
+// chunk swept by kRedBlocks blocks (a multiple of the XCD count)
+constexpr int kChunkedGrid = kRedBlocks;
+}  // namespace
+
+int chunked_norm_parts(const DevMesh &M) { return norm_per_chunk(M) ? M.halo.nchunks : kChunkedGrid; }
+
+void launch_upd_lap(const DevMesh &M, int j, const double *w, const double *rj, const double *rjm1,
+                    double *rn, double *lapn, PhiCtl *ctl, const double *nrm_in, int np_nrm,
+                    const double *dot_in, int np_dot, double *nrm_out, const Batch &b, hipStream_t s) {
+    // per-chunk partials: one chunk per block (whole XCDs); else the shared grid
+    const int pc = norm_per_chunk(M);
+    const int grid = pc ? lds_grid_cap(M) : kChunkedGrid;
+    hipLaunchKernelGGL(k_upd_lap_lds, dim3(grid, b.nm), dim3(kUpdLapBlock), 0, s, M, j, w, rj, rjm1, rn,
+                       lapn, ctl, nrm_in, np_nrm, dot_in, np_dot, nrm_out, pc, b);
+}
+
+void launch_iom2_update_lds(const DevMesh &M, int j, double *w, const double *rj, const double *rjm1,
+                            PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
+                            int np_dot, double *nrm_out, const Batch &b, hipStream_t s) {
+    // per-chunk partials: the streaming update's block count (about 4096
+    // values per block, so that each block's prologue serves a few chunks) in
+    // whole XCDs, at most one block per chunk; else the shared grid
+    const int pc = norm_per_chunk(M);
+    int grid = kChunkedGrid;
+    if (pc) {
+        const int cap = lds_grid_cap(M);
+        grid = upd_parts(M.n) / kXcd * kXcd;
+        grid = grid < kXcd ? kXcd : grid;
+        grid = grid < cap ? grid : cap;
+    }
+    hipLaunchKernelGGL(k_iom2_update_lds, dim3(grid, b.nm), dim3(kUpdLapBlock), 0, s, M, j, w, rj, rjm1,
+                       ctl, nrm_in, np_nrm, dot_in, np_dot, nrm_out, pc, b);
 }
 
 void launch_linearize(const DevMesh &M, const double *u, double *eta, double *rec, const Batch &b,

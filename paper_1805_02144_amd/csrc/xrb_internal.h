@@ -125,7 +125,11 @@ enum PlanField {
     kPlanW = 8
 };
 constexpr int kRedBlocks = 512;                    // cap on blocks (partials) of a reduction
-constexpr int kPartStride = 2 * kRedBlocks;        // per-member doubles: dot or norm partials
+// IOM2 column norms: two partial buffers per member (columns alternate), each
+// room for one partial per block of an update or per chunk (chunked updates
+// on grids of at most kNrmRegion chunks)
+constexpr int kNrmRegion = kRedBlocks;
+constexpr int kPartStride = 2 * kNrmRegion;        // per-member doubles: dot or norm partials
 constexpr int kVPartStride = (kPmax + 1) * kRedBlocks;   // per-member doubles: input norms
 
 // blocks of a reducing kernel over `items` work items, `block` per block
@@ -238,6 +242,27 @@ struct JvArgs {
 // forms give the same bits.
 bool jv_fuses_lap(const DevMesh &M, int nm);
 int launch_jv(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipStream_t s);
+// IOM2 columns of a launch over nm members on a grid with chunk tables (two
+// lanes, the product not forming L x itself) take the chunked update, in one
+// of two forms with the same bits.  Single states take launch_upd_lap, the
+// update fused with the next column's Laplacian: the product writes w to a
+// buffer of its own, and the kernel forms R_{j+1} into rn and L R_{j+1} into
+// lapn.  Batches take launch_iom2_update_lds (R_{j+1} over w in place; the
+// next column's Laplacian is its own pass), which overlaps better across
+// members.  The column norm's partials (chunked_norm_parts(M) of them, the
+// count every consumer of an IOM2 column's norm is told) are one per chunk
+// on grids of at most kNrmRegion chunks, so that the two forms may take
+// different grids, and otherwise one per block of kRedBlocks blocks that
+// both forms take, sweeping the same chunks in the same order.
+bool iom2_chunked(const DevMesh &M, int nm);
+bool upd_lap_fused(const DevMesh &M, int nm);
+int chunked_norm_parts(const DevMesh &M);
+void launch_upd_lap(const DevMesh &M, int j, const double *w, const double *rj, const double *rjm1,
+                    double *rn, double *lapn, PhiCtl *ctl, const double *nrm_in, int np_nrm,
+                    const double *dot_in, int np_dot, double *nrm_out, const Batch &b, hipStream_t s);
+void launch_iom2_update_lds(const DevMesh &M, int j, double *w, const double *rj, const double *rjm1,
+                            PhiCtl *ctl, const double *nrm_in, int np_nrm, const double *dot_in,
+                            int np_dot, double *nrm_out, const Batch &b, hipStream_t s);
 
 // out = sum_k coef[k] * vec[k] (coefficients inside PhiCtl, offset per member);
 // nrm_out (nullable) receives partials of ||out||^2

@@ -164,7 +164,11 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_iom2_update_lds(DevMesh M, int
                                                                  int np_nrm, const double *dot_in,
                                                                  int np_dot, double *nrm_out,
                                                                  int per_chunk, Batch bt) {
-    constexpr int C = kChunk;
+    constexpr int C = kChunk, NW = kUpdLapBlock / 64;
+    // per-chunk mode: the wave sums of the block's chunks (at most
+    // ceil(kNrmRegion / kXcd) chunks per block), combined once at the end in
+    // block_sum_all's order
+    __shared__ double wsum[(kNrmRegion / kXcd) * NW];
     __shared__ double pro[16 * 4];
     __shared__ double lds[16];
     const int mk = blockIdx.y;
@@ -198,7 +202,8 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_iom2_update_lds(DevMesh M, int
     const IomCoef kc = iom2_coefficients(ctl, j, mk, nrm_in, np_nrm, dot_in, np_dot, pro);
     if (kc.stop) return;
     double r = 0.0;
-    for (int ck = ck0; ck < ck_end; ck += nbx) {
+    int nck = 0;   // chunks this block took
+    for (int ck = ck0; ck < ck_end; ck += nbx, ++nck) {
         const int c0 = ck * C, cnt = min(C, n - c0);
         if (ck != ck0) fetch(ck);
         if (t < 2 * cnt) {
@@ -207,13 +212,21 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_iom2_update_lds(DevMesh M, int
             r += fma(x.y, x.y, x.x * x.x);
         }
         if (per_chunk) {
-            double vv[1] = {r};
-            block_sum_all<1>(vv, lds);
-            if (t == 0) parts[ck] = vv[0];
+            const double sw = wave_sum(r);   // valid in lane 0
+            if ((t & 63) == 0) wsum[nck * NW + (t >> 6)] = sw;
             r = 0.0;
         }
     }
-    if (!per_chunk) {
+    if (per_chunk) {
+        // chunk c's total as block_sum_all forms it: the wave sums in wave order
+        __syncthreads();
+        if (t < nck) {
+            double tot = 0.0;
+#pragma unroll
+            for (int v = 0; v < NW; ++v) tot += wsum[t * NW + v];
+            parts[ck0 + t * nbx] = tot;
+        }
+    } else {
         double vv[1] = {r};
         block_sum_all<1>(vv, lds);
         if (t == 0) parts[blockIdx.x] = vv[0];

@@ -201,16 +201,18 @@ xrb_status xrb_ktv(xrb_ctx *ctx, const double *a, const double *b, double *out);
  *    single-state launches and for launches over many cells to the pair that
  *    minimises the sum of the two times relative to each one's best, among
  *    the pairs that keep batched members bitwise equal to single runs (the
- *    same count, or two and eight on grids up to 65536 cells); the current
- *    pair is kept unless that one is more than 3 % better.  Overrides
- *    xrb_params.lanes.
+ *    same count, or two and eight on grids up to 16384 cells, which carry no
+ *    chunk tables); the current pair is kept unless that one is more than
+ *    3 % better.  Overrides xrb_params.lanes.
  * 2. Block shapes, at the chosen lanes (none of them changes a result bit):
- *    on grids up to 65536 cells, where the reducing products sum per-cell
- *    terms in cell order, the threads per product block (the one-pass size,
- *    half of it, 256 and 512), separately for single states and batches, and
- *    the threads per Laplacian block (64, 128, 256); on larger grids with the
- *    LDS-staged kernels, the blocks of the Laplacian launch (512, 1024, 2048).
- *    The built-in rule is kept unless a candidate is more than 3 % faster.
+ *    where a gather product sums per-cell terms in cell order (grids up to
+ *    65536 cells, not two lanes with chunk tables), the threads per product
+ *    block (the one-pass size, half of it, 256 and 512), separately for
+ *    single states and batches, and the threads per Laplacian block (64,
+ *    128, 256); with the LDS-staged kernels (two lanes, grids above 16384
+ *    cells), the blocks of the Laplacian launch (512, 1024, 2048, at most
+ *    one per chunk).  The built-in rule is kept unless a candidate is more
+ *    than 3 % faster.
  * Every batched launch covers all members (the member-minor launch order was
  * measured and lost).  Synchronises the stream; allocates 8 nm_batch vectors
  * for its duration.  out (host): the timings in microseconds per launch and

@@ -1683,8 +1683,9 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
     }
     M.half_r = 0.5 * params->radius;
     M.lanes = params->lanes ? params->lanes : stencil_lanes(n);
-    // batches of small grids take two lanes per cell (same bits as eight)
-    M.lanes_batch = (!params->lanes && M.lanes == 8 && n <= 65536) ? 2 : M.lanes;
+    // batches of small grids take two lanes per cell (same bits as eight there:
+    // the default takes eight only up to 16384 cells, which carry no chunk tables)
+    M.lanes_batch = (!params->lanes && M.lanes == 8) ? 2 : M.lanes;
     M.nu = geo.nu;
     M.two_omega = 2.0 * params->omega;
     M.g = params->gravity;

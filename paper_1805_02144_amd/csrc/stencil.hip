@@ -29,7 +29,8 @@ bool jv_fuses_lap(const DevMesh &M, int nm) { return M.lanes == 8 && (long)nm * 
 // Lanes per cell of a forward stencil launch over nm members: few cells in
 // all take M.lanes (more memory-level parallelism per cell, for latency),
 // many take M.lanes_batch (fewer repeated per-cell instructions, for
-// throughput).  Two and eight lanes give the same bits.
+// throughput).  Two and eight lanes give the same bits on grids without
+// chunk tables (lanes_pair_bitwise).
 int launch_lanes(const DevMesh &M, int nm) {
     return (long)nm * M.n > 200000L ? M.lanes_batch : M.lanes;
 }

@@ -212,3 +212,26 @@ def test_level6_lds_product_matches_eight_lanes(X):
         ctx.step("exprb42", u, dts[k])
         assert np.array_equal(u.cpu().numpy(), got[k]), k
     ctx.close()
+
+
+def test_level7_batched_equals_single(X):
+    """Level 7 (641 chunks) takes the chunked IOM2 update with one norm
+    partial per block of a shared 512-block grid: the single state's update
+    fused with the next Laplacian and the batch's chunked update must still
+    give the same bits, step for step."""
+    import torch
+    level, nm = 7, 2
+    mesh = get_mesh(level)
+    U, dts = F.ensemble_states(level, 1805021447, nm)
+    ctx = X.Context(mesh, "cuda:0", lanes=2)
+    say("level 7 two-lane batch vs single")
+    Ub = torch.tensor(U, device="cuda:0")
+    ctx.reset_history()
+    ctx.step_batch("exprb42", Ub, dts)
+    got = Ub.cpu().numpy()
+    for k in range(nm):
+        ctx.reset_history()
+        u = torch.tensor(U[k], device="cuda:0")
+        ctx.step("exprb42", u, dts[k])
+        assert np.array_equal(u.cpu().numpy(), got[k]), k
+    ctx.close()

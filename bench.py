@@ -64,7 +64,7 @@ C2_EVENT_EVERY = 64
 
 # Kernel sources of the roofline kernel: a PMC traffic figure or a rocprof
 # average in profiles/ is used only while these hash to the value it was
-# taken on.
+# taken on (their code: comments and blank lines do not count).
 TRAFFIC_SOURCES = ["paper_1805_02144_amd/csrc/stencil.hip", "paper_1805_02144_amd/csrc/stencil_common.h",
                    "paper_1805_02144_amd/csrc/reduce.h", "paper_1805_02144_amd/csrc/xrb_internal.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_l8_jet_traffic.md")
@@ -73,10 +73,15 @@ TRAFFIC_FILE_L6 = os.path.join(ROOT, "profiles", "c2_l6_jv_iom2_traffic.md")
 
 def kernel_source_hash():
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+        h.update(code.encode("utf-8"))
     return h.hexdigest()[:16]
 
 

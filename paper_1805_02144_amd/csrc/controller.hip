@@ -1,18 +1,20 @@
 // Per-attempt kernel of phipm_simul_iom2 (Alg. 1, steps 2(ii)-6), one
 // 256-thread workgroup:
 //   * X = exp(tau Hhat) of the augmented IOM2 Hessenberg matrix
-//     Hhat = [[H_m, e_1 e_1^T], [0, N_{p+1}]] (remark after Alg. 1), by a
-//     degree-13 Pade approximant with scaling and squaring -- the method whose
-//     flop count (44/3 + 2 s) K^3 eq. cost prices;
+//     Hhat = [[H_m, e_1 e_1^T], [0, N_{p+1}]] (remark after Alg. 1), by the
+//     degree-16 Taylor polynomial in Paterson-Stockmeyer form with scaling
+//     and squaring: products only, every one on the FP64 matrix cores (a
+//     Pade approximant would need a pivoted solve, whose one barrier per
+//     column cost more here than the whole polynomial);
 //   * error estimate eps = beta h_{m+1,m} |X(m, m+p+1)| and
 //     omega = t_out eps / (tau Tol) (steps 3 and 6);
-//   * (tau, m) update with the cost comparison of eq. cost (steps 4-5);
+//   * (tau, m) update with the cost comparison of eq. cost (steps 4-5; the
+//     cost model prices the exponential as the paper does, by the degree-13
+//     Pade flop count (44/3 + 2 s) K^3);
 //   * on acceptance, the coefficients of y_{k+1} (eq. 3.17) for the
 //     combination kernel and t^l/l! for the next w_j recurrence (eq. 3.18).
 // Matrices live in LDS (K <= 49, padded to 52).  The matrix products run on
-// the FP64 matrix cores (16 x 16 tiles, one wave per tile); the Pade
-// denominator solve is a Gauss-Jordan elimination with one barrier per
-// column.
+// the FP64 matrix cores (16 x 16 tiles, one wave per tile).
 #include "column.h"
 #include "reduce.h"
 #include "xrb_internal.h"
@@ -105,183 +107,79 @@ __device__ inline void mat_mul(const double *A, const double *B, double *C, int 
                      [C](int e, const double(&v)[1]) { C[e] = v[0]; });
 }
 
-// Lane exchange inside a row of 16 lanes by a DPP control word.
-template <int CTRL>
-__device__ inline double dpp_row(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-    return __hiloint2double(hi, lo);
-}
+// lane l's v, the same in every lane
 __device__ inline double read_lane(double v, int l) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// Largest value over the 64 lanes of the wave, returned in every lane:
-// xor-1, xor-2, half-row and row mirrors give each row of 16 its maximum,
-// then the four row results are read as scalars.
-__device__ inline double wave_max_all(double a) {
-    a = fmax(a, dpp_row<0xB1>(a));    // quad_perm [1,0,3,2]
-    a = fmax(a, dpp_row<0x4E>(a));    // quad_perm [2,3,0,1]
-    a = fmax(a, dpp_row<0x141>(a));   // row_half_mirror
-    a = fmax(a, dpp_row<0x140>(a));   // row_mirror
-    return fmax(fmax(read_lane(a, 0), read_lane(a, 16)), fmax(read_lane(a, 32), read_lane(a, 48)));
-}
-
-// 1/d from the hardware reciprocal refined by one Newton step (the pivot
-// reciprocal sits on the elimination's critical path; a division there costs
-// several dependent operations more)
-__device__ inline double recip(double d) {
-    const double r = __builtin_amdgcn_rcp(d);
-    return fma(r, fma(-d, r, 1.0), r);
-}
-
-// X = M^{-1} R for K x K matrices M and R in LDS (row stride kLd, K <= KC),
-// by Gauss-Jordan elimination with partial pivoting: for each column the
-// pivot is the first not yet used row of largest |M(r, col)|, and that
-// column is eliminated from every other row of [M | R].  Rows are never
-// swapped; X(c, :) = R(p_c, :) / M(p_c, c) at the end, p_c the pivot row of
-// column c.  Thread t owns column t mod 128 of [M | R] on the rows of parity
-// t / 128, keeps them in registers and writes every update through to LDS
-// (rows K..KC-1 of M and R are padding and take zeros).  Every wave finds
-// the pivot itself (DPP maximum and a ballot over the column read from
-// LDS), so one barrier per column separates the updates.  X is written over
-// the whole kLd x kLd block (zero outside K x K).  Sets *status to ENAN on
-// a zero pivot.
-template <int KC>
-__device__ inline void gauss_jordan(double *Mt, double *R, double *X, int K, int *piv_of,
-                                    double *dinv_of, int *status) {
-    constexpr int NR = (KC + 1) / 2;   // rows per thread: h, h + 2, ... < KC <= kLd
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int q = tid & 127;
-    const int h = __builtin_amdgcn_readfirstlane(tid >> 7);   // the same in the whole wave
-    const bool live = q < 2 * K;
-    double *P = live ? (q < K ? Mt + q : R + (q - K)) : Mt;
-    const int lrow = lane < kLd ? lane : kLd - 1;
-    double x[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        const double v = P[(h + 2 * k) * kLd];
-        x[k] = (live && h + 2 * k < K) ? v : 0.0;
-    }
-    uint64_t used = 0;
-    for (int col = 0; col < K; ++col) {
-        // column col: lane r reads row r (pivot search); every thread reads
-        // the entries of its own rows (multipliers, the same in the wave)
-        const double vr = Mt[lrow * kLd + col];
-        double cm[NR];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) cm[k] = Mt[(h + 2 * k) * kLd + col];
-        const double vs = lane < K ? vr : 0.0;
-        double a = -1.0;
-        if (lane < K && !((used >> lane) & 1)) {
-            const double v = fabs(vs);
-            a = v >= 0.0 ? v : 0.0;   // a NaN entry ranks lowest
-        }
-        const double mx = wave_max_all(a);
-        const int piv = __ffsll((long long)__ballot(a == mx)) - 1;
-        used |= 1ull << piv;
-        const double dinv = recip(read_lane(vs, piv));
-        if (tid == 0) {
-            piv_of[col] = piv;
-            dinv_of[col] = dinv;
-            if (!(mx > 0.0)) *status = XRB_ENAN;
-        }
-        const bool upd_col = live && (q >= K || q > col);
-        const double pv = P[piv * kLd];
-#pragma unroll
-        for (int k = 0; k < NR; ++k) {
-            const int r = h + 2 * k;
-            const double l = (upd_col && r < K && r != piv) ? cm[k] * dinv : 0.0;
-            x[k] -= l * pv;
-        }
-        if (live) {
-#pragma unroll
-            for (int k = 0; k < NR; ++k) P[(h + 2 * k) * kLd] = x[k];
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < kMat; e += blockDim.x) {
-        const int c = e / kLd, j = e % kLd;
-        X[e] = (c < K && j < K) ? R[piv_of[c] * kLd + j] * dinv_of[c] : 0.0;
-    }
-    __syncthreads();
-}
-
-// Pade [13/13] coefficients of exp from the closed form, b_0 = 1 (evaluated
-// at compile time with the same IEEE operations as at run time)
-struct Pade13 {
-    double b[14];
+// Taylor coefficients 1/k!, k = 0..16 (evaluated at compile time with the
+// same IEEE operations as at run time)
+struct Taylor16 {
+    double c[17];
 };
-constexpr Pade13 pade13() {
-    Pade13 p{};
-    p.b[0] = 1.0;
-    for (int j = 0; j < 13; ++j) p.b[j + 1] = p.b[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
-    return p;
+constexpr Taylor16 taylor16() {
+    Taylor16 t{};
+    t.c[0] = 1.0;
+    for (int k = 1; k <= 16; ++k) t.c[k] = t.c[k - 1] / k;
+    return t;
 }
+// The scaled matrix's 1-norm bound: for ||B||_1 <= 0.75 the remainder of the
+// degree-16 series, sum_{k>16} B^k/k!, is below 0.75^17/17! e^0.75 / (1 - 0.75/18)
+// < 5e-17 in norm against ||e^B|| >= e^-0.75, under half a unit roundoff
+// relative to the result.
+constexpr double kTaylorTheta = 0.75;
 
 // LDS matrices of the exponential (each kLd x kLd)
 struct ExpmLds {
-    double *Bm, *B2, *B4, *B6, *Ue, *Uo, *Vm;
-    int *piv_of;
-    double *dinv_of;
+    double *B1, *B2, *B3, *B4, *T, *U;
 };
 
-// exp(Bm)^(2^n_sq) for the scaled matrix Bm of order K (zero padded); the
-// result is one of the LDS matrices, returned.
+// exp(B1)^(2^n_sq) for the scaled matrix B1 of order K (zero padded), the
+// polynomial as sum_i B^4i A_i with A_i = c_4i I + c_4i+1 B + c_4i+2 B^2 +
+// c_4i+3 B^3 (i < 4) plus c_16 B^16, by Horner in B^4: B^2, then B^3 and B^4
+// in one pass (the innermost block A_3 + c_16 B^4 formed in its epilogue),
+// three Horner products with A_i added in their epilogues, then the
+// squarings.  The result is one of the LDS matrices, returned.
 template <int KC>
-__device__ double *pade13_expm(const ExpmLds &L, int K, int K4, int n_sq, int *status) {
-    constexpr Pade13 kPade = pade13();
-    const double *b = kPade.b;
-    double *Bm = L.Bm, *B2 = L.B2, *B4 = L.B4, *B6 = L.B6, *Ue = L.Ue, *Uo = L.Uo, *Vm = L.Vm;
-    // B^2, B^4, B^6; the pass forming B^6 also forms the two inner sums
-    //   Ue = b12 B^6 + b10 B^4 + b8 B^2,  Uo = b13 B^6 + b11 B^4 + b9 B^2
-    mat_mul<KC>(Bm, Bm, B2, K4);
-    mat_mul<KC>(B2, B2, B4, K4);
+__device__ double *taylor16_expm(const ExpmLds &L, int K, int K4, int n_sq) {
+    constexpr Taylor16 kTay = taylor16();
+    const double *c = kTay.c;
+    double *B1 = L.B1, *B2 = L.B2, *B3 = L.B3, *B4 = L.B4;
+    mat_mul<KC>(B1, B1, B2, K4);
     {
-        const double *const bb[1] = {B2};
-        mfma_pass<KC, 1>(B4, bb, K4, [](int, int, int) { return 0.0; },
-                         [&](int e, const double(&v)[1]) {
-                             B6[e] = v[0];
-                             Ue[e] = b[12] * v[0] + b[10] * B4[e] + b[8] * B2[e];
-                             Uo[e] = b[13] * v[0] + b[11] * B4[e] + b[9] * B2[e];
-                         });
-    }
-    // one pass, both polynomials (the same B^6 operand):
-    //   V = B^6 Ue + b6 B^6 + b4 B^4 + b2 B^2 + b0 I      -> Vm
-    //   W = B^6 Uo + b7 B^6 + b5 B^4 + b3 B^2 + b1 I      -> B2 (in place)
-    {
-        const double *const bb[2] = {Ue, Uo};
-        mfma_pass<KC, 2>(B6, bb, K4,
-                         [&](int nb, int r, int c) {
-                             const int e = r * kLd + c;
-                             const double id = (r == c && r < K) ? 1.0 : 0.0;
-                             return nb == 0 ? b[6] * B6[e] + b[4] * B4[e] + b[2] * B2[e] + b[0] * id
-                                            : b[7] * B6[e] + b[5] * B4[e] + b[3] * B2[e] + b[1] * id;
-                         },
+        const double *const bb[2] = {B1, B2};
+        double *T = L.T;
+        mfma_pass<KC, 2>(B2, bb, K4, [](int, int, int) { return 0.0; },
                          [&](int e, const double(&v)[2]) {
-                             Vm[e] = v[0];
-                             B2[e] = v[1];
+                             B3[e] = v[0];
+                             B4[e] = v[1];
+                             const int r = e / kLd, col = e - r * kLd;
+                             const double id = (r == col && r < K) ? 1.0 : 0.0;
+                             T[e] = c[12] * id + c[13] * B1[e] + c[14] * B2[e] + c[15] * v[0] + c[16] * v[1];
                          });
     }
-    // U = B W; the pass writes M = V - U (into B4) and V + U (over V)
-    {
-        const double *const bb[1] = {B2};
-        mfma_pass<KC, 1>(Bm, bb, K4, [](int, int, int) { return 0.0; },
-                         [&](int e, const double(&u)[1]) {
-                             const double v = Vm[e];
-                             B4[e] = v - u[0];
-                             Vm[e] = v + u[0];
-                         });
+    double *src = L.T, *dst = L.U;
+    for (int i = 2; i >= 0; --i) {
+        const double *const bb[1] = {src};
+        mfma_pass<KC, 1>(B4, bb, K4,
+                         [&](int, int r, int col) {
+                             const int e = r * kLd + col;
+                             const double id = (r == col && r < K) ? 1.0 : 0.0;
+                             return c[4 * i] * id + c[4 * i + 1] * B1[e] + c[4 * i + 2] * B2[e] +
+                                    c[4 * i + 3] * B3[e];
+                         },
+                         [&](int e, const double(&v)[1]) { dst[e] = v[0]; });
+        double *tmp = src;
+        src = dst;
+        dst = tmp;
     }
-    // X = (V - U)^{-1} (V + U) into Bm, then the squarings
-    gauss_jordan<KC>(B4, Vm, Bm, K, L.piv_of, L.dinv_of, status);
-    double *X = Bm, *T = B2;
+    double *X = src, *Y = dst;
     for (int q = 0; q < n_sq; ++q) {
-        mat_mul<KC>(X, X, T, K4);
+        mat_mul<KC>(X, X, Y, K4);
         double *tmp = X;
-        X = T;
-        T = tmp;
+        X = Y;
+        Y = tmp;
     }
     return X;
 }
@@ -322,9 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
     PhiCtl *c = ctl0 + mk;
     const CtlArgs a = dargs ? dargs[mk] : a0;
     const double *nrm_in = nrm_parts + (size_t)mk * kPartStride + (size_t)a.nrm_buf * kNrmRegion;
-    __shared__ double Bm[kMat], B2[kMat], B4[kMat], B6[kMat], Ue[kMat], Uo[kMat], Vm[kMat];
-    __shared__ int piv_of[kLd];
-    __shared__ double dinv_of[kLd];
+    __shared__ double Bm[kMat], B2[kMat], B3[kMat], B4[kMat], Tm[kMat], Um[kMat];
     __shared__ double sh_tau_u, sh_norm, sh_hsub;
     __shared__ int sh_lands, sh_meff, sh_status;
     __shared__ double red[32];
@@ -405,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
         if (!(nrm < 1e300)) {
             if (tid == 0) sh_status = XRB_ENAN;   // non-finite Hessenberg entries
         } else {
-            while (nrm * sc > 5.371920351148152) {
+            while (nrm * sc > kTaylorTheta) {
                 ++n_sq;
                 sc *= 0.5;
             }
@@ -421,10 +317,10 @@ __global__ void __launch_bounds__(kBlock) k_controller(PhiCtl *ctl0, CtlArgs a0,
             Bm[(tid - 1) * kLd + tid] = tau_u * sc;   // superdiagonal of N_{p+1}
         }
         __syncthreads();
-        const ExpmLds L{Bm, B2, B4, B6, Ue, Uo, Vm, piv_of, dinv_of};
-        if (K4 <= 16) X = pade13_expm<16>(L, K, K4, n_sq, &sh_status);
-        else if (K4 <= 32) X = pade13_expm<32>(L, K, K4, n_sq, &sh_status);
-        else X = pade13_expm<kLd>(L, K, K4, n_sq, &sh_status);
+        const ExpmLds L{Bm, B2, B3, B4, Tm, Um};
+        if (K4 <= 16) X = taylor16_expm<16>(L, K, K4, n_sq);
+        else if (K4 <= 32) X = taylor16_expm<32>(L, K, K4, n_sq);
+        else X = taylor16_expm<kLd>(L, K, K4, n_sq);
     }
 
     // combination coefficients of the basis, beta sigma_k X(k, m+p-1), a row per thread

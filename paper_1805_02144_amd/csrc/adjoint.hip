@@ -90,9 +90,9 @@ __global__ void __launch_bounds__(kLapTLdsBlock) k_lapT_lds(DevMesh M, const dou
     const int t = threadIdx.x, q = t & (L - 1);
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
-    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
+    for (int ck = span.first + kk; ck < ck_end; ck += nbx) {
         const int c0 = ck * C, cnt = min(C, n - c0);
         const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
         __syncthreads();   // the previous chunk's readers are done
@@ -300,10 +300,10 @@ __global__ void __launch_bounds__(kJtvLdsBlock, 4) k_jtv_lds(DevMesh M, JvArgs a
     const int q = t & (L - 1);
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
     double r0 = 0.0, r1 = 0.0;
-    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+    for (int ck = span.first + kk; ck < ck_end; ck += nbx) {
         const int c0 = ck * C;
         const int cnt = min(C, n - c0);
         const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
@@ -534,9 +534,9 @@ __global__ void __launch_bounds__(kKpLdsBlock, 4) k_kpairs_lds(DevMesh M, KPairA
     const Halo &h = M.halo;
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
-    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
+    for (int ck = span.first + kk; ck < ck_end; ck += nbx) {
         const int c0 = ck * C, cnt = min(C, n - c0);
         const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
         const int li = t / L;

@@ -112,9 +112,9 @@ __global__ void __launch_bounds__(kLapLdsBlock) k_lap4_lds(DevMesh M, const doub
     const int t = threadIdx.x, q = t & (L - 1);
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
-    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
+    for (int ck = span.first + kk; ck < ck_end; ck += nbx) {
         const int c0 = ck * C, cnt = min(C, n - c0);
         const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
         __syncthreads();   // the previous chunk's readers are done
@@ -183,8 +183,8 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_iom2_update_lds(DevMesh M, int
     const int t = threadIdx.x;
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
     const double2 z2 = make_double2(0.0, 0.0);
     double2 pw = z2, pr = z2, pm = z2;
     auto fetch = [&](int ck) {
@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_iom2_update_lds(DevMesh M, int
         pr = in ? r2[e] : z2;
         pm = (in && j > 0) ? m2[e] : z2;
     };
-    const int ck0 = xcd * cpx + kk;
+    const int ck0 = span.first + kk;
     if (ck0 < ck_end) fetch(ck0);
     PhiCtl *ctl = ctl_member(ctl0, mk);
     // a new basis (j = 0) starts fresh; later columns stop after a breakdown
@@ -267,8 +267,8 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_upd_lap_lds(DevMesh M, int j, 
     const int t = threadIdx.x, q = t & (L - 1);
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
     const double2 z2 = make_double2(0.0, 0.0);
     // the thread's staged pairs of a chunk: pair k = t + u kUpdLapBlock, u < 2
     double2 pw[2], pr[2], pm[2];
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kUpdLapBlock) k_upd_lap_lds(DevMesh M, int j, 
     const IomCoef kc = iom2_coefficients(ctl, j, mk, nrm_in, np_nrm, dot_in, np_dot, pro);
     if (kc.stop) return;
     double r = 0.0;
-    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+    for (int ck = span.first + kk; ck < ck_end; ck += nbx) {
         const int c0 = ck * C, cnt = min(C, n - c0);
         const int hn = h.hoff[ck + 1] - h.hoff[ck];
         fetch(ck);
@@ -692,7 +692,8 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
 
 // The product of large grids with its neighbours staged in LDS.  Block b
 // takes chunks of kChunk consecutive cells (XCD-major: the blocks on XCD x
-// sweep the x-th eighth of the chunks together, window by window).  For each
+// sweep that die's contiguous share of the chunks, xcd_chunks, together,
+// window by window).  For each
 // chunk, one thread per cell of the chunk and of its one-ring halo loads the
 // cell's x, L x and linearisation record (u, centre, eta) and stores in LDS
 // what its edges need: s = u . x_vel + g x_h and the flux F = h x_vel +
@@ -742,10 +743,10 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
     const int q = t & (L - 1);
     const int G = (int)gridDim.x, b = (int)blockIdx.x;
     const int nbx = G / kXcd, xcd = b % kXcd, kk = b / kXcd;
-    const int cpx = (h.nchunks + kXcd - 1) / kXcd;   // chunks per XCD
-    const int ck_end = min((xcd + 1) * cpx, h.nchunks);
+    const ChunkSpan span = xcd_chunks(h.nchunks, xcd);
+    const int ck_end = span.end;
     double r0 = 0.0, r1 = 0.0;
-    for (int ck = xcd * cpx + kk; ck < ck_end; ck += nbx) {
+    for (int ck = span.first + kk; ck < ck_end; ck += nbx) {
         const int c0 = ck * C;
         const int cnt = min(C, n - c0);
         const int h0 = h.hoff[ck], hn = h.hoff[ck + 1] - h0;
@@ -918,7 +919,7 @@ __global__ void __launch_bounds__(256) k_diag_sum(const double *__restrict__ par
 }
 
 // Blocks that cover every chunk once: the chunk count rounded up to whole
-// XCDs (the LDS kernels sweep chunk x * ceil(nchunks / 8) + k on XCD x).
+// XCDs (no die's share in xcd_chunks exceeds ceil(nchunks / 8)).
 int lds_grid_cap(const DevMesh &M) { return (M.halo.nchunks + kXcd - 1) / kXcd * kXcd; }
 
 // Whether a product launch takes k_jv_lds: a grid with chunk tables, two

@@ -10,6 +10,22 @@ namespace stc {
 
 constexpr int kXcd = 8;   // accelerator dies, each with its own L2
 
+// The chunks [first, end) of the LDS-staged kernels that the blocks on die x
+// sweep (blocks b with b % kXcd == x, the hardware's round-robin): the chunk
+// count split over the dies as evenly as possible, the larger shares on the
+// last dies.  A die with one chunk more than its blocks' even share then
+// gives the extra step to the block that also takes the grid's last chunk,
+// which may hold a few cells only (2561 chunks over 512 blocks: 5 steps
+// everywhere but one block's sixth, two-cell chunk).
+struct ChunkSpan {
+    int first, end;
+};
+__device__ inline ChunkSpan xcd_chunks(int nchunks, int xcd) {
+    const int base = nchunks / kXcd, from = kXcd - nchunks % kXcd;
+    const int first = xcd * base + (xcd > from ? xcd - from : 0);
+    return {first, first + base + (xcd >= from ? 1 : 0)};
+}
+
 // one block per block/L cells, rounded up to a whole number of blocks per XCD
 inline int cells_grid(int n, int block, int L) {
     const int cpb = block / L;

@@ -1680,6 +1680,7 @@ xrb_status xrb_create(const xrb_mesh *mesh, const xrb_params *params, void *stre
         M.halo.hids = hids;
         M.halo.lnbr = lnbr;
         M.halo.nchunks = (int)nh - 1;
+        M.halo.short_terms = geo.short_terms;
     }
     M.half_r = 0.5 * params->radius;
     M.lanes = params->lanes ? params->lanes : stencil_lanes(n);

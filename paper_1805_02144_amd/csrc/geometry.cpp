@@ -45,8 +45,9 @@ namespace xrb {
 namespace {
 
 // the range of the LDS-staged product's weight series (kShortY2Max in
-// stencil_common.h)
+// stencil_common.h), and of its four-term form (kShort4Y2Max)
 constexpr double kShortY2MaxHost = 4e-4;
+constexpr double kShort4Y2MaxHost = 3e-5;
 
 struct V3 {
     double x, y, z;
@@ -195,6 +196,7 @@ void build_halo(HostGeometry &geo) {
     std::vector<int32_t> hoff(nch + 1, 0), hids;
     std::vector<uint16_t> lnbr(6 * (size_t)n, 0);
     // the product's weight series hold for half-chords y with y^2 <= kShortY2MaxHost
+    double y2max = 0.0;
     for (int i = 0; i < n; ++i)
         for (int s = 0; s < 6; ++s) {
             const int j = geo.nbr[6 * (size_t)i + s];
@@ -204,6 +206,7 @@ void build_halo(HostGeometry &geo) {
                 y2 += 0.25 * dx * dx;
             }
             if (y2 > kShortY2MaxHost) return;   // tables stay empty: the product keeps its gathers
+            y2max = std::max(y2max, y2);
         }
     std::vector<int32_t> ring;
     for (int k = 0; k < nch; ++k) {
@@ -231,6 +234,7 @@ void build_halo(HostGeometry &geo) {
     geo.hoff.swap(hoff);
     geo.hids.swap(hids);
     geo.lnbr.swap(lnbr);
+    geo.short_terms = y2max <= kShort4Y2MaxHost ? 4 : 5;
 }
 
 }  // namespace xrb

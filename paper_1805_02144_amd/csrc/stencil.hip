@@ -696,12 +696,15 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
 // window by window).  For each
 // chunk, one thread per cell of the chunk and of its one-ring halo loads the
 // cell's x, L x and linearisation record (u, centre, eta) and stores in LDS
-// what its edges need: s = u . x_vel + g x_h and the flux F = h x_vel +
-// x_h u (both formed once per cell instead of once per edge), x_vel, the
-// centre and L x -- 14 doubles; the chunk's own cells also keep u, eta and
-// x_h.  Every edge term then reads its neighbour from LDS through the
-// chunk's 16-bit local ids, with the weights formed from c and the chord by
-// edge_weights_short.  Two lanes serve a cell (kJvLdsL), with the lane
+// what its edges need: s = u . x_vel + g x_h, the flux F = h x_vel + x_h u
+// and P = x_vel x c (c the unit centre), all formed once per cell instead of
+// once per edge, the centre and L x -- 14 doubles; the chunk's own cells
+// also keep u, eta and x.  Every edge term then reads its neighbour from LDS
+// through the chunk's 16-bit local ids, with alpha and beta formed from c
+// and the chord by the NT-term series (edge_ab_short).  The circulation term
+// beta (c_i x c_j) . (x_i + x_j) is taken as beta (P_i . c_j - P_j . c_i)
+// (the two scalar triple products), which needs no cross product per edge.
+// Two lanes serve a cell (kJvLdsL), with the lane
 // placement and sums of k_jv<EPI, 2>; the rounding differs from the gather
 // kernels (weights from the series, no stored alpha), so a grid with chunk
 // tables keeps this kernel for all its two-lane products.  Reductions:
@@ -710,14 +713,14 @@ __global__ void __launch_bounds__(kJvMaxBlock<EPI>) k_jv(DevMesh M, JvArgs a, Ba
 constexpr int kJvLdsL = 2;
 constexpr int kJvLdsBlock = kChunk * kJvLdsL;
 
-template <int EPI>
+template <int EPI, int NT>
 __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, Batch bt) {
     constexpr int L = kJvLdsL, C = kChunk, S = kChunk + kHaloMax;
-    // staged cells (chunk, then halo): (s, F_x) (F_y, F_z) (x_x, x_y) (x_z, centre_x)
+    // staged cells (chunk, then halo): (s, F_x) (F_y, F_z) (P_x, P_y) (P_z, centre_x)
     // (centre_y, centre_z) (Lx_0, Lx_1) (Lx_2, Lx_3); the chunk's own cells:
-    // (u_x, u_y) (u_z, h) (eta, x_h)
+    // (u_x, u_y) (u_z, x_z) (eta, x_h) (x_x, x_y)
     __shared__ double2 nA[S], nB[S], nC[S], nD[S], nE[S], nL0[S], nL1[S];
-    __shared__ double2 oU0[C], oU1[C], oE[C];
+    __shared__ double2 oU0[C], oU1[C], oE[C], oX[C];
     __shared__ double lds[64];
     const int mk = blockIdx.y;
     if (!member_active(bt.pred, mk)) return;
@@ -762,15 +765,17 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
             nL1[sl] = l2[2 * (size_t)j + 1];
             const double vx = v0.x, vy = v0.y, vz = v1.x, vh = v1.y;
             const double wx = w0.x, wy = w0.y, wz = w1.x, wh = w1.y;
+            const double cx = w2.x, cy = w2.y, cz = w3.x;
             nA[sl] = make_double2(wx * vx + wy * vy + wz * vz + g * vh, wh * vx + vh * wx);
             nB[sl] = make_double2(wh * vy + vh * wy, wh * vz + vh * wz);
-            nC[sl] = v0;
-            nD[sl] = make_double2(vz, w2.x);
-            nE[sl] = make_double2(w2.y, w3.x);
+            nC[sl] = make_double2(vy * cz - vz * cy, vz * cx - vx * cz);
+            nD[sl] = make_double2(vx * cy - vy * cx, cx);
+            nE[sl] = make_double2(cy, cz);
             if (own) {
                 oU0[m] = w0;
-                oU1[m] = w1;
+                oU1[m] = make_double2(wz, vz);
                 oE[m] = make_double2(w3.y, vh);
+                oX[m] = v0;
             }
         }
         __syncthreads();
@@ -784,7 +789,7 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
         ci.y = E0.x;
         ci.z = E0.y;
         ci.ra = 0.0;
-        const double xx = C0.x, xy = C0.y, xz = D0.x;
+        const double pix = C0.x, piy = C0.y, piz = D0.x;
         const double lxo[4] = {s0.x, s0.y, s1.x, s1.y};
         const double si = A0.x, fx = A0.y, fy = B0.x, fz = B0.y;
         double gx = 0.0, gy0 = 0.0, gz0 = 0.0, dv = 0.0, zt = 0.0;
@@ -801,15 +806,19 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
             cj.y = Ej.x;
             cj.z = Ej.y;
             cj.ra = 0.0;
-            const EdgeW w = edge_weights_short(ci, cj, c, M.half_r);
+            double al, be, dx, dy, dz;
+            edge_ab_short<NT>(ci, cj, c, M.half_r, al, be, dx, dy, dz);
             const double ds = Aj.x - si;
+            const double wax = al * dx, way = al * dy, waz = al * dz;
             // fused multiply-adds throughout: this kernel's bits need only
             // match themselves (batched and single launches)
-            gx = fma(w.ax, ds, gx);
-            gy0 = fma(w.ay, ds, gy0);
-            gz0 = fma(w.az, ds, gz0);
-            dv = fma(w.az, fz + Bj.y, fma(w.ay, fy + Bj.x, fma(w.ax, fx + Aj.y, dv)));
-            zt = fma(w.bz, xz + Dj.x, fma(w.by, xy + Cj.y, fma(w.bx, xx + Cj.x, zt)));
+            gx = fma(wax, ds, gx);
+            gy0 = fma(way, ds, gy0);
+            gz0 = fma(waz, ds, gz0);
+            dv = fma(waz, fz + Bj.y, fma(way, fy + Bj.x, fma(wax, fx + Aj.y, dv)));
+            const double tz = fma(pix, cj.x, fma(piy, cj.y, piz * cj.z)) -
+                              fma(Cj.x, ci.x, fma(Cj.y, ci.y, Dj.x * ci.z));
+            zt = fma(be, tz, zt);
             const double lxj[4] = {e0.x, e0.y, e1.x, e1.y};
 #pragma unroll
             for (int bb = 0; bb < 4; ++bb) d[bb] = fma(c, lxj[bb] - lxo[bb], d[bb]);
@@ -821,8 +830,9 @@ __global__ void __launch_bounds__(kJvLdsBlock, 4) k_jv_lds(DevMesh M, JvArgs a, 
         zt = grp_sum<L>(zt);
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) d[bb] = grp_sum<L>(d[bb]);
-        const double2 U0 = oU0[li], U1 = oU1[li], EE = oE[li];
+        const double2 U0 = oU0[li], U1 = oU1[li], EE = oE[li], XX = oX[li];
         const double ux = U0.x, uy = U0.y, uz = U1.x;
+        const double xx = XX.x, xy = XX.y, xz = U1.y;
         const double eta = EE.x, xh = EE.y;
         const double nx = ci.x, ny = ci.y, nz = ci.z;
         const double gr = nx * gx + ny * gy0 + nz * gz0;
@@ -942,12 +952,17 @@ int jv_launch_t(const DevMesh &M, const JvArgs &a, int epi, const Batch &b, hipS
         const int cap = lds_grid_cap(M);
         const int np = epi == kEpiNorm ? red_parts(M.n) : (cap < red_parts(M.n) ? cap : red_parts(M.n));
         const dim3 grid(np, b.nm), block(kJvLdsBlock);
-        if (epi == kEpiIom2)
-            hipLaunchKernelGGL(k_jv_lds<kEpiIom2>, grid, block, 0, s, M, a, b);
-        else if (epi == kEpiNorm)
-            hipLaunchKernelGGL(k_jv_lds<kEpiNorm>, grid, block, 0, s, M, a, b);
-        else
-            hipLaunchKernelGGL(k_jv_lds<kEpiNone>, grid, block, 0, s, M, a, b);
+        const bool t4 = M.halo.short_terms == 4;
+        if (epi == kEpiIom2) {
+            if (t4) hipLaunchKernelGGL((k_jv_lds<kEpiIom2, 4>), grid, block, 0, s, M, a, b);
+            else hipLaunchKernelGGL((k_jv_lds<kEpiIom2, kShortTerms>), grid, block, 0, s, M, a, b);
+        } else if (epi == kEpiNorm) {
+            if (t4) hipLaunchKernelGGL((k_jv_lds<kEpiNorm, 4>), grid, block, 0, s, M, a, b);
+            else hipLaunchKernelGGL((k_jv_lds<kEpiNorm, kShortTerms>), grid, block, 0, s, M, a, b);
+        } else {
+            if (t4) hipLaunchKernelGGL((k_jv_lds<kEpiNone, 4>), grid, block, 0, s, M, a, b);
+            else hipLaunchKernelGGL((k_jv_lds<kEpiNone, kShortTerms>), grid, block, 0, s, M, a, b);
+        }
         return epi == kEpiNone ? 0 : np;
     }
     if (epi == kEpiNone) {

@@ -160,9 +160,12 @@ __device__ inline void load4(const double *__restrict__ v, int i, double (&o)[4]
 // sums, so these weights agree with the stored alpha and the square-root
 // form of beta to rounding.  The LDS-staged product uses them (no alpha
 // stream, no square root); the host enables that product only on grids
-// inside the series' range.
+// inside the series' range.  Four terms suffice for y^2 <= kShort4Y2Max
+// (the first omitted term, b_4 y^8, is below 3e-19; levels 7 and 8 have
+// y^2 up to 2.7e-5 and 7e-6): the host picks the term count per grid.
 constexpr int kShortTerms = 5;
 constexpr double kShortY2Max = 4e-4;
+constexpr double kShort4Y2Max = 3e-5;
 struct ShortSeries {
     double a[kShortTerms], b[kShortTerms];
 };
@@ -175,6 +178,28 @@ constexpr ShortSeries short_series() {
         s.b[k + 1] = s.b[k] * (double)(2 * k + 1) / (double)(2 * k + 2);
     }
     return s;
+}
+
+// The edge's flux weight alpha (the a of EdgeW is alpha (x_j - x_i)), the
+// circulation weight beta and x_j - x_i from c and the two centres by the
+// first NT terms of the series above.
+template <int NT>
+__device__ inline void edge_ab_short(const Cell &ci, const Cell &cj, double c, double half_r,
+                                     double &al, double &be, double &dx, double &dy, double &dz) {
+    static_assert(NT >= 1 && NT <= kShortTerms, "series terms");
+    constexpr ShortSeries S = short_series();
+    dx = cj.x - ci.x;
+    dy = cj.y - ci.y;
+    dz = cj.z - ci.z;
+    const double y2 = 0.25 * (dx * dx + dy * dy + dz * dz);
+    double fa = S.a[NT - 1], fb = S.b[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) {
+        fa = fa * y2 + S.a[k];
+        fb = fb * y2 + S.b[k];
+    }
+    al = c * half_r * fa;
+    be = al * fb;
 }
 
 // Flux and circulation weights of the edge i -> j rebuilt from its scalar

@@ -39,6 +39,7 @@ struct Halo {
     const int32_t *hids = nullptr;   // halo cell ids, chunk after chunk
     const uint16_t *lnbr = nullptr;  // [n][6]
     int nchunks = 0;                 // 0: no tables (small grid, or a halo above kHaloMax)
+    int short_terms = 5;             // terms of the LDS product's weight series (4 or 5)
 };
 struct DevMesh {
     int n = 0;
@@ -404,6 +405,7 @@ struct HostGeometry {
     // chunk tables of the LDS-staged product (see Halo); empty when unused
     std::vector<int32_t> hoff, hids;
     std::vector<uint16_t> lnbr;
+    int short_terms = 5;   // terms of the product's weight series (see Halo)
 };
 // Validates the mesh, picks the kernels' cell order (geo.perm: recursive
 // coordinate bisection into kChunk-cell patches) and derives every per-cell

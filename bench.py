@@ -153,7 +153,7 @@ def kernel_name(n_cells):
     """The IOM2 product the library launches on an n-cell grid (two lanes per
     cell): the LDS-staged kernel above 16384 cells, the gather kernel below."""
     if n_cells > 16384:
-        return "k_jv_lds<kEpiIom2> (LDS-staged Jacobian product + IOM2 dots)"
+        return "k_jv_lds<kEpiIom2, NT> (LDS-staged Jacobian product + IOM2 dots, NT-term weight series)"
     return "k_jv<kEpiIom2> (fused Jacobian product + IOM2 dots)"
 
 

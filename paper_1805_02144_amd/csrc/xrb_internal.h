@@ -23,8 +23,8 @@ constexpr int kKmax = kMmax + kPmax + 1;                  // augmented matrix or
 //   b = l t_e / (2 A_i)  = beta  (x_i x x_j),  beta  = 2 alpha / |x_i + x_j|
 // and the Laplacian weight is c = l / (d A_i).  alpha and c are stored per
 // edge slot; the kernels form beta from alpha and the two centres they load
-// (the LDS-staged product forms alpha and beta from c and the chord: see
-// edge_weights_short).
+// (the LDS-staged kernels form alpha and beta from c and the chord by a
+// short series: see edge_weights_short and edge_ab_short).
 //
 // Grids above 16384 cells (where the stencils default to two lanes per cell)
 // also carry the chunk tables of the LDS-staged product and Laplacian: the
@@ -49,7 +49,7 @@ struct DevMesh {
     const double *cen = nullptr;                   // [n][4]: unit centre x, y, z, 1 / cell area
     double nu = 0.0, g = 0.0;
     double two_omega = 0.0;                        // Coriolis f_i = two_omega * z_i
-    double half_r = 0.0;                           // sphere radius / 2 (edge_weights_short)
+    double half_r = 0.0;                           // sphere radius / 2 (the short weight series)
     int lanes = 8;                                 // lanes per cell in the stencils (1, 2, 4, 8)
     int lanes_batch = 8;                           // lanes of forward launches over many cells
     // launch shapes the autotuner may set (0 = the built-in rule); none of
@@ -414,7 +414,8 @@ int build_geometry(const xrb_mesh &mesh, const xrb_params &prm, HostGeometry &ge
                    std::string &err);
 // Chunk tables for grids whose products take the LDS-staged kernel; leaves
 // them empty when a chunk's halo exceeds kHaloMax or two neighbours lie
-// beyond the range of edge_weights_short's series.
+// beyond the range of the short weight series, and sets short_terms to four
+// when every half-chord is within the four-term range.
 void build_halo(HostGeometry &geo);
 
 }  // namespace xrb

@@ -77,7 +77,9 @@ def test_rhs_parity(X, level):
     assert blocks_rel(got, s.rhs(u), s.n) < TOL_STENCIL
 
 
-@pytest.mark.parametrize("level", [2, 4, 6])
+# level 7 takes the LDS-staged product with its four-term weight series
+# (levels 7 and 8), level 6 the five-term one, levels 2 and 4 the gather form
+@pytest.mark.parametrize("level", [2, 4, 6, 7])
 def test_jv_parity(X, level):
     mesh, ctx, s = setup(X, level)
     u = F.initial_state("c2_l6_24x3600", level=level)
